@@ -1,0 +1,198 @@
+"""Throughput of the BTA block Cholesky factorization + selected inversion
+(POBTAF + POBTASI) in FP64 on one MI355X.
+
+A step is one full pass of the hot path over one synthetic BTA matrix:
+bta_factor (A -> L) followed by bta_selinv (L -> Sigma at the BTA pattern),
+out of place, inputs resident in HBM.  The workload is n=128 diagonal blocks
+of b=2048 with an a=8 arrow tip, drawn by the seeded L L^T generator (scaled
+off-diagonal reading), the shape of a spatio-temporal GMRF precision matrix.
+
+Prints one JSON line: TFLOP/s over the algorithmic flop count, the roofline
+record of the dominant kernel (HIP events on the launch stream over the timed
+region) and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 matrix (MFMA) peak
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--b", type=int, default=2048)
+    ap.add_argument("--a", type=int, default=8)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-target-s", type=float, default=15.0, help="CPU oracle sample budget (seconds)")
+    return ap.parse_args()
+
+
+def cpu_baseline(b, a, seed, target_s):
+    """The oracle (numpy/scipy, host BLAS threads) on n_s blocks of the same
+    b and a, scaled to TFLOP/s with the same flop count."""
+    import numpy as np  # noqa: F401
+
+    import oracle
+    from paper_2503_17528_amd import synth
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        cores = max([int(i.get("num_threads", 0)) for i in threadpool_info() if i.get("user_api") == "blas"] or [0])
+    except Exception:
+        cores = 0
+    if cores <= 0:
+        cores = os.cpu_count() or 1
+
+    def run(ns):
+        wl = synth.workload(ns, b, a, "scaled" if b >= 2048 else "literal")
+        Q = synth.make_np(wl, seed)
+        t0 = time.perf_counter()
+        F = oracle.pobtaf(Q["D"], Q["B"], Q["R"], Q["T"])
+        oracle.pobtasi(F["LD"], F["LB"], F["LR"], F["LT"])
+        dt = time.perf_counter() - t0
+        return wl, dt
+
+    wl, dt = run(2)
+    rate = wl.flops()["total"] / dt
+    ns = int(max(2, min(64, round(target_s * rate / (wl.flops()["total"] / 2)))))
+    if ns > 2:
+        wl, dt = run(ns)
+    tf = wl.flops()["total"] / dt / 1e12
+    return {"value": round(tf, 4), "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"POBTAF+POBTASI oracle on n={ns} blocks of b={b}, a={a} (same block shape), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}): this build has no multi-GPU path; "
+              "the single-GPU throughput is the reported value.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2503_17528_amd import bta, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    L = bta.lib()
+    L.bta_internal_timing.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.bta_internal_timing_read.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+
+    n, b, a = args.n, args.b, args.a
+    reading = "scaled" if b >= 2048 else "literal"
+    wl = synth.workload(n, b, a, reading, name=f"bta_n{n}_b{b}_a{a}")
+    print(f"[bench] drawing {wl.name} ({wl.block_bytes() / 1e9:.2f} GB of blocks) on {dev}", file=sys.stderr, flush=True)
+    Q = synth.make_torch(wl, args.seed, dev)
+    D, B, R, T = Q["D"], Q["B"], Q["R"], Q["T"]
+    outL = tuple(torch.empty_like(x) for x in (D, B, R, T))
+    outX = tuple(torch.empty_like(x) for x in (D, B, R, T))
+    wf, nf = bta.workspace(bta.BTA_OP_FACTOR, n, b, a, dev)
+    ws, nsel = bta.workspace(bta.BTA_OP_SELINV, n, b, a, dev)
+    torch.cuda.synchronize()
+
+    def step():
+        LD, LB, LR, LT, info = bta.factor(D, B, R, T, out=outL, work=wf, check=False)
+        bta.selinv(LD, LB, LR, LT, out=outX, work=ws)
+        return info
+
+    for _ in range(args.warmup):
+        info = step()
+    torch.cuda.synchronize()
+    if args.warmup and int(info.item()) != 0:
+        raise RuntimeError(f"factorization failed: info={int(info.item())}")
+
+    # timed region: K steps between synchronizations; per-kernel HIP events on the launch stream
+    L.bta_internal_timing(1, 4096 * max(1, args.steps))
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t_wall0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        info = step()
+    ev1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    ms_total = ev0.elapsed_time(ev1)
+    kms = (ctypes.c_double * 4)()
+    kcnt = (ctypes.c_longlong * 4)()
+    rd = L.bta_internal_timing_read(kms, kcnt)
+    L.bta_internal_timing(0, 0)
+    if int(info.item()) != 0:
+        raise RuntimeError(f"factorization failed: info={int(info.item())}")
+
+    fl = wl.flops()
+    ms_step = ms_total / args.steps
+    tflops = fl["total"] / (ms_step * 1e-3) / 1e12
+
+    # dominant kernel: the one with the largest total time; algorithmic flops per launch
+    names = ["factor_kernel", "gemm_kernel", "trinv_diag_tiles_kernel", "other"]
+    T_ = (b + 63) // 64
+    trinv_fl = n * T_ * (64.0 ** 3) / 3.0
+    per_step_flops = {"factor_kernel": fl["factor"], "gemm_kernel": fl["selinv"] - trinv_fl,
+                      "trinv_diag_tiles_kernel": trinv_fl, "other": 0.0}
+    kern = {}
+    for k, nm in enumerate(names):
+        if kcnt[k] == 0:
+            continue
+        launches_per_step = kcnt[k] / args.steps
+        avg_ms = kms[k] / kcnt[k]
+        fl_launch = per_step_flops[nm] / launches_per_step
+        kern[nm] = {"launches_per_step": launches_per_step, "avg_ms": avg_ms, "total_ms_per_step": kms[k] / args.steps,
+                    "flops_per_launch": fl_launch, "tflops": fl_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0}
+    dom = max(kern, key=lambda k: kern[k]["total_ms_per_step"]) if kern else None
+    roofline = None
+    if dom:
+        ach = kern[dom]["tflops"]
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                    "flops_per_launch": kern[dom]["flops_per_launch"], "avg_launch_ms": round(kern[dom]["avg_ms"], 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(b, a, args.seed, args.cpu_target_s)
+
+    line = {
+        "metric": "POBTAF+POBTASI FP64 TFLOP/s and % FP64 MFMA peak on 1 MI355X at err<=1e-10",
+        "value": round(tflops, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": n, "b": b, "a": a, "reading": reading, "seed": args.seed,
+                   "flops_per_step": fl["total"], "flops_factor": fl["factor"], "flops_selinv": fl["selinv"]},
+        "pct_fp64_peak": round(100.0 * tflops / PEAK_FP64_TFLOPS, 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()} for k, v in kern.items()},
+        "timer_status": int(rd),
+        "wall_s_timed": round(t_wall, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

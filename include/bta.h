@@ -1,0 +1,126 @@
+/*
+ * bta.h -- C ABI of the MI355X (gfx950) block Cholesky factorization and
+ * selected inversion of symmetric positive-definite block-tridiagonal-
+ * arrowhead (BTA) matrices.
+ *
+ * Paper notation (Section 2.1, Table 2): a BTA matrix A has n diagonal blocks
+ * of size b, the lower blocks A_{i+1,i} (b x b), the arrowhead blocks A_{n,i}
+ * (a x b, the last block row) and the arrow tip A_{n,n} (a x a); N = n*b + a.
+ * a = 0 is the block-tridiagonal case.
+ *
+ * Block storage used by every entry point: row-major, contiguous, FP64,
+ *   D[n][b][b]   = A_{i,i}    (only the lower triangle is read)
+ *   B[n-1][b][b] = A_{i+1,i}
+ *   R[n][a][b]   = A_{n,i}
+ *   T[a][a]      = A_{n,n}    (only the lower triangle is read)
+ * The factor L and the selected inverse X = Sigma = A^{-1} (restricted to
+ * the nonzero block positions of A) use the same four arrays.
+ *
+ * Common conventions:
+ *  - Every pointer argument is a device pointer (HIP device memory of the
+ *    current device) owned by the caller; the library never allocates or
+ *    frees memory.  Scratch memory is the caller's `work` buffer of at least
+ *    bta_workspace_bytes(op, ...) bytes, 256-byte aligned.
+ *  - Every call only validates its arguments and enqueues work on `stream`
+ *    (0 = the null stream); it returns before the work runs.  The return
+ *    value reports argument errors (BTA_EINVAL) and launch errors (BTA_EHIP)
+ *    only; numerical outcomes are reported on the device (d_info).
+ *  - Outputs may alias the corresponding inputs exactly (in place: LD == D,
+ *    and so on); any other overlap between arrays is rejected with
+ *    BTA_EINVAL.  Arrays must be 8-byte aligned.
+ *  - n >= 1, b >= 1, a >= 0.  With a == 0, R/T (and LR/LT, XR/XT) may be
+ *    NULL; with n == 1, B (and LB, XB) may be NULL.
+ *  - Calls on different streams may run concurrently only if they use
+ *    different workspaces.
+ */
+#ifndef BTA_H
+#define BTA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define BTA_API __attribute__((visibility("default")))
+#else
+#define BTA_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* bta_stream_t; /* a hipStream_t */
+
+typedef enum {
+  BTA_OK = 0,
+  BTA_EINVAL = 1,   /* invalid argument (dims, NULL, overlap, alignment, workspace) */
+  BTA_ENOTPD = 2,   /* reserved: the matrix is not positive definite (see d_info) */
+  BTA_EHIP = 3,     /* a HIP runtime call failed; bta_last_error() has its text */
+  BTA_ENOTSUP = 4   /* no supported HIP device (not gfx950) */
+} bta_status;
+
+typedef enum {
+  BTA_OP_FACTOR = 0,
+  BTA_OP_SELINV = 1,
+  BTA_OP_SOLVE = 2,
+  BTA_OP_LOGDET = 3
+} bta_op;
+
+/* Bytes of caller workspace that `op` needs for these sizes (nrhs is used by
+ * BTA_OP_SOLVE only).  Returns 0 for invalid sizes. */
+BTA_API size_t bta_workspace_bytes(int op, int64_t n, int64_t b, int64_t a, int64_t nrhs);
+
+/*
+ * POBTAF (Algorithm 1): block Cholesky factorization A = L L^T.
+ *  in : D, B, R, T   blocks of A (lower triangles of D[i] and T are read)
+ *  out: LD, LB, LR, LT   blocks of L: L_{i,i} (lower, exact zeros above the
+ *       diagonal), L_{i+1,i}, L_{n,i}, L_{n,n} (lower, zeros above).
+ *  d_info: device int64; set to 0 on success, to the 1-based global row of
+ *       the first pivot that is not positive or not finite (LAPACK POTRF
+ *       convention; tip rows are n*b+1 .. n*b+a), or to -1 if an internal
+ *       progress watchdog fired.  On a nonzero d_info the outputs are
+ *       unspecified and must not be passed to bta_selinv or bta_solve.
+ */
+BTA_API int bta_factor(int64_t n, int64_t b, int64_t a,
+               const double* D, const double* B, const double* R, const double* T,
+               double* LD, double* LB, double* LR, double* LT,
+               void* work, size_t work_bytes, int64_t* d_info, bta_stream_t stream);
+
+/*
+ * POBTASI (Algorithm 2): selected inversion from the factor of bta_factor.
+ *  in : LD, LB, LR, LT   blocks of L
+ *  out: XD, XB, XR, XT   blocks of Sigma = A^{-1} at the BTA pattern:
+ *       Sigma_{i,i} and Sigma_{n,n} full symmetric, Sigma_{i+1,i},
+ *       Sigma_{n,i}.
+ */
+BTA_API int bta_selinv(int64_t n, int64_t b, int64_t a,
+               const double* LD, const double* LB, const double* LR, const double* LT,
+               double* XD, double* XB, double* XR, double* XT,
+               void* work, size_t work_bytes, bta_stream_t stream);
+
+/*
+ * Solve A x = rhs with the factor (block forward then back substitution; not
+ * in the paper).  rhs is [N][nrhs] row-major and is overwritten by x.
+ */
+BTA_API int bta_solve(int64_t n, int64_t b, int64_t a,
+              const double* LD, const double* LB, const double* LR, const double* LT,
+              double* rhs, int64_t nrhs, void* work, size_t work_bytes, bta_stream_t stream);
+
+/*
+ * log det A = 2 * sum log diag(L) over the diagonal blocks and the tip.
+ * d_out: device double receiving the result.
+ */
+BTA_API int bta_logdet(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT,
+               double* d_out, void* work, size_t work_bytes, bta_stream_t stream);
+
+/* Static text for a status code. */
+BTA_API const char* bta_status_string(int status);
+
+/* Text of the last BTA_EHIP / BTA_EINVAL error raised on this thread. */
+BTA_API const char* bta_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BTA_H */

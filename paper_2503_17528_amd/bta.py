@@ -1,0 +1,229 @@
+"""ctypes binding of the C ABI in ``include/bta.h`` (argument marshalling only).
+
+The raw entry points keep the C names (``bta_factor``, ``bta_selinv``,
+``bta_solve``, ``bta_logdet``, ``bta_workspace_bytes``, ``bta_status_string``)
+and take integers / raw device addresses.  ``factor``, ``selinv``, ``solve``
+and ``logdet`` wrap them for contiguous float64 torch tensors on the current
+HIP device and stream: they allocate outputs and workspace with torch and
+pass pointers; every step of the computation runs in the HIP library.
+
+The library must be built (``paper_2503_17528_amd.build``); there is no
+fallback: if ``libbta.so`` is missing or cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbta.so")
+
+BTA_OK, BTA_EINVAL, BTA_ENOTPD, BTA_EHIP, BTA_ENOTSUP = 0, 1, 2, 3, 4
+BTA_OP_FACTOR, BTA_OP_SELINV, BTA_OP_SOLVE, BTA_OP_LOGDET = 0, 1, 2, 3
+
+EXPORTED = ("bta_workspace_bytes", "bta_factor", "bta_selinv", "bta_solve", "bta_logdet",
+            "bta_status_string", "bta_last_error")
+
+_lib = None
+
+
+class BTAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class NotPositiveDefinite(BTAError):
+    def __init__(self, row: int):
+        super().__init__(BTA_ENOTPD, f"matrix is not positive definite: first failing pivot at global row {row} (1-based)")
+        self.row = row
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libbta.so`` (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run paper_2503_17528_amd.build.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, vp, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+    L.bta_workspace_bytes.argtypes = [ctypes.c_int, i64, i64, i64, i64]
+    L.bta_workspace_bytes.restype = sz
+    L.bta_factor.argtypes = [i64, i64, i64] + [vp] * 8 + [vp, sz, vp, vp]
+    L.bta_factor.restype = ctypes.c_int
+    L.bta_selinv.argtypes = [i64, i64, i64] + [vp] * 8 + [vp, sz, vp]
+    L.bta_selinv.restype = ctypes.c_int
+    L.bta_solve.argtypes = [i64, i64, i64] + [vp] * 4 + [vp, i64, vp, sz, vp]
+    L.bta_solve.restype = ctypes.c_int
+    L.bta_logdet.argtypes = [i64, i64, i64, vp, vp, vp, vp, sz, vp]
+    L.bta_logdet.restype = ctypes.c_int
+    L.bta_status_string.argtypes = [ctypes.c_int]
+    L.bta_status_string.restype = ctypes.c_char_p
+    L.bta_last_error.argtypes = []
+    L.bta_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+# ---------------------------------------------------------------- raw entry points (C names)
+
+
+def bta_workspace_bytes(op: int, n: int, b: int, a: int, nrhs: int = 0) -> int:
+    return int(lib().bta_workspace_bytes(op, n, b, a, nrhs))
+
+
+def bta_factor(n, b, a, D, B, R, T, LD, LB, LR, LT, work, work_bytes, d_info, stream) -> int:
+    return int(lib().bta_factor(n, b, a, D, B, R, T, LD, LB, LR, LT, work, work_bytes, d_info, stream))
+
+
+def bta_selinv(n, b, a, LD, LB, LR, LT, XD, XB, XR, XT, work, work_bytes, stream) -> int:
+    return int(lib().bta_selinv(n, b, a, LD, LB, LR, LT, XD, XB, XR, XT, work, work_bytes, stream))
+
+
+def bta_solve(n, b, a, LD, LB, LR, LT, rhs, nrhs, work, work_bytes, stream) -> int:
+    return int(lib().bta_solve(n, b, a, LD, LB, LR, LT, rhs, nrhs, work, work_bytes, stream))
+
+
+def bta_logdet(n, b, a, LD, LT, d_out, work, work_bytes, stream) -> int:
+    return int(lib().bta_logdet(n, b, a, LD, LT, d_out, work, work_bytes, stream))
+
+
+def bta_status_string(status: int) -> str:
+    return lib().bta_status_string(status).decode()
+
+
+def bta_last_error() -> str:
+    return lib().bta_last_error().decode()
+
+
+# ---------------------------------------------------------------- torch wrappers
+
+
+def _check(status: int, what: str):
+    if status != BTA_OK:
+        raise BTAError(status, f"{what}: {bta_status_string(status)}: {bta_last_error()}")
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None or t.numel() == 0:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> Optional[int]:
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream or None
+
+
+def _dims(D, R, T) -> Tuple[int, int, int]:
+    n, b = int(D.shape[0]), int(D.shape[1])
+    a = int(T.shape[0]) if T is not None else 0
+    return n, b, a
+
+
+def _validate(t, shape, name):
+    import torch
+
+    if t is None:
+        return
+    if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != tuple(shape) or not t.is_cuda:
+        raise ValueError(f"{name}: expected a contiguous float64 HIP tensor of shape {tuple(shape)}, "
+                         f"got {tuple(t.shape)} {t.dtype} contiguous={t.is_contiguous()} device={t.device}")
+
+
+def workspace(op: int, n: int, b: int, a: int, device, nrhs: int = 0):
+    import torch
+
+    nbytes = bta_workspace_bytes(op, n, b, a, nrhs)
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device), nbytes
+
+
+def factor(D, B, R, T, out=None, work=None, stream=None, check: bool = True):
+    """L = POBTAF(A).  Returns (LD, LB, LR, LT, info) with info a 0-dim int64
+    device tensor; with ``check`` the call synchronizes and raises
+    NotPositiveDefinite on a failed pivot.  ``out`` may be (D, B, R, T)
+    itself for an in-place factorization."""
+    import torch
+
+    n, b, a = _dims(D, R, T)
+    _validate(D, (n, b, b), "D"); _validate(B, (max(n - 1, 0), b, b), "B")
+    _validate(R, (n, a, b), "R"); _validate(T, (a, a), "T")
+    dev = D.device
+    if out is None:
+        out = (torch.empty_like(D), torch.empty_like(B), torch.empty_like(R), torch.empty_like(T))
+    LD, LB, LR, LT = out
+    info = torch.zeros((), dtype=torch.int64, device=dev)
+    if work is None:
+        work, nbytes = workspace(BTA_OP_FACTOR, n, b, a, dev)
+    else:
+        nbytes = work.numel()
+    st = bta_factor(n, b, a, _ptr(D), _ptr(B), _ptr(R), _ptr(T), _ptr(LD), _ptr(LB), _ptr(LR), _ptr(LT),
+                    work.data_ptr(), nbytes, info.data_ptr(), _stream(stream))
+    _check(st, "bta_factor")
+    if check:
+        v = int(info.item())
+        if v > 0:
+            raise NotPositiveDefinite(v)
+        if v < 0:
+            raise BTAError(BTA_EHIP, "bta_factor: progress watchdog fired")
+    return LD, LB, LR, LT, info
+
+
+def selinv(LD, LB, LR, LT, out=None, work=None, stream=None):
+    """X = POBTASI(L): blocks of A^{-1} at the BTA pattern.  ``out`` may be
+    (LD, LB, LR, LT) itself for an in-place selected inversion."""
+    import torch
+
+    n, b, a = _dims(LD, LR, LT)
+    _validate(LD, (n, b, b), "LD"); _validate(LB, (max(n - 1, 0), b, b), "LB")
+    _validate(LR, (n, a, b), "LR"); _validate(LT, (a, a), "LT")
+    if out is None:
+        out = (torch.empty_like(LD), torch.empty_like(LB), torch.empty_like(LR), torch.empty_like(LT))
+    XD, XB, XR, XT = out
+    if work is None:
+        work, nbytes = workspace(BTA_OP_SELINV, n, b, a, LD.device)
+    else:
+        nbytes = work.numel()
+    st = bta_selinv(n, b, a, _ptr(LD), _ptr(LB), _ptr(LR), _ptr(LT), _ptr(XD), _ptr(XB), _ptr(XR), _ptr(XT),
+                    work.data_ptr(), nbytes, _stream(stream))
+    _check(st, "bta_selinv")
+    return XD, XB, XR, XT
+
+
+def solve(LD, LB, LR, LT, rhs, inplace: bool = False, work=None, stream=None):
+    """x = A^{-1} rhs from the factor; rhs of shape (N,) or (N, nrhs)."""
+    n, b, a = _dims(LD, LR, LT)
+    N = n * b + a
+    x = rhs if inplace else rhs.clone()
+    vec = x.dim() == 1
+    x2 = x.view(N, 1) if vec else x
+    nrhs = int(x2.shape[1])
+    _validate(x2, (N, nrhs), "rhs")
+    if work is None:
+        work, nbytes = workspace(BTA_OP_SOLVE, n, b, a, LD.device, nrhs)
+    else:
+        nbytes = work.numel()
+    st = bta_solve(n, b, a, _ptr(LD), _ptr(LB), _ptr(LR), _ptr(LT), x2.data_ptr(), nrhs, work.data_ptr(), nbytes,
+                   _stream(stream))
+    _check(st, "bta_solve")
+    return x
+
+
+def logdet(LD, LT, work=None, stream=None):
+    """log det A from the factor, as a 0-dim float64 device tensor."""
+    import torch
+
+    n, b = int(LD.shape[0]), int(LD.shape[1])
+    a = int(LT.shape[0]) if LT is not None else 0
+    out = torch.empty((), dtype=torch.float64, device=LD.device)
+    if work is None:
+        work, nbytes = workspace(BTA_OP_LOGDET, n, b, a, LD.device)
+    else:
+        nbytes = work.numel()
+    st = bta_logdet(n, b, a, _ptr(LD), _ptr(LT), out.data_ptr(), work.data_ptr(), nbytes, _stream(stream))
+    _check(st, "bta_logdet")
+    return out

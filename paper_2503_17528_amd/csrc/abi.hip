@@ -1,0 +1,191 @@
+// C ABI entry points (include/bta.h): argument validation, workspace sizing,
+// dispatch to the launchers.  Validation happens before any HIP call, so the
+// argument checks work on a host without a GPU.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/bta.h"
+#include "bta_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(BTA_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool dims_ok(int64_t n, int64_t b, int64_t a) {
+  if (n < 1 || b < 1 || a < 0) return false;
+  // 32-bit tile bookkeeping inside the kernels
+  if (b > (1 << 20) || a > (1 << 20) || n > (1LL << 30)) return false;
+  return true;
+}
+
+struct Arr {
+  const void* p;
+  size_t bytes;
+  const char* name;
+};
+
+// Every array present must be non-null and 8-byte aligned; arrays may
+// coincide exactly only within an (input, output) pair; any other overlap is
+// an error.
+int check_arrays(const Arr* arr, int count, const int* pair_of) {
+  for (int i = 0; i < count; ++i) {
+    if (arr[i].bytes == 0) continue;
+    if (!arr[i].p) return fail(BTA_EINVAL, "%s is NULL", arr[i].name);
+    if (reinterpret_cast<uintptr_t>(arr[i].p) & 7) return fail(BTA_EINVAL, "%s is not 8-byte aligned", arr[i].name);
+  }
+  for (int i = 0; i < count; ++i) {
+    for (int j = i + 1; j < count; ++j) {
+      if (arr[i].bytes == 0 || arr[j].bytes == 0) continue;
+      const uintptr_t a0 = reinterpret_cast<uintptr_t>(arr[i].p), a1 = a0 + arr[i].bytes;
+      const uintptr_t b0 = reinterpret_cast<uintptr_t>(arr[j].p), b1 = b0 + arr[j].bytes;
+      const bool overlap = a0 < b1 && b0 < a1;
+      if (!overlap) continue;
+      const bool exact_pair = (pair_of[i] == j || pair_of[j] == i) && a0 == b0 && arr[i].bytes == arr[j].bytes;
+      if (!exact_pair) return fail(BTA_EINVAL, "%s overlaps %s", arr[i].name, arr[j].name);
+    }
+  }
+  return BTA_OK;
+}
+
+int device_ok() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(BTA_ENOTSUP, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+  return BTA_OK;
+}
+
+size_t blk_bytes(int64_t count, int64_t r, int64_t c) { return (size_t)std::max<int64_t>(count, 0) * r * c * 8; }
+
+int check_work(void* work, size_t work_bytes, size_t need) {
+  if (need == 0) return BTA_OK;
+  if (!work) return fail(BTA_EINVAL, "workspace is NULL (%zu bytes needed)", need);
+  if (reinterpret_cast<uintptr_t>(work) & 255) return fail(BTA_EINVAL, "workspace must be 256-byte aligned");
+  if (work_bytes < need) return fail(BTA_EINVAL, "workspace too small: %zu < %zu bytes", work_bytes, need);
+  return BTA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t bta_workspace_bytes(int op, int64_t n, int64_t b, int64_t a, int64_t nrhs) {
+  if (!dims_ok(n, b, a)) return 0;
+  switch (op) {
+    case BTA_OP_FACTOR: return bta::factor_plan(n, b, a).bytes;
+    case BTA_OP_SELINV: return bta::selinv_plan(n, b, a).bytes;
+    case BTA_OP_SOLVE: return nrhs >= 1 ? bta::solve_work_bytes(n, b, a, nrhs) : 0;
+    case BTA_OP_LOGDET: return bta::logdet_work_bytes(n, b, a);
+    default: return 0;
+  }
+}
+
+int bta_factor(int64_t n, int64_t b, int64_t a, const double* D, const double* B, const double* R, const double* T,
+               double* LD, double* LB, double* LR, double* LT, void* work, size_t work_bytes, int64_t* d_info,
+               bta_stream_t stream) {
+  if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
+  const Arr arr[9] = {
+      {D, blk_bytes(n, b, b), "D"},        {B, blk_bytes(n - 1, b, b), "B"}, {R, blk_bytes(n, a, b), "R"},
+      {T, blk_bytes(1, a, a), "T"},        {LD, blk_bytes(n, b, b), "LD"},   {LB, blk_bytes(n - 1, b, b), "LB"},
+      {LR, blk_bytes(n, a, b), "LR"},      {LT, blk_bytes(1, a, a), "LT"},   {d_info, 8, "d_info"}};
+  const int pair[9] = {4, 5, 6, 7, 0, 1, 2, 3, -1};
+  int st = check_arrays(arr, 9, pair);
+  if (st) return st;
+  const bta::FactorPlan fp = bta::factor_plan(n, b, a);
+  st = check_work(work, work_bytes, fp.bytes);
+  if (st) return st;
+  st = device_ok();
+  if (st) return st;
+  hipError_t e = bta::factor_launch(fp, n, b, a, D, B, R, T, LD, LB, LR, LT, work, d_info,
+                                    reinterpret_cast<hipStream_t>(stream), bta::device_cu_count());
+  return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_factor launch");
+}
+
+int bta_selinv(int64_t n, int64_t b, int64_t a, const double* LD, const double* LB, const double* LR, const double* LT,
+               double* XD, double* XB, double* XR, double* XT, void* work, size_t work_bytes, bta_stream_t stream) {
+  if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
+  const Arr arr[8] = {
+      {LD, blk_bytes(n, b, b), "LD"}, {LB, blk_bytes(n - 1, b, b), "LB"}, {LR, blk_bytes(n, a, b), "LR"},
+      {LT, blk_bytes(1, a, a), "LT"}, {XD, blk_bytes(n, b, b), "XD"},     {XB, blk_bytes(n - 1, b, b), "XB"},
+      {XR, blk_bytes(n, a, b), "XR"}, {XT, blk_bytes(1, a, a), "XT"}};
+  const int pair[8] = {4, 5, 6, 7, 0, 1, 2, 3};
+  int st = check_arrays(arr, 8, pair);
+  if (st) return st;
+  const bta::SelinvPlan sp = bta::selinv_plan(n, b, a);
+  st = check_work(work, work_bytes, sp.bytes);
+  if (st) return st;
+  st = device_ok();
+  if (st) return st;
+  hipError_t e = bta::selinv_launch(sp, n, b, a, LD, LB, LR, LT, XD, XB, XR, XT, work, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_selinv launch");
+}
+
+int bta_solve(int64_t n, int64_t b, int64_t a, const double* LD, const double* LB, const double* LR, const double* LT,
+              double* rhs, int64_t nrhs, void* work, size_t work_bytes, bta_stream_t stream) {
+  if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
+  if (nrhs < 1 || nrhs > (1 << 20)) return fail(BTA_EINVAL, "invalid nrhs=%lld", (long long)nrhs);
+  const int64_t N = n * b + a;
+  const Arr arr[5] = {{LD, blk_bytes(n, b, b), "LD"}, {LB, blk_bytes(n - 1, b, b), "LB"}, {LR, blk_bytes(n, a, b), "LR"},
+                      {LT, blk_bytes(1, a, a), "LT"}, {rhs, blk_bytes(1, N, nrhs), "rhs"}};
+  const int pair[5] = {-1, -1, -1, -1, -1};
+  int st = check_arrays(arr, 5, pair);
+  if (st) return st;
+  st = check_work(work, work_bytes, bta::solve_work_bytes(n, b, a, nrhs));
+  if (st) return st;
+  st = device_ok();
+  if (st) return st;
+  hipError_t e = bta::solve_launch(n, b, a, LD, LB, LR, LT, rhs, nrhs, work, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_solve launch");
+}
+
+int bta_logdet(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT, double* d_out, void* work,
+               size_t work_bytes, bta_stream_t stream) {
+  if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
+  const Arr arr[3] = {{LD, blk_bytes(n, b, b), "LD"}, {LT, blk_bytes(1, a, a), "LT"}, {d_out, 8, "d_out"}};
+  const int pair[3] = {-1, -1, -1};
+  int st = check_arrays(arr, 3, pair);
+  if (st) return st;
+  st = check_work(work, work_bytes, bta::logdet_work_bytes(n, b, a));
+  if (st) return st;
+  st = device_ok();
+  if (st) return st;
+  hipError_t e = bta::logdet_launch(n, b, a, LD, LT, d_out, work, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_logdet launch");
+}
+
+const char* bta_status_string(int status) {
+  switch (status) {
+    case BTA_OK: return "BTA_OK";
+    case BTA_EINVAL: return "BTA_EINVAL: invalid argument";
+    case BTA_ENOTPD: return "BTA_ENOTPD: matrix is not positive definite";
+    case BTA_EHIP: return "BTA_EHIP: HIP runtime error";
+    case BTA_ENOTSUP: return "BTA_ENOTSUP: unsupported device";
+    default: return "unknown bta status";
+  }
+}
+
+const char* bta_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,341 @@
+// Device building blocks shared by the gfx950 kernels: FP64 MFMA tile engine
+// over 64 x 64 output tiles staged through LDS, the in-LDS Cholesky of a
+// diagonal tile fused with the inverse of its factor, and the cross-workgroup
+// flag protocol of the persistent tile-task kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bta {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+constexpr int TS = 64;        // output tile edge
+constexpr int NT = 256;       // threads per workgroup (4 waves of 64)
+constexpr int LDS_LD = 66;    // LDS row stride in doubles: rows shift by 4 banks, keeps 16-byte alignment
+
+// ---------------------------------------------------------------------------
+// v_mfma_f64_16x16x4_f64.  Operand layout (lane l): A supplies (row l%16, k l/16),
+// B supplies (k l/16, col l%16).  The 4 accumulator values of lane l hold
+// rows 4*j + l/16 (j = 0..3) of column l%16.
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ int acc_row(int lane, int j) { return 4 * j + (lane >> 4); }
+__device__ __forceinline__ int acc_col(int lane) { return lane & 15; }
+
+// A 64 x 64 accumulator tile spread over the 4 waves of a workgroup: wave w
+// owns rows 32*(w>>1) .. +32 and cols 32*(w&1) .. +32 as 2 x 2 MFMA blocks.
+struct Acc {
+  d4 v[2][2];
+};
+
+__device__ __forceinline__ void acc_zero(Acc& c) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) c.v[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+// (row, col) inside the 64 x 64 tile of accumulator element (bi, bj, j) of this thread
+__device__ __forceinline__ int tile_row(int tid, int bi, int j) {
+  const int w = tid >> 6, lane = tid & 63;
+  return 32 * (w >> 1) + 16 * bi + acc_row(lane, j);
+}
+__device__ __forceinline__ int tile_col(int tid, int bj) {
+  const int w = tid >> 6, lane = tid & 63;
+  return 32 * (w & 1) + 16 * bj + acc_col(lane);
+}
+
+// ---------------------------------------------------------------------------
+// Operand tile: element (m, k) of a rows x cols window, m < 64, k < 64;
+// trans == false: p[m*ld + k]  (k contiguous);  trans == true: p[k*ld + m].
+// Elements outside the window read as zero.
+struct OpTile {
+  const double* p;
+  int64_t ld;
+  int rows;
+  int cols;
+  bool trans;
+};
+
+// Per-thread register staging of one 64 x 64 operand tile (16 doubles).
+struct Stage {
+  double v[16];
+};
+
+__device__ __forceinline__ void stage_load(Stage& s, const OpTile& t, int tid) {
+  if (!t.trans) {
+    const int m = tid >> 2, k0 = (tid & 3) * 16;
+    const double* src = t.p + (int64_t)m * t.ld + k0;
+    const bool row_ok = m < t.rows;
+    const bool full = row_ok && (k0 + 16 <= t.cols) && ((t.ld & 1) == 0) && ((((uintptr_t)src) & 15) == 0);
+    if (full) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        d2v x = *reinterpret_cast<const d2v*>(src + 2 * j);
+        s.v[2 * j] = x[0];
+        s.v[2 * j + 1] = x[1];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) s.v[j] = (row_ok && k0 + j < t.cols) ? src[j] : 0.0;
+    }
+  } else {
+    const int k = tid >> 2, m0 = (tid & 3) * 16;
+    const double* src = t.p + (int64_t)k * t.ld + m0;
+    const bool k_ok = k < t.cols;
+    const bool full = k_ok && (m0 + 16 <= t.rows) && ((t.ld & 1) == 0) && ((((uintptr_t)src) & 15) == 0);
+    if (full) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        d2v x = *reinterpret_cast<const d2v*>(src + 2 * j);
+        s.v[2 * j] = x[0];
+        s.v[2 * j + 1] = x[1];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) s.v[j] = (k_ok && m0 + j < t.rows) ? src[j] : 0.0;
+    }
+  }
+}
+
+__device__ __forceinline__ void stage_zero(Stage& s) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) s.v[j] = 0.0;
+}
+
+// LDS image of an operand: row m (output row or column index), k contiguous.
+__device__ __forceinline__ void stage_store(const Stage& s, double* lds, bool trans, int tid) {
+  if (!trans) {
+    const int m = tid >> 2, k0 = (tid & 3) * 16;
+    double* dst = lds + m * LDS_LD + k0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) *reinterpret_cast<d2v*>(dst + 2 * j) = d2v{s.v[2 * j], s.v[2 * j + 1]};
+  } else {
+    const int k = tid >> 2, m0 = (tid & 3) * 16;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) lds[(m0 + j) * LDS_LD + k] = s.v[j];
+  }
+}
+
+// acc += A_lds * B_lds^T over one 64-wide k tile: A_lds rows are output rows,
+// B_lds rows are output columns, both k-contiguous with stride LDS_LD.
+// The 16 k values of each MFMA group are permuted so that every lane reads 4
+// consecutive k (two 16-byte LDS reads) per operand per group.
+__device__ __forceinline__ void mma_tile(Acc& c, const double* As, const double* Bs, int tid) {
+  const int w = tid >> 6, lane = tid & 63;
+  const int r0 = 32 * (w >> 1) + (lane & 15);
+  const int c0 = 32 * (w & 1) + (lane & 15);
+  const int kl = (lane >> 4) * 4;
+#pragma unroll
+  for (int kg = 0; kg < 4; ++kg) {
+    d4 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double* pa = As + (r0 + 16 * i) * LDS_LD + kg * 16 + kl;
+      const double* pb = Bs + (c0 + 16 * i) * LDS_LD + kg * 16 + kl;
+      d2v a01 = *reinterpret_cast<const d2v*>(pa);
+      d2v a23 = *reinterpret_cast<const d2v*>(pa + 2);
+      d2v b01 = *reinterpret_cast<const d2v*>(pb);
+      d2v b23 = *reinterpret_cast<const d2v*>(pb + 2);
+      a[i] = d4{a01[0], a01[1], a23[0], a23[1]};
+      b[i] = d4{b01[0], b01[1], b23[0], b23[1]};
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) c.v[i][j] = mfma16(a[i][s], b[j][s], c.v[i][j]);
+  }
+}
+
+// Write the accumulator tile into LDS as a row-major 64 x 64 image (stride LDS_LD).
+__device__ __forceinline__ void acc_to_lds(const Acc& c, double* lds, int tid) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) lds[tile_row(tid, bi, j) * LDS_LD + tile_col(tid, bj)] = c.v[bi][bj][j];
+}
+
+// Load a rows x cols window of a row-major global tile into the accumulator
+// layout (zeros outside the window), scaled by `scale`.
+__device__ __forceinline__ void acc_load(Acc& c, const double* p, int64_t ld, int rows, int cols, double scale, int tid) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = tile_row(tid, bi, j), q = tile_col(tid, bj);
+        c.v[bi][bj][j] = (r < rows && q < cols) ? scale * p[(int64_t)r * ld + q] : 0.0;
+      }
+}
+
+// Store the accumulator (times `scale`) into a rows x cols window of a
+// row-major global tile.  mode 0: all; mode 1: lower triangle only (r >= c);
+// mode 2: lower triangle with exact zeros written above the diagonal.
+__device__ __forceinline__ void acc_store(const Acc& c, double* p, int64_t ld, int rows, int cols, double scale, int mode, int tid) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = tile_row(tid, bi, j), q = tile_col(tid, bj);
+        if (r < rows && q < cols) {
+          double v = scale * c.v[bi][bj][j];
+          if (mode == 1 && q > r) continue;
+          if (mode == 2 && q > r) v = 0.0;
+          p[(int64_t)r * ld + q] = v;
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// In-LDS Cholesky of a 64 x 64 SPD tile fused with the inverse of its factor.
+// Input: the tile in LDS `S` (row-major, stride LDS_LD; lower triangle read).
+// Output: L (lower, zeros above) and W = L^{-1} (lower, zeros above) back in
+// `S` and `Wl` (both row-major, stride LDS_LD).  Returns (uniformly) the
+// 1-based index of the first pivot that is not positive and finite, else 0.
+//
+// Thread (r = tid%64, q = tid/64) keeps row r, columns q, q+4, ..., q+60 of
+// both S and W in registers.  Column k is finished by the wave that owns it
+// (q == k%4): it takes the pivot from lane k, scales its column and publishes
+// it through LDS; one barrier per column; every thread then applies the
+// rank-1 update to its part of the trailing matrix.  The rows of W follow by
+// forward substitution on the identity, which only needs row k of W inside
+// the same wave (cross-lane reads, no barrier).
+__device__ __forceinline__ double rd_lane(double x, int lane) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ int chol_inv_tile(double* S, double* Wl, double* colbuf /* [2][64] */, double* pivbuf /* [2] */,
+                             int* fail_sh, int tid) {
+  const int r = tid & 63, q = tid >> 6;
+  double s[16], w[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    s[m] = S[r * LDS_LD + q + 4 * m];
+    w[m] = (r == q + 4 * m) ? 1.0 : 0.0;
+  }
+  if (tid == 0) *fail_sh = 0x7fffffff;  // "no failure"; lowered by atomicMin below
+  int fail = 0;
+  for (int k = 0; k < 64; ++k) {
+    const int mk = k >> 2;
+    double* col = colbuf + (k & 1) * 64;
+    if (q == (k & 3)) {
+      double smk = 0.0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) smk = (m == mk) ? s[m] : smk;
+      const double d = rd_lane(smk, k);
+      const bool ok = (d > 0.0) && (d <= 1.7976931348623157e308);
+      if (!ok && fail == 0) fail = k + 1;
+      const double sq = sqrt(d);
+      const double rinv = 1.0 / sq;
+      const double lv = (r > k) ? smk * rinv : ((r == k) ? sq : 0.0);
+#pragma unroll
+      for (int m = 0; m < 16; ++m) s[m] = (m == mk) ? lv : s[m];
+      col[r] = lv;
+      if (r == 0) pivbuf[k & 1] = rinv;
+    }
+    __syncthreads();
+    const double lr = col[r];
+    const double rinv = pivbuf[k & 1];
+    // trailing update of S (columns c > k held by this thread)
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      if (q + 4 * m > k) s[m] -= lr * col[q + 4 * m];
+    }
+    // W: finish row k (scale by 1/L_kk), then eliminate it from the rows below
+    if (r == k) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) w[m] *= rinv;
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      if (4 * m <= k) {  // columns q + 4m <= k can be nonzero in row k
+        const double wk = rd_lane(w[m], k);
+        if (r > k) w[m] -= lr * wk;
+      }
+    }
+  }
+  if (fail != 0 && (tid & 63) == 0) atomicMin(fail_sh, fail);
+  // write back L and W (lower, zeros above)
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int c = q + 4 * m;
+    S[r * LDS_LD + c] = (c <= r) ? s[m] : 0.0;
+    Wl[r * LDS_LD + c] = (c <= r) ? w[m] : 0.0;
+  }
+  __syncthreads();
+  const int f = *fail_sh;
+  return f == 0x7fffffff ? 0 : f;
+}
+
+// In-LDS inverse of a lower-triangular 64 x 64 tile by forward substitution
+// on the identity: thread (r, q) keeps row r, columns q + 4m of the inverse;
+// row k is finished (scaled by 1/L_kk) by lane k of every wave and then
+// eliminated from the rows below with cross-lane reads only.
+__device__ __forceinline__ void trinv_tile(const double* S, double* w, int tid) {
+  const int r = tid & 63, q = tid >> 6;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) w[m] = (r == q + 4 * m) ? 1.0 : 0.0;
+  for (int k = 0; k < 64; ++k) {
+    const double lr = S[r * LDS_LD + k];
+    const double inv = 1.0 / S[k * LDS_LD + k];
+    if (r == k) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) w[m] *= inv;
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      if (4 * m <= k) {
+        const double wk = rd_lane(w[m], k);
+        if (r > k) w[m] -= lr * wk;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cross-workgroup completion flags (one int per tile, 0 = pending).
+// Producer: every wave fences its own global writes at agent scope, then one
+// thread publishes the flag with release semantics.  Consumer: one thread
+// polls with relaxed loads, then an acquire fence makes the producer's writes
+// visible to the whole workgroup (L1 is per CU, L2 per XCD).
+__device__ __forceinline__ void publish_flag(int* flag, int tid) {
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool flag_set(const int* flag) {
+  return __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// Spin (thread 0 only) until *flag != 0.  Gives up and raises *abort after
+// about `limit` polls, or returns at once if *abort is already raised, so
+// that every wave always reaches the end of the kernel.
+__device__ __forceinline__ bool spin_wait(const int* flag, int* abort, long long limit) {
+  long long polls = 0;
+  while (!flag_set(flag)) {
+    if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    __builtin_amdgcn_s_sleep(4);
+    if (++polls > limit) {
+      __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+  }
+  return true;
+}
+
+__device__ __forceinline__ void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+}  // namespace bta

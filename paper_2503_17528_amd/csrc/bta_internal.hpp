@@ -1,0 +1,119 @@
+// Host-side interfaces between the C ABI and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace bta {
+
+// ---------------------------------------------------------------- factor
+struct FactorPlan {
+  int T, TA;
+  long long nflags, step_full, step_last, ntasks;
+  size_t off_ctl, off_flags, off_Wd, off_Wt, off_P, bytes;
+};
+FactorPlan factor_plan(int64_t n, int64_t b, int64_t a);
+hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
+                         const double* D, const double* B, const double* R, const double* T,
+                         double* LD, double* LB, double* LR, double* LT,
+                         void* work, int64_t* info, hipStream_t stream, int num_cus);
+
+// ---------------------------------------------------------------- grouped GEMM
+// One product term: sum_k A(m,k) B(c,k) over a k range.  A(m,k) is
+// A[m*lda + k] (at == 0) or A[k*lda + m] (at == 1); B likewise with bt.
+// Batched operands advance by s*0 per first batch index and s*1 per second.
+enum : int { TRI_NONE = 0, TRI_K_GE_COL = 1, TRI_K_GE_ROW = 2, TRI_K_LE_ROW = 3, TRI_K_LE_COL = 4 };
+enum : int { ST_FULL = 0, ST_LOWER = 1, ST_LOWER_MIRROR = 3 };
+
+struct GSeg {
+  const double* A;
+  const double* B;
+  int64_t lda, ldb;
+  int64_t sA0, sA1, sB0, sB1;
+  int K;
+  int at, bt, tri;
+};
+
+struct GProb {
+  GSeg seg[2];
+  int nseg;
+  const double* Cin;  // may be null when beta == 0
+  double* Cout;
+  int64_t ldc, sC0, sC1;
+  int M, N;
+  int nb0, nb1;        // batch = nb0 x nb1
+  double alpha, beta;  // Cout = beta*Cin + alpha*sum
+  int store;           // ST_*
+  int lower_tiles;     // only tiles with tile_row >= tile_col
+  // filled by gemm_launch
+  int ntm, ntn, tiles_per_batch;
+  long long tile_begin;
+};
+
+constexpr int GEMM_MAX_PROBS = 4;
+struct GemmArgs {
+  GProb p[GEMM_MAX_PROBS];
+  int nprob;
+  long long ntiles;
+};
+
+// Launch the problems (at most GEMM_MAX_PROBS) as one grid; empty problems are skipped.
+hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream);
+
+// ---------------------------------------------------------------- selinv
+struct SelinvPlan {
+  int64_t chunk;  // blocks per preprocessing chunk
+  size_t off_W, off_T1, off_P, off_Xp, off_WT, bytes;
+};
+SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a);
+hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
+                         const double* LD, const double* LB, const double* LR, const double* LT,
+                         double* XD, double* XB, double* XR, double* XT,
+                         void* work, hipStream_t stream);
+
+// ---------------------------------------------------------------- solve / logdet
+size_t solve_work_bytes(int64_t n, int64_t b, int64_t a, int64_t nrhs);
+hipError_t solve_launch(int64_t n, int64_t b, int64_t a, const double* LD, const double* LB,
+                        const double* LR, const double* LT, double* rhs, int64_t nrhs,
+                        void* work, hipStream_t stream);
+size_t logdet_work_bytes(int64_t n, int64_t b, int64_t a);
+hipError_t logdet_launch(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT,
+                         double* out, void* work, hipStream_t stream);
+
+// ---------------------------------------------------------------- shared small kernels
+// Triangular inverse of 64 x 64 diagonal tiles: for batch index (blk, t),
+// W tile t of block blk = inverse of lower-triangular L tile t (ragged last
+// tile padded with the identity); writes the full 64 x 64 tile of W with
+// zeros above the diagonal into W (row-major, ld = m, block stride sW).
+hipError_t trinv_diag_tiles_launch(const double* L, int64_t ldL, int64_t sL, double* W, int64_t ldW, int64_t sW,
+                                   int m, int nblk, hipStream_t stream);
+// Fill `count` doubles with zero.
+hipError_t fill_zero_launch(double* p, size_t count, hipStream_t stream);
+// Copy a rows x cols row-major matrix (batched by nb with strides).
+hipError_t copy2d_launch(const double* src, int64_t lds, int64_t ss, double* dst, int64_t ldd, int64_t sd,
+                         int rows, int cols, int nb, hipStream_t stream);
+
+int device_cu_count();
+
+// Host dry run: when a recorder is installed on this thread, the launchers
+// above only record what they would touch (no HIP calls).  Used to check
+// every operand window against its array bounds on the CPU.
+struct Window {
+  const void* base;
+  int64_t rows, cols, ld;  // row-major window: element (r, c) at base + r*ld + c (doubles)
+  bool write;
+};
+struct DryRecorder {
+  std::vector<Window> windows;
+};
+extern thread_local DryRecorder* g_dry;
+
+// Optional per-kernel timing with HIP events recorded on the launch stream
+// around each launch of the main kernels (off unless enabled).
+enum : int { KT_FACTOR = 0, KT_GEMM = 1, KT_TRINV = 2, KT_OTHER = 3, KT_COUNT = 4 };
+bool timing_on();
+void timing_mark(int kind, bool start, hipStream_t stream);
+
+}  // namespace bta

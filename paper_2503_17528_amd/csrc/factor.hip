@@ -1,0 +1,569 @@
+// POBTAF (Algorithm 1) on gfx950 as one persistent kernel over a tile DAG.
+//
+// The BTA factorization is run as a left-looking tile Cholesky of the band:
+// every 64 x 64 tile of L is one task, executed by one workgroup, that
+// accumulates all updates it needs (in the order of the k tiles) and then
+// finishes the tile:
+//
+//   DIAG (i,c)   L_ii(c,c)   = chol( A_ii(c,c) - sum L(c,k) L(c,k)^T ), W = its inverse
+//   OFFD (i,r,c) L_ii(r,c)   = ( A_ii(r,c) - sum L(r,k) L(c,k)^T ) W(c,c)^T      (r > c)
+//   SUB  (i,r,c) L_{i+1,i}   = ( A_{i+1,i}(r,c) - sum ... ) W(c,c)^T
+//   ARW  (i,r,c) L_{n,i}     = ( A_{n,i}(r,c)  - sum ... ) W(c,c)^T
+//   TUPD (i,r,c) P_i(r,c)    = sum_k L_{n,i}(r,k) L_{n,i}(c,k)^T   (tip update of one step)
+//   TIPD/TIPO    L_nn tiles from A_nn - sum_i P_i (in step order) - sum ...
+//
+// The sums over the previous block column (A_{i,i} -= L_{i,i-1} L_{i,i-1}^T and
+// A_{n,i} -= L_{n,i-1} L_{i,i-1}^T, the Schur updates of Algorithm 1) are folded
+// into the tasks of block column i, so a tile of block i+1 starts accumulating
+// as soon as the tiles of block i it needs are final: there is no barrier
+// between the steps of the sweep.  The triangular solves of Algorithm 1 are
+// products with the inverse W of the 64 x 64 diagonal factor tile, so all the
+// arithmetic outside the diagonal tiles runs on FP64 MFMA.
+//
+// Workgroups take task tickets from an atomic counter in a fixed topological
+// order (column by column across the whole band), so a task only ever waits
+// for tasks with smaller tickets, which are owned by running workgroups: the
+// schedule cannot deadlock whatever the number of resident workgroups.  Every
+// wait is bounded; a stuck wait raises an abort flag that releases all waits.
+#include <vector>
+
+#include "bta_device.hpp"
+#include "bta_internal.hpp"
+
+namespace bta {
+
+enum : int { T_DIAG = 0, T_OFFD = 1, T_SUB = 2, T_ARW = 3, T_TUPD = 4, T_TIPD = 5, T_TIPO = 6 };
+
+struct FactorParams {
+  int n, b, a;
+  int T;   // tiles per block edge: ceil(b/64)
+  int TA;  // tiles per tip edge: ceil(a/64)
+  const double* D; const double* B; const double* R; const double* Tt;
+  double* LD; double* LB; double* LR; double* LT;
+  double* Wd;      // [n][T] 64x64 inverses of the diagonal factor tiles
+  double* Wt;      // [TA] inverses of the tip diagonal factor tiles
+  double* P;       // [n][TA][TA] 64x64 per-step tip updates
+  int* flags;      // completion flags
+  int* ctl;        // [0..1] 64-bit ticket counter, [2] abort flag
+  int64_t* info;   // caller's info
+  long long ntasks;
+  long long step_full, step_last;  // tasks per step (with / without SUB)
+  long long spin_limit;
+};
+
+struct Task {
+  int type, i, r, c;
+};
+
+__host__ __device__ inline int64_t fl_D(const FactorParams& p, int i, int r, int c) {
+  return (int64_t)i * (2LL * p.T * p.T + (int64_t)p.TA * p.T + (int64_t)p.TA * p.TA) + (int64_t)r * p.T + c;
+}
+__host__ __device__ inline int64_t fl_B(const FactorParams& p, int i, int r, int c) {
+  return fl_D(p, i, 0, 0) + (int64_t)p.T * p.T + (int64_t)r * p.T + c;
+}
+__host__ __device__ inline int64_t fl_R(const FactorParams& p, int i, int r, int c) {
+  return fl_D(p, i, 0, 0) + 2LL * p.T * p.T + (int64_t)r * p.T + c;
+}
+__host__ __device__ inline int64_t fl_U(const FactorParams& p, int i, int r, int c) {
+  return fl_D(p, i, 0, 0) + 2LL * p.T * p.T + (int64_t)p.TA * p.T + (int64_t)r * p.TA + c;
+}
+__host__ __device__ inline int64_t fl_tip(const FactorParams& p, int r, int c) {
+  return fl_D(p, p.n, 0, 0) + (int64_t)r * p.TA + c;
+}
+
+__host__ __device__ Task decode(const FactorParams& p, long long t) {
+  Task k{-1, 0, 0, 0};
+  const int T = p.T, TA = p.TA;
+  long long rem;
+  bool has_sub;
+  const long long full_total = (long long)(p.n - 1) * p.step_full;
+  if (t < full_total) {
+    k.i = (int)(t / p.step_full);
+    rem = t - (long long)k.i * p.step_full;
+    has_sub = true;
+  } else if (t - full_total < p.step_last) {
+    k.i = p.n - 1;
+    rem = t - full_total;
+    has_sub = false;
+  } else {
+    rem = t - full_total - p.step_last;
+    for (int c = 0; c < TA; ++c) {
+      const int g = TA - c;
+      if (rem < g) {
+        k.type = rem == 0 ? T_TIPD : T_TIPO;
+        k.r = c + (int)rem;
+        k.c = c;
+        return k;
+      }
+      rem -= g;
+    }
+    return k;
+  }
+  const int Tb = has_sub ? T : 0;
+  for (int c = 0; c < T; ++c) {
+    const int g = (T - c) + Tb + TA;
+    if (rem < g) {
+      k.c = c;
+      if (rem < T - c) {
+        k.type = rem == 0 ? T_DIAG : T_OFFD;
+        k.r = c + (int)rem;
+      } else if (rem - (T - c) < Tb) {
+        k.type = T_SUB;
+        k.r = (int)(rem - (T - c));
+      } else {
+        k.type = T_ARW;
+        k.r = (int)(rem - (T - c) - Tb);
+      }
+      return k;
+    }
+    rem -= g;
+  }
+  // tip updates of this step (lower tiles, column by column)
+  for (int c = 0; c < TA; ++c) {
+    const int g = TA - c;
+    if (rem < g) {
+      k.type = T_TUPD;
+      k.r = c + (int)rem;
+      k.c = c;
+      return k;
+    }
+    rem -= g;
+  }
+  return k;
+}
+
+// Tile views of the block arrays.
+__host__ __device__ inline int ext(int total, int t) { int e = total - 64 * t; return e < 64 ? e : 64; }
+
+struct Shared {
+  double As[TS * LDS_LD];
+  double Bs[TS * LDS_LD];
+  double colbuf[2 * 64];
+  double pivbuf[2];
+  long long ticket;
+  int fail;
+  int ok;
+};
+
+// One k step of a left-looking task: operand tiles and their completion flags.
+struct KSrc {
+  OpTile a, b;
+  const int* fa;
+  const int* fb;
+};
+
+// Enumerate the k sources of a task.  Returns the number of k tiles and fills
+// src for index kk when kk >= 0.
+__host__ __device__ int ksources(const FactorParams& p, const Task& t, int kk, KSrc* src) {
+  const int T = p.T, b = p.b, a = p.a;
+  const int64_t bb = (int64_t)b * b, ab = (int64_t)a * b;
+  const int nprev = (t.i > 0) ? T : 0;  // previous block column (cross-step update)
+  switch (t.type) {
+    case T_DIAG:
+    case T_OFFD: {
+      const int cnt = nprev + t.c;
+      if (kk < 0) return cnt;
+      if (kk < nprev) {
+        const double* Lb = p.LB + (int64_t)(t.i - 1) * bb;
+        src->a = OpTile{Lb + (int64_t)t.r * 64 * b + kk * 64, b, ext(b, t.r), ext(b, kk), false};
+        src->b = OpTile{Lb + (int64_t)t.c * 64 * b + kk * 64, b, ext(b, t.c), ext(b, kk), false};
+        src->fa = p.flags + fl_B(p, t.i - 1, t.r, kk);
+        src->fb = p.flags + fl_B(p, t.i - 1, t.c, kk);
+      } else {
+        const int k = kk - nprev;
+        const double* Ld = p.LD + (int64_t)t.i * bb;
+        src->a = OpTile{Ld + (int64_t)t.r * 64 * b + k * 64, b, ext(b, t.r), ext(b, k), false};
+        src->b = OpTile{Ld + (int64_t)t.c * 64 * b + k * 64, b, ext(b, t.c), ext(b, k), false};
+        src->fa = p.flags + fl_D(p, t.i, t.r, k);
+        src->fb = p.flags + fl_D(p, t.i, t.c, k);
+      }
+      return cnt;
+    }
+    case T_SUB: {
+      const int cnt = t.c;
+      if (kk < 0) return cnt;
+      const double* Lb = p.LB + (int64_t)t.i * bb;
+      const double* Ld = p.LD + (int64_t)t.i * bb;
+      src->a = OpTile{Lb + (int64_t)t.r * 64 * b + kk * 64, b, ext(b, t.r), ext(b, kk), false};
+      src->b = OpTile{Ld + (int64_t)t.c * 64 * b + kk * 64, b, ext(b, t.c), ext(b, kk), false};
+      src->fa = p.flags + fl_B(p, t.i, t.r, kk);
+      src->fb = p.flags + fl_D(p, t.i, t.c, kk);
+      return cnt;
+    }
+    case T_ARW: {
+      const int cnt = nprev + t.c;
+      if (kk < 0) return cnt;
+      if (kk < nprev) {
+        const double* Lr = p.LR + (int64_t)(t.i - 1) * ab;
+        const double* Lb = p.LB + (int64_t)(t.i - 1) * bb;
+        src->a = OpTile{Lr + (int64_t)t.r * 64 * b + kk * 64, b, ext(a, t.r), ext(b, kk), false};
+        src->b = OpTile{Lb + (int64_t)t.c * 64 * b + kk * 64, b, ext(b, t.c), ext(b, kk), false};
+        src->fa = p.flags + fl_R(p, t.i - 1, t.r, kk);
+        src->fb = p.flags + fl_B(p, t.i - 1, t.c, kk);
+      } else {
+        const int k = kk - nprev;
+        const double* Lr = p.LR + (int64_t)t.i * ab;
+        const double* Ld = p.LD + (int64_t)t.i * bb;
+        src->a = OpTile{Lr + (int64_t)t.r * 64 * b + k * 64, b, ext(a, t.r), ext(b, k), false};
+        src->b = OpTile{Ld + (int64_t)t.c * 64 * b + k * 64, b, ext(b, t.c), ext(b, k), false};
+        src->fa = p.flags + fl_R(p, t.i, t.r, k);
+        src->fb = p.flags + fl_D(p, t.i, t.c, k);
+      }
+      return cnt;
+    }
+    case T_TUPD: {
+      const int cnt = T;
+      if (kk < 0) return cnt;
+      const double* Lr = p.LR + (int64_t)t.i * ab;
+      src->a = OpTile{Lr + (int64_t)t.r * 64 * b + kk * 64, b, ext(a, t.r), ext(b, kk), false};
+      src->b = OpTile{Lr + (int64_t)t.c * 64 * b + kk * 64, b, ext(a, t.c), ext(b, kk), false};
+      src->fa = p.flags + fl_R(p, t.i, t.r, kk);
+      src->fb = p.flags + fl_R(p, t.i, t.c, kk);
+      return cnt;
+    }
+    case T_TIPD:
+    case T_TIPO: {
+      const int cnt = t.c;
+      if (kk < 0) return cnt;
+      src->a = OpTile{p.LT + (int64_t)t.r * 64 * a + kk * 64, a, ext(a, t.r), ext(a, kk), false};
+      src->b = OpTile{p.LT + (int64_t)t.c * 64 * a + kk * 64, a, ext(a, t.c), ext(a, kk), false};
+      src->fa = p.flags + fl_tip(p, t.r, kk);
+      src->fb = p.flags + fl_tip(p, t.c, kk);
+      return cnt;
+    }
+  }
+  return 0;
+}
+
+// Block until flags are set (thread 0 polls); returns false on abort.
+__device__ __forceinline__ bool wait_ready(const FactorParams& p, const int* f1, const int* f2, Shared& sh, int tid) {
+  if (tid == 0) {
+    bool ok = spin_wait(f1, p.ctl + 2, p.spin_limit);
+    if (ok && f2 != f1) ok = spin_wait(f2, p.ctl + 2, p.spin_limit);
+    acquire_fence();
+    sh.ok = ok ? 1 : 0;
+  }
+  __syncthreads();
+  return sh.ok != 0;
+}
+
+__global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
+  __shared__ Shared sh;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) sh.ticket = (long long)atomicAdd((unsigned long long*)p.ctl, 1ULL);
+    __syncthreads();
+    const long long tk = sh.ticket;
+    __syncthreads();
+    if (tk >= p.ntasks) break;
+    const Task t = decode(p, tk);
+    const int T = p.T, b = p.b, a = p.a;
+    const int64_t bb = (int64_t)b * b, ab = (int64_t)a * b;
+
+    // ---- output tile and its input
+    const double* in;
+    double* out;
+    int64_t ld;
+    int rows, cols;
+    int* my_flag;
+    switch (t.type) {
+      case T_DIAG:
+      case T_OFFD:
+        in = p.D + t.i * bb + (int64_t)t.r * 64 * b + t.c * 64;
+        out = p.LD + t.i * bb + (int64_t)t.r * 64 * b + t.c * 64;
+        ld = b; rows = ext(b, t.r); cols = ext(b, t.c);
+        my_flag = p.flags + fl_D(p, t.i, t.r, t.c);
+        break;
+      case T_SUB:
+        in = p.B + t.i * bb + (int64_t)t.r * 64 * b + t.c * 64;
+        out = p.LB + t.i * bb + (int64_t)t.r * 64 * b + t.c * 64;
+        ld = b; rows = ext(b, t.r); cols = ext(b, t.c);
+        my_flag = p.flags + fl_B(p, t.i, t.r, t.c);
+        break;
+      case T_ARW:
+        in = p.R + t.i * ab + (int64_t)t.r * 64 * b + t.c * 64;
+        out = p.LR + t.i * ab + (int64_t)t.r * 64 * b + t.c * 64;
+        ld = b; rows = ext(a, t.r); cols = ext(b, t.c);
+        my_flag = p.flags + fl_R(p, t.i, t.r, t.c);
+        break;
+      case T_TUPD:
+        in = nullptr;
+        out = p.P + ((int64_t)t.i * p.TA * p.TA + (int64_t)t.r * p.TA + t.c) * 4096;
+        ld = 64; rows = 64; cols = 64;
+        my_flag = p.flags + fl_U(p, t.i, t.r, t.c);
+        break;
+      default:  // tip
+        in = p.Tt + (int64_t)t.r * 64 * a + t.c * 64;
+        out = p.LT + (int64_t)t.r * 64 * a + t.c * 64;
+        ld = a; rows = ext(a, t.r); cols = ext(a, t.c);
+        my_flag = p.flags + fl_tip(p, t.r, t.c);
+        break;
+    }
+    const bool is_diag = (t.type == T_DIAG || t.type == T_TIPD);
+
+    // ---- accumulator = -(input tile); a padded diagonal tile gets -1 on the padded diagonal
+    Acc acc;
+    if (in) {
+      acc_load(acc, in, ld, rows, cols, -1.0, tid);
+      if (is_diag && rows < 64) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int rr = tile_row(tid, bi, j), cc = tile_col(tid, bj);
+              if (rr == cc && rr >= rows) acc.v[bi][bj][j] = -1.0;
+            }
+      }
+    } else {
+      acc_zero(acc);
+    }
+
+    // tip tiles: subtract the per-step updates in step order
+    if (t.type == T_TIPD || t.type == T_TIPO) {
+      for (int i = 0; i < p.n; ++i) {
+        if (!wait_ready(p, p.flags + fl_U(p, i, t.r, t.c), p.flags + fl_U(p, i, t.r, t.c), sh, tid)) break;
+        const double* Pi = p.P + ((int64_t)i * p.TA * p.TA + (int64_t)t.r * p.TA + t.c) * 4096;
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              acc.v[bi][bj][j] += Pi[tile_row(tid, bi, j) * 64 + tile_col(tid, bj)];
+      }
+    }
+
+    // ---- left-looking accumulation: acc += sum_k A_k B_k^T  (acc holds -(A - sum))
+    const int nk = ksources(p, t, -1, nullptr);
+    int ready_upto = 0;
+    for (int kk = 0; kk < nk; ++kk) {
+      KSrc s;
+      ksources(p, t, kk, &s);
+      if (kk >= ready_upto) {
+        // wait for this k tile, then take every following k tile that is already final
+        if (tid == 0) {
+          bool ok = spin_wait(s.fa, p.ctl + 2, p.spin_limit) && spin_wait(s.fb, p.ctl + 2, p.spin_limit);
+          int upto = kk + 1;
+          while (ok && upto < nk) {
+            KSrc s2;
+            ksources(p, t, upto, &s2);
+            if (flag_set(s2.fa) && flag_set(s2.fb)) ++upto; else break;
+          }
+          acquire_fence();
+          sh.ok = ok ? upto : -1;
+        }
+        __syncthreads();
+        if (sh.ok < 0) break;
+        ready_upto = sh.ok;
+      }
+      Stage ra, rb;
+      stage_load(ra, s.a, tid);
+      stage_load(rb, s.b, tid);
+      __syncthreads();  // previous k tile consumed
+      stage_store(ra, sh.As, false, tid);
+      stage_store(rb, sh.Bs, false, tid);
+      __syncthreads();
+      mma_tile(acc, sh.As, sh.Bs, tid);
+    }
+    __syncthreads();
+
+    // ---- finish the tile
+    if (t.type == T_TUPD) {
+      acc_store(acc, out, 64, 64, 64, 1.0, 0, tid);
+    } else if (is_diag) {
+      // LDS: As <- A - sum (negate back), factor + invert in place
+      acc_to_lds(acc, sh.As, tid);
+      __syncthreads();
+      for (int e = tid; e < 64 * 64; e += NT) sh.As[(e >> 6) * LDS_LD + (e & 63)] *= -1.0;
+      __syncthreads();
+      const int f = chol_inv_tile(sh.As, sh.Bs, sh.colbuf, sh.pivbuf, &sh.fail, tid);
+      if (f != 0 && f <= rows && tid == 0) {
+        const long long row0 = (t.type == T_DIAG) ? (long long)t.i * b + (long long)t.c * 64
+                                                  : (long long)p.n * b + (long long)t.c * 64;
+        atomicMin((unsigned long long*)p.info, (unsigned long long)(row0 + f));
+      }
+      double* Wout = (t.type == T_DIAG) ? p.Wd + ((int64_t)t.i * T + t.c) * 4096 : p.Wt + (int64_t)t.c * 4096;
+      for (int e = tid; e < 64 * 64; e += NT) {
+        const int rr = e >> 6, cc = e & 63;
+        if (rr < rows && cc < cols) out[(int64_t)rr * ld + cc] = sh.As[rr * LDS_LD + cc];
+        Wout[e] = sh.Bs[rr * LDS_LD + cc];
+      }
+    } else {
+      // X = (A - sum) W(c,c)^T
+      const double* Wc = (t.type == T_TIPO) ? p.Wt + (int64_t)t.c * 4096
+                                            : p.Wd + ((int64_t)t.i * T + t.c) * 4096;
+      const int* fdiag = (t.type == T_TIPO) ? p.flags + fl_tip(p, t.c, t.c) : p.flags + fl_D(p, t.i, t.c, t.c);
+      wait_ready(p, fdiag, fdiag, sh, tid);
+      acc_to_lds(acc, sh.As, tid);
+      Stage rw;
+      stage_load(rw, OpTile{Wc, 64, 64, 64, false}, tid);
+      stage_store(rw, sh.Bs, false, tid);
+      __syncthreads();
+      Acc x;
+      acc_zero(x);
+      mma_tile(x, sh.As, sh.Bs, tid);
+      acc_store(x, out, ld, rows, cols, -1.0, 0, tid);
+      // exact zeros in the mirrored (upper) tile of a diagonal block / the tip
+      if (t.type == T_OFFD || t.type == T_TIPO) {
+        double* up = (t.type == T_OFFD) ? p.LD + t.i * bb + (int64_t)t.c * 64 * b + t.r * 64
+                                        : p.LT + (int64_t)t.c * 64 * a + t.r * 64;
+        const int ur = cols, uc = rows;
+        for (int e = tid; e < 64 * 64; e += NT) {
+          const int rr = e >> 6, cc = e & 63;
+          if (rr < ur && cc < uc) up[(int64_t)rr * ld + cc] = 0.0;
+        }
+      }
+    }
+    publish_flag(my_flag, tid);
+  }
+}
+
+// Clear the flags, the ticket counter and the abort flag, and zero info.
+__global__ void factor_reset_kernel(int* flags, long long nflags, int* ctl, int64_t* info) {
+  const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (long long i = i0; i < nflags; i += (long long)gridDim.x * blockDim.x) flags[i] = 0;
+  if (i0 < 4) ctl[i0] = 0;
+  if (i0 == 0) *info = 0x7fffffffffffffffLL;
+}
+
+// info: "no failure" is kept as INT64_MAX during the run; map to 0, and an
+// aborted run (watchdog) to -1.
+__global__ void factor_finish_kernel(const int* ctl, int64_t* info) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (ctl[2] != 0) *info = -1;
+    else if (*info == 0x7fffffffffffffffLL) *info = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
+  FactorPlan fp{};
+  const int64_t T = (b + 63) / 64, TA = (a + 63) / 64;
+  fp.T = (int)T;
+  fp.TA = (int)TA;
+  fp.nflags = n * (2 * T * T + TA * T + TA * TA) + TA * TA;
+  fp.step_full = T * (T + 1) / 2 + T * T + T * TA + TA * (TA + 1) / 2;
+  fp.step_last = T * (T + 1) / 2 + T * TA + TA * (TA + 1) / 2;
+  fp.ntasks = (n - 1) * fp.step_full + fp.step_last + TA * (TA + 1) / 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
+  fp.off_ctl = take(64);
+  fp.off_flags = take(sizeof(int) * (size_t)fp.nflags);
+  fp.off_Wd = take(sizeof(double) * 4096 * (size_t)(n * T));
+  fp.off_Wt = take(sizeof(double) * 4096 * (size_t)(TA > 0 ? TA : 1));
+  fp.off_P = take(sizeof(double) * 4096 * (size_t)(n * TA * TA > 0 ? n * TA * TA : 1));
+  fp.bytes = off;
+  return fp;
+}
+
+hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
+                         const double* D, const double* B, const double* R, const double* T,
+                         double* LD, double* LB, double* LR, double* LT,
+                         void* work, int64_t* info, hipStream_t stream, int num_cus) {
+  char* w = static_cast<char*>(work);
+  FactorParams p;
+  p.n = (int)n; p.b = (int)b; p.a = (int)a; p.T = fp.T; p.TA = fp.TA;
+  p.D = D; p.B = B; p.R = R; p.Tt = T;
+  p.LD = LD; p.LB = LB; p.LR = LR; p.LT = LT;
+  p.Wd = reinterpret_cast<double*>(w + fp.off_Wd);
+  p.Wt = reinterpret_cast<double*>(w + fp.off_Wt);
+  p.P = reinterpret_cast<double*>(w + fp.off_P);
+  p.flags = reinterpret_cast<int*>(w + fp.off_flags);
+  p.ctl = reinterpret_cast<int*>(w + fp.off_ctl);
+  p.info = info;
+  p.ntasks = fp.ntasks;
+  p.step_full = fp.step_full;
+  p.step_last = fp.step_last;
+  p.spin_limit = 1LL << 22;  // a few seconds of polling without progress before the watchdog fires
+  const int rgrid = (int)std::min<long long>(1024, (fp.nflags + 255) / 256 + 1);
+  hipLaunchKernelGGL(factor_reset_kernel, dim3(rgrid), dim3(256), 0, stream, p.flags, fp.nflags, p.ctl, info);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long grid = std::min<long long>(fp.ntasks, 2LL * num_cus);
+  timing_mark(KT_FACTOR, true, stream);
+  hipLaunchKernelGGL(factor_kernel, dim3((unsigned)grid), dim3(NT), 0, stream, p);
+  timing_mark(KT_FACTOR, false, stream);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(factor_finish_kernel, dim3(1), dim3(64), 0, stream, p.ctl, info);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Host replay of the task schedule: every ticket decodes to a distinct tile,
+// every flag a task waits on belongs to a task with a smaller ticket (so the
+// in-order ticket dispatch cannot deadlock), and every operand window lies
+// inside its array.  Returns 0 when the schedule is valid, else an error code.
+int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* [7] or null */) {
+  const FactorPlan fp = factor_plan(n, b, a);
+  FactorParams p{};
+  p.n = (int)n; p.b = (int)b; p.a = (int)a; p.T = fp.T; p.TA = fp.TA;
+  const uintptr_t G = uintptr_t(1) << 40;
+  p.LD = reinterpret_cast<double*>(1 * G);
+  p.LB = reinterpret_cast<double*>(2 * G);
+  p.LR = reinterpret_cast<double*>(3 * G);
+  p.LT = reinterpret_cast<double*>(4 * G);
+  p.flags = reinterpret_cast<int*>(5 * G);
+  p.ntasks = fp.ntasks; p.step_full = fp.step_full; p.step_last = fp.step_last;
+  const size_t lim[4] = {(size_t)(n * b * b), (size_t)((n - 1) * b * b), (size_t)(n * a * b), (size_t)(a * a)};
+  auto inside = [&](const OpTile& o) -> bool {
+    if (o.rows <= 0 || o.cols <= 0) return false;
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(o.p);
+    const int arr = (int)(addr / G) - 1;
+    if (arr < 0 || arr > 3) return false;
+    const size_t off = (addr - (arr + 1) * G) / sizeof(double);
+    const size_t last = off + (size_t)(o.rows - 1) * o.ld + (o.cols - 1);
+    return last < lim[arr] && (size_t)o.cols <= (size_t)o.ld;
+  };
+  std::vector<long long> owner((size_t)fp.nflags, -1);
+  long long cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (long long tk = 0; tk < fp.ntasks; ++tk) {
+    const Task t = decode(p, tk);
+    if (t.type < 0 || t.type > 6) return 1;
+    cnt[t.type]++;
+    int64_t f;
+    switch (t.type) {
+      case T_DIAG: case T_OFFD: f = fl_D(p, t.i, t.r, t.c); if (t.r < t.c || t.r >= p.T) return 2; break;
+      case T_SUB: f = fl_B(p, t.i, t.r, t.c); if (t.i >= n - 1) return 2; break;
+      case T_ARW: f = fl_R(p, t.i, t.r, t.c); break;
+      case T_TUPD: f = fl_U(p, t.i, t.r, t.c); break;
+      default: f = fl_tip(p, t.r, t.c); break;
+    }
+    if (f < 0 || f >= fp.nflags || owner[(size_t)f] != -1) return 3;
+    const int nk = ksources(p, t, -1, nullptr);
+    for (int kk = 0; kk < nk; ++kk) {
+      KSrc s;
+      ksources(p, t, kk, &s);
+      const int64_t fa = s.fa - p.flags, fb = s.fb - p.flags;
+      if (fa < 0 || fa >= fp.nflags || fb < 0 || fb >= fp.nflags) return 4;
+      if (owner[(size_t)fa] < 0 || owner[(size_t)fb] < 0) return 5;
+      if (!inside(s.a) || !inside(s.b)) return 6;
+    }
+    if (t.type == T_OFFD || t.type == T_SUB || t.type == T_ARW) {
+      if (owner[(size_t)fl_D(p, t.i, t.c, t.c)] < 0) return 7;
+    }
+    if (t.type == T_TIPO && owner[(size_t)fl_tip(p, t.c, t.c)] < 0) return 7;
+    if (t.type == T_TIPD || t.type == T_TIPO) {
+      for (int i = 0; i < p.n; ++i)
+        if (owner[(size_t)fl_U(p, i, t.r, t.c)] < 0) return 8;
+    }
+    owner[(size_t)f] = tk;
+  }
+  const long long T = fp.T, TA = fp.TA;
+  const long long expect[7] = {n * T, n * T * (T - 1) / 2, (n - 1) * T * T, n * T * TA, n * TA * (TA + 1) / 2, TA,
+                               TA * (TA - 1) / 2};
+  for (int k = 0; k < 7; ++k) {
+    if (counts) counts[k] = cnt[k];
+    if (cnt[k] != expect[k]) return 9;
+  }
+  return 0;
+}
+
+}  // namespace bta
+
+extern "C" __attribute__((visibility("default"))) int bta_internal_factor_schedule_check(int64_t n, int64_t b, int64_t a,
+                                                                                          long long* counts) {
+  return bta::factor_schedule_check(n, b, a, counts);
+}

@@ -1,0 +1,287 @@
+// POBTASI (Algorithm 2) on gfx950, in the inverse-factor form.
+//
+// With W_i = L_ii^{-1}, P_i = [L_{i+1,i}; L_{n,i}] W_i and the already final
+// window S_{i+1} = [[X_{i+1,i+1}, X_{n,i+1}^T], [X_{n,i+1}, X_{n,n}]], the
+// backward step of Algorithm 2 reads
+//
+//   [X_{i+1,i}; X_{n,i}] = -S_{i+1} P_i
+//   X_{i,i}              = W_i^T W_i - [X_{i+1,i}; X_{n,i}]^T P_i
+//
+// which is the listing's U blocks followed by its right-side solves with
+// L_ii, with each solve replaced by the product with W_i (the paper's own
+// substitution of repeated TRSMs by one inversion plus GEMMs).  W_i, P_i and
+// V_i = W_i^T W_i depend on the factor only, so they are computed for all
+// blocks up front in large batched launches (chunks of blocks); the
+// sequential backward sweep is then two MFMA GEMM launches per step.
+//   X_{n,n} = L_nn^{-T} L_nn^{-1} comes from the same inverse + product.
+#include <algorithm>
+
+#include "bta_device.hpp"
+#include "bta_internal.hpp"
+
+namespace bta {
+
+static GProb prob_init() {
+  GProb p{};
+  p.nseg = 0;
+  p.nb0 = 1;
+  p.nb1 = 1;
+  p.alpha = 1.0;
+  p.beta = 0.0;
+  p.store = ST_FULL;
+  p.lower_tiles = 0;
+  return p;
+}
+
+static GSeg seg(const double* A, int64_t lda, int at, const double* B, int64_t ldb, int bt, int K, int tri,
+                int64_t sA0 = 0, int64_t sB0 = 0, int64_t sA1 = 0, int64_t sB1 = 0) {
+  GSeg s{};
+  s.A = A; s.B = B; s.lda = lda; s.ldb = ldb; s.at = at; s.bt = bt; s.K = K; s.tri = tri;
+  s.sA0 = sA0; s.sB0 = sB0; s.sA1 = sA1; s.sB1 = sB1;
+  return s;
+}
+
+#define BTA_TRY(x)                      \
+  do {                                  \
+    hipError_t e_ = (x);                \
+    if (e_ != hipSuccess) return e_;    \
+  } while (0)
+
+// Inverse of nblk lower-triangular m x m matrices L (ld ldL, stride sL) into W
+// (ld ldW, stride sW; must be zero on entry), using T1 (same layout as W) as
+// scratch.  64-tile inverses first, then doubling: for neighbouring groups of
+// g tiles, W21 = -W22 (L21 W11).
+static hipError_t trtri_batched(const double* L, int64_t ldL, int64_t sL, double* W, double* T1, int64_t ldW, int64_t sW,
+                                int m, int nblk, hipStream_t s) {
+  BTA_TRY(trinv_diag_tiles_launch(L, ldL, sL, W, ldW, sW, m, nblk, s));
+  const int T = (m + 63) / 64;
+  for (int g = 1; g < T; g *= 2) {
+    // groups start at tiles 0, 2g, 4g, ... and exist while start + g < T; all
+    // but possibly the last have g + g full 64-row tiles
+    const int ngroups = (T - g + 2 * g - 1) / (2 * g);
+    const int s_last = 2 * g * (ngroups - 1);
+    const bool last_full = (s_last + 2 * g < T) || (s_last + 2 * g == T && m % 64 == 0);
+    const int nfull = last_full ? ngroups : ngroups - 1;
+    const int s_part = s_last;
+    const bool part = !last_full;
+    const int m1 = 64 * g;
+    const int64_t gstepL = (int64_t)2 * g * 64 * (ldL + 1);
+    const int64_t gstepW = (int64_t)2 * g * 64 * (ldW + 1);
+    GProb pr[2];
+    int np = 0;
+    // T1 = L21 * W11
+    for (int which = 0; which < 2; ++which) {
+      const int s0 = which == 0 ? 0 : s_part;
+      const int cnt = which == 0 ? nfull : (part ? 1 : 0);
+      if (cnt == 0) continue;
+      const int m2 = which == 0 ? 64 * g : (m - 64 * (s0 + g));
+      GProb p = prob_init();
+      const double* L21 = L + (int64_t)(s0 + g) * 64 * ldL + (int64_t)s0 * 64;
+      const double* W11 = W + (int64_t)s0 * 64 * ldW + (int64_t)s0 * 64;
+      p.seg[0] = seg(L21, ldL, 0, W11, ldW, 1, m1, TRI_K_GE_COL, sL, sW, gstepL, gstepW);
+      p.nseg = 1;
+      p.Cout = T1 + (int64_t)(s0 + g) * 64 * ldW + (int64_t)s0 * 64;
+      p.ldc = ldW; p.sC0 = sW; p.sC1 = gstepW;
+      p.M = m2; p.N = m1; p.nb0 = nblk; p.nb1 = cnt;
+      pr[np++] = p;
+    }
+    BTA_TRY(gemm_launch(pr, np, s));
+    np = 0;
+    // W21 = -W22 * T1
+    for (int which = 0; which < 2; ++which) {
+      const int s0 = which == 0 ? 0 : s_part;
+      const int cnt = which == 0 ? nfull : (part ? 1 : 0);
+      if (cnt == 0) continue;
+      const int m2 = which == 0 ? 64 * g : (m - 64 * (s0 + g));
+      GProb p = prob_init();
+      const double* W22 = W + (int64_t)(s0 + g) * 64 * (ldW + 1);
+      const double* T1b = T1 + (int64_t)(s0 + g) * 64 * ldW + (int64_t)s0 * 64;
+      p.seg[0] = seg(W22, ldW, 0, T1b, ldW, 1, m2, TRI_K_LE_ROW, sW, sW, gstepW, gstepW);
+      p.nseg = 1;
+      p.Cout = W + (int64_t)(s0 + g) * 64 * ldW + (int64_t)s0 * 64;
+      p.ldc = ldW; p.sC0 = sW; p.sC1 = gstepW;
+      p.M = m2; p.N = m1; p.nb0 = nblk; p.nb1 = cnt;
+      p.alpha = -1.0;
+      pr[np++] = p;
+    }
+    BTA_TRY(gemm_launch(pr, np, s));
+  }
+  return hipSuccess;
+}
+
+SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a) {
+  SelinvPlan sp{};
+  const int64_t T = (b + 63) / 64;
+  // enough blocks per chunk to give the 64-tile inverses ~512 workgroups,
+  // within ~4 GB of workspace (W, T1 and P per block of the chunk)
+  int64_t chunk = (512 + T - 1) / T;
+  const int64_t per_block = 8 * (2 * b * b + (b + a) * b);
+  chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, (int64_t(4) << 30) / per_block));
+  chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, 64));
+  chunk = std::min<int64_t>(chunk, n);
+  sp.chunk = chunk;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
+  const size_t bb = (size_t)b * b, pb = (size_t)(b + a) * b;
+  sp.off_W = take(8 * bb * chunk);
+  sp.off_T1 = take(8 * bb * chunk);
+  sp.off_P = take(8 * pb * chunk);
+  sp.off_Xp = take(8 * pb);
+  sp.off_WT = take(8 * (size_t)std::max<int64_t>(1, 2 * a * a));
+  sp.bytes = off;
+  return sp;
+}
+
+hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
+                         const double* LD, const double* LB, const double* LR, const double* LT,
+                         double* XD, double* XB, double* XR, double* XT,
+                         void* work, hipStream_t s) {
+  char* w = static_cast<char*>(work);
+  double* Ws = reinterpret_cast<double*>(w + sp.off_W);
+  double* T1 = reinterpret_cast<double*>(w + sp.off_T1);
+  double* Pw = reinterpret_cast<double*>(w + sp.off_P);
+  double* Xp = reinterpret_cast<double*>(w + sp.off_Xp);
+  double* WT = reinterpret_cast<double*>(w + sp.off_WT);
+  const int64_t bb = b * b, ab = a * b, pb = (b + a) * b;
+  const int ib = (int)b, ia = (int)a;
+
+  // ---- tip: X_nn = W_T^T W_T
+  if (a > 0) {
+    double* WTt = WT + a * a;
+    BTA_TRY(fill_zero_launch(WT, (size_t)(2 * a * a), s));
+    BTA_TRY(trtri_batched(LT, a, 0, WT, WTt, a, 0, ia, 1, s));
+    GProb p = prob_init();
+    p.seg[0] = seg(WT, a, 1, WT, a, 1, ia, TRI_K_GE_ROW);
+    p.nseg = 1;
+    p.Cout = XT; p.ldc = a;
+    p.M = ia; p.N = ia;
+    p.lower_tiles = 1;
+    p.store = ST_LOWER_MIRROR;
+    BTA_TRY(gemm_launch(&p, 1, s));
+  }
+
+  // ---- per-block preprocessing, chunk by chunk
+  for (int64_t i0 = 0; i0 < n; i0 += sp.chunk) {
+    const int nblk = (int)std::min<int64_t>(sp.chunk, n - i0);
+    const int nsub = (int)std::min<int64_t>(nblk, (n - 1) - i0);  // blocks of the chunk with an L_{i+1,i}
+    BTA_TRY(fill_zero_launch(Ws, (size_t)bb * nblk, s));
+    BTA_TRY(trtri_batched(LD + i0 * bb, b, bb, Ws, T1, b, bb, ib, nblk, s));
+    GProb pr[3];
+    int np = 0;
+    if (nsub > 0) {  // P_B = L_{i+1,i} W_i
+      GProb p = prob_init();
+      p.seg[0] = seg(LB + i0 * bb, b, 0, Ws, b, 1, ib, TRI_K_GE_COL, bb, bb);
+      p.nseg = 1;
+      p.Cout = Pw; p.ldc = b; p.sC0 = pb;
+      p.M = ib; p.N = ib; p.nb0 = nsub;
+      pr[np++] = p;
+    }
+    if (a > 0) {  // P_R = L_{n,i} W_i
+      GProb p = prob_init();
+      p.seg[0] = seg(LR + i0 * ab, b, 0, Ws, b, 1, ib, TRI_K_GE_COL, ab, bb);
+      p.nseg = 1;
+      p.Cout = Pw + bb; p.ldc = b; p.sC0 = pb;
+      p.M = ia; p.N = ib; p.nb0 = nblk;
+      pr[np++] = p;
+    }
+    {  // V_i = W_i^T W_i (lower) into X_ii
+      GProb p = prob_init();
+      p.seg[0] = seg(Ws, b, 1, Ws, b, 1, ib, TRI_K_GE_ROW, bb, bb);
+      p.nseg = 1;
+      p.Cout = XD + i0 * bb; p.ldc = b; p.sC0 = bb;
+      p.M = ib; p.N = ib; p.nb0 = nblk;
+      p.lower_tiles = 1;
+      p.store = ST_LOWER;
+      pr[np++] = p;
+    }
+    BTA_TRY(gemm_launch(pr, np, s));
+    BTA_TRY(copy2d_launch(Pw, b, pb, XB + i0 * bb, b, bb, ib, ib, nsub, s));
+    if (a > 0) BTA_TRY(copy2d_launch(Pw + bb, b, pb, XR + i0 * ab, b, ab, ia, ib, nblk, s));
+  }
+
+  // ---- backward sweep
+  for (int64_t i = n - 1; i >= 0; --i) {
+    const bool has_sub = i < n - 1;
+    const double* PB = has_sub ? XB + i * bb : nullptr;
+    const double* PR = a > 0 ? XR + i * ab : nullptr;
+    GProb pr[2];
+    int np = 0;
+    if (has_sub) {  // X_{i+1,i} = -(X_{i+1,i+1} P_B + X_{n,i+1}^T P_R)
+      GProb p = prob_init();
+      p.seg[0] = seg(XD + (i + 1) * bb, b, 0, PB, b, 1, ib, TRI_NONE);
+      p.nseg = 1;
+      if (a > 0) { p.seg[1] = seg(XR + (i + 1) * ab, b, 1, PR, b, 1, ia, TRI_NONE); p.nseg = 2; }
+      p.Cout = Xp; p.ldc = b;
+      p.M = ib; p.N = ib;
+      p.alpha = -1.0;
+      pr[np++] = p;
+    }
+    if (a > 0) {  // X_{n,i} = -(X_{n,i+1} P_B + X_nn P_R)
+      GProb p = prob_init();
+      if (has_sub) {
+        p.seg[0] = seg(XR + (i + 1) * ab, b, 0, PB, b, 1, ib, TRI_NONE);
+        p.seg[1] = seg(XT, a, 0, PR, b, 1, ia, TRI_NONE);
+        p.nseg = 2;
+      } else {
+        p.seg[0] = seg(XT, a, 0, PR, b, 1, ia, TRI_NONE);
+        p.nseg = 1;
+      }
+      p.Cout = Xp + bb; p.ldc = b;
+      p.M = ia; p.N = ib;
+      p.alpha = -1.0;
+      pr[np++] = p;
+    }
+    BTA_TRY(gemm_launch(pr, np, s));
+    {  // X_ii = V_i - [X_{i+1,i}; X_{n,i}]^T P_i  (lower, mirrored)
+      GProb p = prob_init();
+      p.nseg = 0;
+      if (has_sub) p.seg[p.nseg++] = seg(Xp, b, 1, PB, b, 1, ib, TRI_NONE);
+      if (a > 0) p.seg[p.nseg++] = seg(Xp + bb, b, 1, PR, b, 1, ia, TRI_NONE);
+      p.Cin = XD + i * bb; p.Cout = XD + i * bb; p.ldc = b;
+      p.M = ib; p.N = ib;
+      p.alpha = -1.0; p.beta = 1.0;
+      p.lower_tiles = 1;
+      p.store = ST_LOWER_MIRROR;
+      BTA_TRY(gemm_launch(&p, 1, s));
+    }
+    if (has_sub) BTA_TRY(copy2d_launch(Xp, b, 0, XB + i * bb, b, 0, ib, ib, 1, s));
+    if (a > 0) BTA_TRY(copy2d_launch(Xp + bb, b, 0, XR + i * ab, b, 0, ia, ib, 1, s));
+  }
+  return hipSuccess;
+}
+
+// Host dry run of selinv_launch with fake, widely separated array bases:
+// every window any launch would touch must lie inside one array (inputs are
+// never written).  Returns 0 when all windows are in bounds.
+int selinv_dry_check(int64_t n, int64_t b, int64_t a) {
+  const SelinvPlan sp = selinv_plan(n, b, a);
+  const uintptr_t G = uintptr_t(1) << 40;
+  const size_t sz[9] = {(size_t)(n * b * b) * 8, (size_t)((n - 1) * b * b) * 8, (size_t)(n * a * b) * 8, (size_t)(a * a) * 8,
+                        (size_t)(n * b * b) * 8, (size_t)((n - 1) * b * b) * 8, (size_t)(n * a * b) * 8, (size_t)(a * a) * 8,
+                        sp.bytes};
+  auto base = [&](int k) { return reinterpret_cast<double*>((uintptr_t)(k + 1) * G); };
+  DryRecorder rec;
+  g_dry = &rec;
+  hipError_t e = selinv_launch(sp, n, b, a, base(0), base(1), base(2), base(3), base(4), base(5), base(6), base(7),
+                               reinterpret_cast<void*>(base(8)), nullptr);
+  g_dry = nullptr;
+  if (e != hipSuccess) return 1;
+  for (const Window& w : rec.windows) {
+    if (w.rows <= 0 || w.cols <= 0) continue;
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(w.base);
+    const int arr = (int)(addr / G) - 1;
+    if (arr < 0 || arr > 8) return 2;
+    if (w.cols > w.ld) return 3;
+    const size_t first = addr - (uintptr_t)(arr + 1) * G;
+    const size_t last = first + 8 * ((size_t)(w.rows - 1) * w.ld + (w.cols - 1));
+    if (last + 8 > sz[arr]) return 4;
+    if (w.write && arr < 4) return 5;  // inputs are read only (out of place)
+  }
+  return 0;
+}
+
+}  // namespace bta
+
+extern "C" __attribute__((visibility("default"))) int bta_internal_selinv_dry_check(int64_t n, int64_t b, int64_t a) {
+  return bta::selinv_dry_check(n, b, a);
+}

@@ -1,0 +1,263 @@
+// Triangular solves with the BTA factor (A x = y via L z = y, L^T x = z) and
+// the log-determinant 2 * sum log diag(L).  Neither is in the paper; both are
+// needed for f(A) = log det A + y^T A^{-1} y and its gradient.
+//
+// The solve is memory bound (O(n b^2) reads of L per sweep).  Each right-hand
+// side column is handled by one workgroup that sweeps the block rows in order;
+// inside a diagonal block the substitution goes tile by tile, with the 64 x 64
+// diagonal tiles applied through their precomputed inverses.
+#include <algorithm>
+
+#include "bta_device.hpp"
+#include "bta_internal.hpp"
+
+namespace bta {
+
+// ---------------------------------------------------------------- logdet
+__global__ __launch_bounds__(256) void logdet_partial_kernel(const double* LD, const double* LT, int64_t n, int64_t b,
+                                                             int64_t a, double* partial) {
+  __shared__ double red[256];
+  const int64_t blk = blockIdx.x;
+  const double* L;
+  int64_t m;
+  if (blk < n) { L = LD + blk * b * b; m = b; } else { L = LT; m = a; }
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < m; k += 256) s += log(L[k * m + k]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blk] = red[0];
+}
+
+__global__ __launch_bounds__(256) void logdet_final_kernel(const double* partial, int64_t count, double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < count; k += 256) s += partial[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = 2.0 * red[0];
+}
+
+size_t logdet_work_bytes(int64_t n, int64_t b, int64_t a) { return 8 * (size_t)(n + 1) + 256; }
+
+hipError_t logdet_launch(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT, double* out, void* work,
+                         hipStream_t stream) {
+  double* partial = static_cast<double*>(work);
+  const int64_t nb = n + (a > 0 ? 1 : 0);
+  hipLaunchKernelGGL(logdet_partial_kernel, dim3((unsigned)nb), dim3(256), 0, stream, LD, LT, n, b, a, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(logdet_final_kernel, dim3(1), dim3(256), 0, stream, partial, nb, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- solve
+
+// Compact 64 x 64 inverses of the diagonal tiles of nblk m x m lower-triangular
+// blocks: tile t of block blk goes to Wc + (blk*T + t) * 4096 (ld 64).
+__global__ __launch_bounds__(NT) void tile_inverses_kernel(const double* L, int64_t m, int64_t sL, int T, double* Wc) {
+  __shared__ double S[TS * LDS_LD];
+  const int tid = threadIdx.x;
+  const int64_t blk = blockIdx.x / T;
+  const int t = (int)(blockIdx.x - blk * T);
+  const int ext = (int)std::min<int64_t>(64, m - (int64_t)t * 64);
+  const double* Lt = L + blk * sL + (int64_t)t * 64 * m + (int64_t)t * 64;
+  for (int e = tid; e < 64 * 64; e += NT) {
+    const int rr = e >> 6, cc = e & 63;
+    double v;
+    if (rr < ext && cc < ext) v = (cc <= rr) ? Lt[(int64_t)rr * m + cc] : 0.0;
+    else v = (rr == cc) ? 1.0 : 0.0;
+    S[rr * LDS_LD + cc] = v;
+  }
+  __syncthreads();
+  double w[16];
+  trinv_tile(S, w, tid);
+  const int r = tid & 63, q = tid >> 6;
+  double* Wt = Wc + (blk * T + t) * 4096;
+#pragma unroll
+  for (int mm = 0; mm < 16; ++mm) {
+    const int c = q + 4 * mm;
+    Wt[r * 64 + c] = (c <= r) ? w[mm] : 0.0;
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// out[r] (r < R <= 64) += sign * sum_{k<K} M[r*ld + k] x[k]   (row access, lanes over k)
+__device__ void rowdot_acc(const double* M, int64_t ld, int R, int64_t K, const double* x, double* out, double sign, int tid) {
+  const int w = tid >> 6, lane = tid & 63;
+  for (int r = w; r < R; r += 4) {
+    double s = 0.0;
+    const double* row = M + (int64_t)r * ld;
+    for (int64_t k = lane; k < K; k += 64) s += row[k] * x[k];
+    s = wave_sum(s);
+    if (lane == 0) out[r] += sign * s;
+  }
+}
+
+// out[k] (k < Kc <= 64) += sign * sum_{r<R} M[r*ld + k] x[r]   (column access)
+__device__ void coldot_acc(const double* M, int64_t ld, int64_t R, int Kc, const double* x, double* out, double* red,
+                           double sign, int tid) {
+  const int k = tid & 63, ph = tid >> 6;
+  double s = 0.0;
+  if (k < Kc)
+    for (int64_t r = ph; r < R; r += 4) s += M[r * ld + k] * x[r];
+  red[ph * 64 + k] = s;
+  __syncthreads();
+  if (tid < 64 && tid < Kc) out[tid] += sign * (red[tid] + red[64 + tid] + red[128 + tid] + red[192 + tid]);
+  __syncthreads();
+}
+
+struct SolveParams {
+  int64_t n, b, a, nrhs, N;
+  int T, TA;
+  const double* LD; const double* LB; const double* LR; const double* LT;
+  double* rhs;
+  const double* Wd;  // [n*T] tile inverses
+  const double* Wt;  // [TA] tip tile inverses
+  double* vec;       // [nrhs][N] contiguous working copies
+};
+
+__global__ __launch_bounds__(NT) void solve_kernel(SolveParams p) {
+  __shared__ double v[64];
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int64_t j = blockIdx.x;
+  const int64_t n = p.n, b = p.b, a = p.a, N = p.N;
+  const int64_t bb = b * b, ab = a * b;
+  double* z = p.vec + j * N;
+  for (int64_t r = tid; r < N; r += NT) z[r] = p.rhs[r * p.nrhs + j];
+  __syncthreads();
+
+  // ---- forward: z_i = L_ii^{-1} (y_i - L_{i,i-1} z_{i-1}); tip last
+  for (int64_t i = 0; i < n; ++i) {
+    const double* Ld = p.LD + i * bb;
+    for (int c = 0; c < p.T; ++c) {
+      const int ext = (int)std::min<int64_t>(64, b - (int64_t)c * 64);
+      const int64_t r0 = i * b + (int64_t)c * 64;
+      if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
+      __syncthreads();
+      if (i > 0) rowdot_acc(p.LB + (i - 1) * bb + (int64_t)c * 64 * b, b, ext, b, z + (i - 1) * b, v, -1.0, tid);
+      rowdot_acc(Ld + (int64_t)c * 64 * b, b, ext, (int64_t)c * 64, z + i * b, v, -1.0, tid);
+      __syncthreads();
+      // z_c = W_cc v
+      const double* W = p.Wd + (i * p.T + c) * 4096;
+      if (tid < 64) red[tid] = 0.0;
+      __syncthreads();
+      rowdot_acc(W, 64, ext, ext, v, red, 1.0, tid);
+      __syncthreads();
+      if (tid < ext) z[r0 + tid] = red[tid];
+      __syncthreads();
+    }
+  }
+  if (a > 0) {
+    for (int c = 0; c < p.TA; ++c) {
+      const int ext = (int)std::min<int64_t>(64, a - (int64_t)c * 64);
+      const int64_t r0 = n * b + (int64_t)c * 64;
+      if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
+      __syncthreads();
+      for (int64_t i = 0; i < n; ++i)
+        rowdot_acc(p.LR + i * ab + (int64_t)c * 64 * b, b, ext, b, z + i * b, v, -1.0, tid);
+      rowdot_acc(p.LT + (int64_t)c * 64 * a, a, ext, (int64_t)c * 64, z + n * b, v, -1.0, tid);
+      __syncthreads();
+      if (tid < 64) red[tid] = 0.0;
+      __syncthreads();
+      rowdot_acc(p.Wt + (int64_t)c * 4096, 64, ext, ext, v, red, 1.0, tid);
+      __syncthreads();
+      if (tid < ext) z[r0 + tid] = red[tid];
+      __syncthreads();
+    }
+  }
+
+  // ---- backward: x_n = L_nn^{-T} z_n; x_i = L_ii^{-T}(z_i - L_{i+1,i}^T x_{i+1} - L_{n,i}^T x_n)
+  __shared__ double red2[256];
+  if (a > 0) {
+    for (int c = p.TA - 1; c >= 0; --c) {
+      const int ext = (int)std::min<int64_t>(64, a - (int64_t)c * 64);
+      const int64_t r0 = n * b + (int64_t)c * 64;
+      if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
+      __syncthreads();
+      const int64_t below = a - ((int64_t)c * 64 + ext);
+      if (below > 0)
+        coldot_acc(p.LT + ((int64_t)c * 64 + ext) * a + (int64_t)c * 64, a, below, ext, z + n * b + (int64_t)c * 64 + ext,
+                   v, red, -1.0, tid);
+      // x_c = W_cc^T v
+      if (tid < 64) red2[tid] = 0.0;
+      __syncthreads();
+      coldot_acc(p.Wt + (int64_t)c * 4096, 64, ext, ext, v, red2, red, 1.0, tid);
+      if (tid < ext) z[r0 + tid] = red2[tid];
+      __syncthreads();
+    }
+  }
+  for (int64_t i = n - 1; i >= 0; --i) {
+    const double* Ld = p.LD + i * bb;
+    for (int c = p.T - 1; c >= 0; --c) {
+      const int ext = (int)std::min<int64_t>(64, b - (int64_t)c * 64);
+      const int64_t r0 = i * b + (int64_t)c * 64;
+      if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
+      __syncthreads();
+      if (i < n - 1) coldot_acc(p.LB + i * bb + (int64_t)c * 64, b, b, ext, z + (i + 1) * b, v, red, -1.0, tid);
+      if (a > 0) coldot_acc(p.LR + i * ab + (int64_t)c * 64, b, a, ext, z + n * b, v, red, -1.0, tid);
+      const int64_t below = b - ((int64_t)c * 64 + ext);
+      if (below > 0)
+        coldot_acc(Ld + ((int64_t)c * 64 + ext) * b + (int64_t)c * 64, b, below, ext, z + i * b + (int64_t)c * 64 + ext, v,
+                   red, -1.0, tid);
+      if (tid < 64) red2[tid] = 0.0;
+      __syncthreads();
+      coldot_acc(p.Wd + (i * p.T + c) * 4096, 64, ext, ext, v, red2, red, 1.0, tid);
+      if (tid < ext) z[r0 + tid] = red2[tid];
+      __syncthreads();
+    }
+  }
+  for (int64_t r = tid; r < N; r += NT) p.rhs[r * p.nrhs + j] = z[r];
+}
+
+size_t solve_work_bytes(int64_t n, int64_t b, int64_t a, int64_t nrhs) {
+  const int64_t T = (b + 63) / 64, TA = (a + 63) / 64;
+  const int64_t N = n * b + a;
+  size_t bytes = 0;
+  auto take = [&](size_t x) { bytes += (x + 255) & ~size_t(255); };
+  take(8 * 4096 * (size_t)(n * T));
+  take(8 * 4096 * (size_t)std::max<int64_t>(TA, 1));
+  take(8 * (size_t)(N * nrhs));
+  return bytes;
+}
+
+hipError_t solve_launch(int64_t n, int64_t b, int64_t a, const double* LD, const double* LB, const double* LR,
+                        const double* LT, double* rhs, int64_t nrhs, void* work, hipStream_t stream) {
+  const int64_t T = (b + 63) / 64, TA = (a + 63) / 64;
+  char* w = static_cast<char*>(work);
+  size_t off = 0;
+  auto take = [&](size_t x) { size_t o = off; off += (x + 255) & ~size_t(255); return o; };
+  SolveParams p;
+  p.n = n; p.b = b; p.a = a; p.nrhs = nrhs; p.N = n * b + a;
+  p.T = (int)T; p.TA = (int)TA;
+  p.LD = LD; p.LB = LB; p.LR = LR; p.LT = LT; p.rhs = rhs;
+  double* Wd = reinterpret_cast<double*>(w + take(8 * 4096 * (size_t)(n * T)));
+  double* Wt = reinterpret_cast<double*>(w + take(8 * 4096 * (size_t)std::max<int64_t>(TA, 1)));
+  p.vec = reinterpret_cast<double*>(w + take(8 * (size_t)(p.N * nrhs)));
+  p.Wd = Wd; p.Wt = Wt;
+  hipLaunchKernelGGL(tile_inverses_kernel, dim3((unsigned)(n * T)), dim3(NT), 0, stream, LD, b, b * b, (int)T, Wd);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a > 0) {
+    hipLaunchKernelGGL(tile_inverses_kernel, dim3((unsigned)TA), dim3(NT), 0, stream, LT, a, (int64_t)0, (int)TA, Wt);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(solve_kernel, dim3((unsigned)nrhs), dim3(NT), 0, stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace bta

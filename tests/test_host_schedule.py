@@ -1,0 +1,45 @@
+"""CPU checks of the host logic behind the GPU kernels (no GPU needed).
+
+* The persistent factorization kernel takes tasks in ticket order; the host
+  replay checks that every ticket decodes to a distinct tile, that every flag
+  a task waits on belongs to a task with a smaller ticket (no deadlock
+  whatever the number of resident workgroups), and that every operand tile
+  lies inside its array.
+* The selected inversion is a sequence of launches; its dry run records every
+  window each launch would read or write and checks it against array bounds.
+"""
+import ctypes
+import itertools
+
+import pytest
+
+from paper_2503_17528_amd import bta
+
+
+@pytest.fixture(scope="module")
+def L():
+    lib = ctypes.CDLL(bta.LIB_PATH)
+    lib.bta_internal_factor_schedule_check.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p]
+    lib.bta_internal_selinv_dry_check.argtypes = [ctypes.c_int64] * 3
+    return lib
+
+
+SHAPES = list(itertools.product([1, 2, 3, 7], [1, 5, 63, 64, 65, 130, 200], [0, 1, 4, 64, 65, 130]))
+
+
+@pytest.mark.parametrize("n,b,a", SHAPES)
+def test_factor_schedule_is_topological_and_in_bounds(L, n, b, a):
+    counts = (ctypes.c_longlong * 7)()
+    assert L.bta_internal_factor_schedule_check(n, b, a, counts) == 0
+    T, TA = (b + 63) // 64, (a + 63) // 64
+    assert sum(counts) == n * T * (T + 1) // 2 + (n - 1) * T * T + n * T * TA + n * TA * (TA + 1) // 2 + TA * (TA + 1) // 2
+
+
+@pytest.mark.parametrize("n,b,a", [(128, 2048, 8), (256, 512, 4), (16, 64, 4), (96, 384, 6)])
+def test_factor_schedule_workload_sizes(L, n, b, a):
+    assert L.bta_internal_factor_schedule_check(n, b, a, None) == 0
+
+
+@pytest.mark.parametrize("n,b,a", SHAPES + [(128, 2048, 8), (256, 4096, 16), (256, 512, 4), (33, 384, 6)])
+def test_selinv_launch_windows_in_bounds(L, n, b, a):
+    assert L.bta_internal_selinv_dry_check(n, b, a) == 0
