@@ -203,13 +203,14 @@ __device__ __forceinline__ void acc_store(const Acc& c, double* p, int64_t ld, i
 // `S` and `Wl` (both row-major, stride LDS_LD).  Returns (uniformly) the
 // 1-based index of the first pivot that is not positive and finite, else 0.
 //
-// Thread (r = tid%64, q = tid/64) keeps row r, columns q, q+4, ..., q+60 of
-// both S and W in registers.  Column k is finished by the wave that owns it
-// (q == k%4): it takes the pivot from lane k, scales its column and publishes
-// it through LDS; one barrier per column; every thread then applies the
-// rank-1 update to its part of the trailing matrix.  The rows of W follow by
-// forward substitution on the identity, which only needs row k of W inside
-// the same wave (cross-lane reads, no barrier).
+// Thread (r = tid%64, q = tid/64) keeps row r, columns 16q .. 16q+15 of both
+// S and W in registers.  Column k is finished by wave k/16: it takes the pivot
+// from lane k, scales its column and publishes it through LDS; one barrier per
+// column; every thread then applies the rank-1 update to its part of the
+// trailing matrix.  The rows of W follow by forward substitution on the
+// identity, which only needs row k of W inside the same wave (cross-lane
+// reads, no barrier).  The 16 columns of a wave are walked by an unrolled
+// loop so that every register index is static.
 __device__ __forceinline__ double rd_lane(double x, int lane) {
   int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
   int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
@@ -222,47 +223,56 @@ __device__ int chol_inv_tile(double* S, double* Wl, double* colbuf /* [2][64] */
   double s[16], w[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
-    s[m] = S[r * LDS_LD + q + 4 * m];
-    w[m] = (r == q + 4 * m) ? 1.0 : 0.0;
+    s[m] = S[r * LDS_LD + 16 * q + m];
+    w[m] = (r == 16 * q + m) ? 1.0 : 0.0;
   }
   if (tid == 0) *fail_sh = 0x7fffffff;  // "no failure"; lowered by atomicMin below
   int fail = 0;
-  for (int k = 0; k < 64; ++k) {
-    const int mk = k >> 2;
-    double* col = colbuf + (k & 1) * 64;
-    if (q == (k & 3)) {
-      double smk = 0.0;
-#pragma unroll
-      for (int m = 0; m < 16; ++m) smk = (m == mk) ? s[m] : smk;
-      const double d = rd_lane(smk, k);
-      const bool ok = (d > 0.0) && (d <= 1.7976931348623157e308);
-      if (!ok && fail == 0) fail = k + 1;
-      const double sq = sqrt(d);
-      const double rinv = 1.0 / sq;
-      const double lv = (r > k) ? smk * rinv : ((r == k) ? sq : 0.0);
-#pragma unroll
-      for (int m = 0; m < 16; ++m) s[m] = (m == mk) ? lv : s[m];
-      col[r] = lv;
-      if (r == 0) pivbuf[k & 1] = rinv;
-    }
-    __syncthreads();
-    const double lr = col[r];
-    const double rinv = pivbuf[k & 1];
-    // trailing update of S (columns c > k held by this thread)
+  for (int qo = 0; qo < 4; ++qo) {  // owner wave of columns 16qo .. 16qo+15
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-      if (q + 4 * m > k) s[m] -= lr * col[q + 4 * m];
-    }
-    // W: finish row k (scale by 1/L_kk), then eliminate it from the rows below
-    if (r == k) {
+      const int k = 16 * qo + m;
+      double* col = colbuf + (k & 1) * 64;
+      if (q == qo) {
+        const double d = rd_lane(s[m], k);
+        const bool ok = (d > 0.0) && (d <= 1.7976931348623157e308);
+        if (!ok && fail == 0) fail = k + 1;
+        const double sq = sqrt(d);
+        const double rinv = 1.0 / sq;
+        const double lv = (r > k) ? s[m] * rinv : ((r == k) ? sq : 0.0);
+        s[m] = lv;
+        col[r] = lv;
+        if (r == 0) pivbuf[k & 1] = rinv;
+      }
+      __syncthreads();
+      const double lr = col[r];
+      const double rinv = pivbuf[k & 1];
+      // trailing update of S: columns c = 16q + mm > k
+      if (q > qo) {
 #pragma unroll
-      for (int m = 0; m < 16; ++m) w[m] *= rinv;
-    }
+        for (int mm = 0; mm < 16; ++mm) s[mm] -= lr * col[16 * q + mm];
+      } else if (q == qo) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      if (4 * m <= k) {  // columns q + 4m <= k can be nonzero in row k
-        const double wk = rd_lane(w[m], k);
-        if (r > k) w[m] -= lr * wk;
+        for (int mm = m + 1; mm < 16; ++mm) s[mm] -= lr * col[16 * q + mm];
+      }
+      // W: finish row k (scale by 1/L_kk), then eliminate it from the rows below;
+      // columns c = 16q + mm <= k can be nonzero in row k
+      if (r == k) {
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) w[mm] *= rinv;
+      }
+      if (q < qo) {
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) {
+          const double wk = rd_lane(w[mm], k);
+          if (r > k) w[mm] -= lr * wk;
+        }
+      } else if (q == qo) {
+#pragma unroll
+        for (int mm = 0; mm <= m; ++mm) {
+          const double wk = rd_lane(w[mm], k);
+          if (r > k) w[mm] -= lr * wk;
+        }
       }
     }
   }
@@ -270,7 +280,7 @@ __device__ int chol_inv_tile(double* S, double* Wl, double* colbuf /* [2][64] */
   // write back L and W (lower, zeros above)
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
-    const int c = q + 4 * m;
+    const int c = 16 * q + m;
     S[r * LDS_LD + c] = (c <= r) ? s[m] : 0.0;
     Wl[r * LDS_LD + c] = (c <= r) ? w[m] : 0.0;
   }
@@ -279,26 +289,36 @@ __device__ int chol_inv_tile(double* S, double* Wl, double* colbuf /* [2][64] */
   return f == 0x7fffffff ? 0 : f;
 }
 
-// In-LDS inverse of a lower-triangular 64 x 64 tile by forward substitution
-// on the identity: thread (r, q) keeps row r, columns q + 4m of the inverse;
-// row k is finished (scaled by 1/L_kk) by lane k of every wave and then
-// eliminated from the rows below with cross-lane reads only.
+// In-LDS inverse of a lower-triangular 64 x 64 tile by forward substitution on
+// the identity: thread (r, q) keeps row r, columns 16q .. 16q+15 of the
+// inverse; row k is finished (scaled by 1/L_kk) by lane k of every wave and
+// then eliminated from the rows below with cross-lane reads only.
 __device__ __forceinline__ void trinv_tile(const double* S, double* w, int tid) {
   const int r = tid & 63, q = tid >> 6;
 #pragma unroll
-  for (int m = 0; m < 16; ++m) w[m] = (r == q + 4 * m) ? 1.0 : 0.0;
-  for (int k = 0; k < 64; ++k) {
-    const double lr = S[r * LDS_LD + k];
-    const double inv = 1.0 / S[k * LDS_LD + k];
-    if (r == k) {
-#pragma unroll
-      for (int m = 0; m < 16; ++m) w[m] *= inv;
-    }
+  for (int m = 0; m < 16; ++m) w[m] = (r == 16 * q + m) ? 1.0 : 0.0;
+  for (int qo = 0; qo < 4; ++qo) {
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-      if (4 * m <= k) {
-        const double wk = rd_lane(w[m], k);
-        if (r > k) w[m] -= lr * wk;
+      const int k = 16 * qo + m;
+      const double lr = S[r * LDS_LD + k];
+      const double inv = 1.0 / S[k * LDS_LD + k];
+      if (r == k) {
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) w[mm] *= inv;
+      }
+      if (q < qo) {
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) {
+          const double wk = rd_lane(w[mm], k);
+          if (r > k) w[mm] -= lr * wk;
+        }
+      } else if (q == qo) {
+#pragma unroll
+        for (int mm = 0; mm <= m; ++mm) {
+          const double wk = rd_lane(w[mm], k);
+          if (r > k) w[mm] -= lr * wk;
+        }
       }
     }
   }

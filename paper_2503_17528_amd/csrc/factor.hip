@@ -235,6 +235,13 @@ __host__ __device__ int ksources(const FactorParams& p, const Task& t, int kk, K
   return 0;
 }
 
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uni64(long long v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(unsigned)(v & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 // Block until flags are set (thread 0 polls); returns false on abort.
 __device__ __forceinline__ bool wait_ready(const FactorParams& p, const int* f1, const int* f2, Shared& sh, int tid) {
   if (tid == 0) {
@@ -244,7 +251,28 @@ __device__ __forceinline__ bool wait_ready(const FactorParams& p, const int* f1,
     sh.ok = ok ? 1 : 0;
   }
   __syncthreads();
-  return sh.ok != 0;
+  return uni(sh.ok) != 0;
+}
+
+// Thread 0: extend the run of consecutive final k tiles starting at `from`
+// without blocking; one acquire fence covers every tile it adds.
+__device__ __forceinline__ int extend_ready(const FactorParams& p, const Task& t, int from, int nk) {
+  int upto = from;
+  while (upto < nk) {
+    KSrc s2;
+    ksources(p, t, upto, &s2);
+    if (flag_set(s2.fa) && flag_set(s2.fb)) ++upto; else break;
+  }
+  if (upto > from) acquire_fence();
+  return upto;
+}
+
+// Publish a finished tile: every wave's stores are complete in L2 before the
+// barrier; one agent-scope release then writes the XCD's L2 back and sets the flag.
+__device__ __forceinline__ void publish(int* flag, int tid) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
@@ -253,10 +281,10 @@ __global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
   for (;;) {
     if (tid == 0) sh.ticket = (long long)atomicAdd((unsigned long long*)p.ctl, 1ULL);
     __syncthreads();
-    const long long tk = sh.ticket;
-    __syncthreads();
+    const long long tk = uni64(sh.ticket);
     if (tk >= p.ntasks) break;
-    const Task t = decode(p, tk);
+    Task t = decode(p, tk);
+    t.type = uni(t.type); t.i = uni(t.i); t.r = uni(t.r); t.c = uni(t.c);
     const int T = p.T, b = p.b, a = p.a;
     const int64_t bb = (int64_t)b * b, ab = (int64_t)a * b;
 
@@ -335,37 +363,38 @@ __global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
       }
     }
 
-    // ---- left-looking accumulation: acc += sum_k A_k B_k^T  (acc holds -(A - sum))
-    const int nk = ksources(p, t, -1, nullptr);
-    int ready_upto = 0;
-    for (int kk = 0; kk < nk; ++kk) {
-      KSrc s;
-      ksources(p, t, kk, &s);
-      if (kk >= ready_upto) {
-        // wait for this k tile, then take every following k tile that is already final
-        if (tid == 0) {
-          bool ok = spin_wait(s.fa, p.ctl + 2, p.spin_limit) && spin_wait(s.fb, p.ctl + 2, p.spin_limit);
-          int upto = kk + 1;
-          while (ok && upto < nk) {
-            KSrc s2;
-            ksources(p, t, upto, &s2);
-            if (flag_set(s2.fa) && flag_set(s2.fb)) ++upto; else break;
-          }
-          acquire_fence();
-          sh.ok = ok ? upto : -1;
-        }
-        __syncthreads();
-        if (sh.ok < 0) break;
-        ready_upto = sh.ok;
-      }
+    // ---- left-looking accumulation, software pipelined: the next k tile is
+    // loaded into registers while the MFMAs of the current one run.
+    const int nk = uni(ksources(p, t, -1, nullptr));
+    bool aborted = false;
+    if (nk > 0) {
+      int upto = 0;
+      KSrc s0;
+      ksources(p, t, 0, &s0);
+      if (!wait_ready(p, s0.fa, s0.fb, sh, tid)) aborted = true;
+      upto = 1;
       Stage ra, rb;
-      stage_load(ra, s.a, tid);
-      stage_load(rb, s.b, tid);
-      __syncthreads();  // previous k tile consumed
-      stage_store(ra, sh.As, false, tid);
-      stage_store(rb, sh.Bs, false, tid);
-      __syncthreads();
-      mma_tile(acc, sh.As, sh.Bs, tid);
+      stage_load(ra, s0.a, tid);
+      stage_load(rb, s0.b, tid);
+      for (int kk = 0; kk < nk && !aborted; ++kk) {
+        __syncthreads();  // previous MFMAs are done with the LDS operands
+        stage_store(ra, sh.As, false, tid);
+        stage_store(rb, sh.Bs, false, tid);
+        if (tid == 0) sh.ok = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, t, kk + 1, nk) : upto;
+        __syncthreads();
+        upto = uni(sh.ok) > upto ? uni(sh.ok) : upto;
+        if (kk + 1 < nk) {
+          KSrc sn;
+          ksources(p, t, kk + 1, &sn);
+          if (kk + 1 >= upto) {  // not final yet: block (rare once the pipeline is primed)
+            if (!wait_ready(p, sn.fa, sn.fb, sh, tid)) { aborted = true; }
+            upto = kk + 2;
+          }
+          stage_load(ra, sn.a, tid);
+          stage_load(rb, sn.b, tid);
+        }
+        mma_tile(acc, sh.As, sh.Bs, tid);
+      }
     }
     __syncthreads();
 
@@ -373,12 +402,15 @@ __global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
     if (t.type == T_TUPD) {
       acc_store(acc, out, 64, 64, 64, 1.0, 0, tid);
     } else if (is_diag) {
-      // LDS: As <- A - sum (negate back), factor + invert in place
-      acc_to_lds(acc, sh.As, tid);
+      // LDS: As <- A - sum (the accumulator holds its negative); factor + invert in place
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) sh.As[tile_row(tid, bi, j) * LDS_LD + tile_col(tid, bj)] = -acc.v[bi][bj][j];
       __syncthreads();
-      for (int e = tid; e < 64 * 64; e += NT) sh.As[(e >> 6) * LDS_LD + (e & 63)] *= -1.0;
-      __syncthreads();
-      const int f = chol_inv_tile(sh.As, sh.Bs, sh.colbuf, sh.pivbuf, &sh.fail, tid);
+      const int f = uni(chol_inv_tile(sh.As, sh.Bs, sh.colbuf, sh.pivbuf, &sh.fail, tid));
       if (f != 0 && f <= rows && tid == 0) {
         const long long row0 = (t.type == T_DIAG) ? (long long)t.i * b + (long long)t.c * 64
                                                   : (long long)p.n * b + (long long)t.c * 64;
@@ -396,9 +428,9 @@ __global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
                                             : p.Wd + ((int64_t)t.i * T + t.c) * 4096;
       const int* fdiag = (t.type == T_TIPO) ? p.flags + fl_tip(p, t.c, t.c) : p.flags + fl_D(p, t.i, t.c, t.c);
       wait_ready(p, fdiag, fdiag, sh, tid);
-      acc_to_lds(acc, sh.As, tid);
       Stage rw;
       stage_load(rw, OpTile{Wc, 64, 64, 64, false}, tid);
+      acc_to_lds(acc, sh.As, tid);
       stage_store(rw, sh.Bs, false, tid);
       __syncthreads();
       Acc x;
@@ -416,7 +448,7 @@ __global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
         }
       }
     }
-    publish_flag(my_flag, tid);
+    publish(my_flag, tid);
   }
 }
 

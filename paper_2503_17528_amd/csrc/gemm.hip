@@ -231,7 +231,7 @@ __global__ __launch_bounds__(NT) void trinv_diag_tiles_kernel(const double* L, i
   if (r < ext) {
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) {
-      const int c = q + 4 * mm;
+      const int c = 16 * q + mm;
       if (c < ext) Wt[(int64_t)r * ldW + c] = (c <= r) ? w[mm] : 0.0;
     }
   }

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(NT) void tile_inverses_kernel(const double* L, int6
   double* Wt = Wc + (blk * T + t) * 4096;
 #pragma unroll
   for (int mm = 0; mm < 16; ++mm) {
-    const int c = q + 4 * mm;
+    const int c = 16 * q + mm;
     Wt[r * 64 + c] = (c <= r) ? w[mm] : 0.0;
   }
 }
