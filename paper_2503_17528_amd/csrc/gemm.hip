@@ -12,129 +12,247 @@
 
 namespace bta {
 
-__device__ __forceinline__ void seg_krange(const GSeg& s, int tm, int tn, int& k0, int& k1) {
-  k0 = 0;
-  k1 = s.K;
-  switch (s.tri) {
-    case TRI_K_GE_COL: k0 = tn * 64; break;
-    case TRI_K_GE_ROW: k0 = tm * 64; break;
-    case TRI_K_LE_ROW: k1 = min(s.K, (tm + 1) * 64); break;
-    case TRI_K_LE_COL: k1 = min(s.K, (tn + 1) * 64); break;
-    default: break;
+// Tile configuration: a workgroup of 4 waves (2 x 2) computes a
+// (32*WM) x (32*WN) tile; each wave WM x WN MFMA blocks of 16 x 16; k is staged
+// through LDS in chunks of BK (row stride BK + 2 doubles: consecutive rows
+// shift by 4 banks and rows stay 16-byte aligned).
+template <int WM, int WN, int BK>
+struct GemmCfg {
+  static constexpr int TM = 32 * WM, TN = 32 * WN, LD = BK + 2;
+  static constexpr int EA = TM * BK / NT, EB = TN * BK / NT;  // doubles staged per thread
+  static_assert(EA == 16 && EB == 16, "staging assumes 16 doubles per thread per operand");
+};
+
+template <int TM, int BK>
+struct Chunk {
+  double v[16];
+};
+
+// Load one TM x BK operand chunk (element (m, k) = trans ? p[k*ld + m] : p[m*ld + k];
+// zero outside mext x kext) into registers.
+template <int TM, int BK>
+__device__ __forceinline__ void chunk_load(Chunk<TM, BK>& c, const double* p, int64_t ld, int trans, int mext, int kext,
+                                           int tid) {
+  if (!trans) {
+    constexpr int TPR = BK / 16;  // threads per row
+    const int m = tid / TPR, k0 = (tid % TPR) * 16;
+    const double* src = p + (int64_t)m * ld + k0;
+    const bool row_ok = m < mext;
+    if (row_ok && k0 + 16 <= kext && ((ld & 1) == 0) && ((((uintptr_t)src) & 15) == 0)) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        d2v x = *reinterpret_cast<const d2v*>(src + 2 * j);
+        c.v[2 * j] = x[0];
+        c.v[2 * j + 1] = x[1];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) c.v[j] = (row_ok && k0 + j < kext) ? src[j] : 0.0;
+    }
+  } else {
+    constexpr int TPK = TM / 16;  // threads per k row
+    const int k = tid / TPK, m0 = (tid % TPK) * 16;
+    const double* src = p + (int64_t)k * ld + m0;
+    const bool k_ok = k < kext;
+    if (k_ok && m0 + 16 <= mext && ((ld & 1) == 0) && ((((uintptr_t)src) & 15) == 0)) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        d2v x = *reinterpret_cast<const d2v*>(src + 2 * j);
+        c.v[2 * j] = x[0];
+        c.v[2 * j + 1] = x[1];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) c.v[j] = (k_ok && m0 + j < mext) ? src[j] : 0.0;
+    }
   }
-  if (k0 > k1) k0 = k1;
 }
 
-__device__ __forceinline__ OpTile op_tile(const double* base, int64_t ld, int trans, int m0, int mext, int k, int kext) {
-  if (!trans) return OpTile{base + (int64_t)m0 * ld + k, ld, mext, kext, false};
-  return OpTile{base + (int64_t)k * ld + m0, ld, mext, kext, true};
+template <int TM, int BK>
+__device__ __forceinline__ void chunk_store(const Chunk<TM, BK>& c, double* lds, int trans, int tid) {
+  constexpr int LD = BK + 2;
+  if (!trans) {
+    constexpr int TPR = BK / 16;
+    const int m = tid / TPR, k0 = (tid % TPR) * 16;
+    double* dst = lds + m * LD + k0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) *reinterpret_cast<d2v*>(dst + 2 * j) = d2v{c.v[2 * j], c.v[2 * j + 1]};
+  } else {
+    constexpr int TPK = TM / 16;
+    const int k = tid / TPK, m0 = (tid % TPK) * 16;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) lds[(m0 + j) * LD + k] = c.v[j];
+  }
 }
 
-__global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs args) {
-  __shared__ double As[TS * LDS_LD];
-  __shared__ double Bs[TS * LDS_LD];
-  const int tid = threadIdx.x;
-  const long long t = blockIdx.x;
+template <int WM, int WN>
+struct AccT {
+  d4 v[WM][WN];
+};
+
+// acc += A_lds B_lds^T over one BK chunk (k permuted within each 16-wide group
+// so that every lane reads 4 consecutive k with two 16-byte LDS reads).
+template <int WM, int WN, int BK>
+__device__ __forceinline__ void chunk_mma(AccT<WM, WN>& acc, const double* As, const double* Bs, int tid) {
+  constexpr int LD = BK + 2;
+  const int w = tid >> 6, lane = tid & 63;
+  const int r0 = 16 * WM * (w >> 1) + (lane & 15);
+  const int c0 = 16 * WN * (w & 1) + (lane & 15);
+  const int kl = (lane >> 4) * 4;
+#pragma unroll
+  for (int kg = 0; kg < BK / 16; ++kg) {
+    d4 a[WM], b[WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      const double* pa = As + (r0 + 16 * i) * LD + kg * 16 + kl;
+      const d2v x0 = *reinterpret_cast<const d2v*>(pa);
+      const d2v x1 = *reinterpret_cast<const d2v*>(pa + 2);
+      a[i] = d4{x0[0], x0[1], x1[0], x1[1]};
+    }
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const double* pb = Bs + (c0 + 16 * j) * LD + kg * 16 + kl;
+      const d2v x0 = *reinterpret_cast<const d2v*>(pb);
+      const d2v x1 = *reinterpret_cast<const d2v*>(pb + 2);
+      b[j] = d4{x0[0], x0[1], x1[0], x1[1]};
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc.v[i][j] = mfma16(a[i][s], b[j][s], acc.v[i][j]);
+  }
+}
+
+template <int WM, int WN, int BK>
+__device__ __forceinline__ void gemm_tile_body(const GemmArgs& args, long long t, int tid, double* As, double* Bs) {
+  using C = GemmCfg<WM, WN, BK>;
+  constexpr int TM = C::TM, TN = C::TN;
   int j = 0;
   while (j + 1 < args.nprob && t >= args.p[j + 1].tile_begin) ++j;
   const GProb& P = args.p[j];
   const long long local = t - P.tile_begin;
   const int batch = (int)(local / P.tiles_per_batch);
-  int tile = (int)(local - (long long)batch * P.tiles_per_batch);
+  const int tile = (int)(local - (long long)batch * P.tiles_per_batch);
   const int b0 = batch / P.nb1, b1 = batch - b0 * P.nb1;
   int tm, tn;
   if (P.lower_tiles) {
-    // tile -> (tm, tn), tm >= tn, row by row
-    tm = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
-    while ((tm + 1) * (tm + 2) / 2 <= tile) ++tm;
-    while (tm * (tm + 1) / 2 > tile) --tm;
-    tn = tile - tm * (tm + 1) / 2;
+    // tile -> (tm, tn) over the tiles that touch the lower triangle, row by row:
+    // row tm holds tiles tn = 0 .. floor((tm*TM + TM - 1) / TN)
+    tm = 0;
+    int rem = tile;
+    for (;;) {
+      const int w = min(P.ntn, (tm * TM + TM - 1) / TN + 1);
+      if (rem < w) break;
+      rem -= w;
+      ++tm;
+    }
+    tn = rem;
   } else {
     tm = tile / P.ntn;
     tn = tile - tm * P.ntn;
   }
-  const int mext = min(64, P.M - tm * 64), next = min(64, P.N - tn * 64);
+  const int m0 = tm * TM, n0 = tn * TN;
+  const int mext = min(TM, P.M - m0), next = min(TN, P.N - n0);
 
-  // flattened k tiles over the segments
-  int kbeg[2], kend[2], nk[2];
-  const double* Ab[2];
-  const double* Bb[2];
-  for (int s = 0; s < 2; ++s) {
-    nk[s] = 0;
-    if (s < P.nseg) {
-      seg_krange(P.seg[s], tm, tn, kbeg[s], kend[s]);
-      nk[s] = (kend[s] - kbeg[s] + 63) / 64;
-      Ab[s] = P.seg[s].A + b0 * P.seg[s].sA0 + b1 * P.seg[s].sA1;
-      Bb[s] = P.seg[s].B + b0 * P.seg[s].sB0 + b1 * P.seg[s].sB1;
+  // k ranges of the segments (triangular operands clip them)
+  int kbeg[2] = {0, 0}, kend[2] = {0, 0}, nk[2] = {0, 0};
+  const double* Ab[2] = {nullptr, nullptr};
+  const double* Bb[2] = {nullptr, nullptr};
+  for (int s = 0; s < P.nseg; ++s) {
+    const GSeg& g = P.seg[s];
+    int k0 = 0, k1 = g.K;
+    switch (g.tri) {
+      case TRI_K_GE_COL: k0 = n0; break;
+      case TRI_K_GE_ROW: k0 = m0; break;
+      case TRI_K_LE_ROW: k1 = min(g.K, m0 + TM); break;
+      case TRI_K_LE_COL: k1 = min(g.K, n0 + TN); break;
+      default: break;
     }
+    k0 = (k0 / BK) * BK;
+    if (k0 > k1) k0 = k1;
+    kbeg[s] = k0;
+    kend[s] = k1;
+    nk[s] = (k1 - k0 + BK - 1) / BK;
+    Ab[s] = g.A + b0 * g.sA0 + b1 * g.sA1;
+    Bb[s] = g.B + b0 * g.sB0 + b1 * g.sB1;
   }
   const int total = nk[0] + nk[1];
 
-  Acc acc;
-  acc_zero(acc);
-  Stage ra, rb;
+  AccT<WM, WN> acc;
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int jj = 0; jj < WN; ++jj) acc.v[i][jj] = d4{0.0, 0.0, 0.0, 0.0};
+  Chunk<TM, BK> ra;
+  Chunk<TN, BK> rb;
   auto load = [&](int kk) {
     const int s = kk < nk[0] ? 0 : 1;
     const int q = s == 0 ? kk : kk - nk[0];
-    const int k = kbeg[s] + q * 64;
-    const int kext = min(64, kend[s] - k);
+    const int k = kbeg[s] + q * BK;
+    const int kext = min(BK, kend[s] - k);
     const GSeg& g = P.seg[s];
-    stage_load(ra, op_tile(Ab[s], g.lda, g.at, tm * 64, mext, k, kext), tid);
-    stage_load(rb, op_tile(Bb[s], g.ldb, g.bt, tn * 64, next, k, kext), tid);
+    const double* pa = g.at ? Ab[s] + (int64_t)k * g.lda + m0 : Ab[s] + (int64_t)m0 * g.lda + k;
+    const double* pb = g.bt ? Bb[s] + (int64_t)k * g.ldb + n0 : Bb[s] + (int64_t)n0 * g.ldb + k;
+    chunk_load<TM, BK>(ra, pa, g.lda, g.at, mext, kext, tid);
+    chunk_load<TN, BK>(rb, pb, g.ldb, g.bt, next, kext, tid);
   };
   if (total > 0) load(0);
   for (int kk = 0; kk < total; ++kk) {
     const int s = kk < nk[0] ? 0 : 1;
     __syncthreads();
-    stage_store(ra, As, P.seg[s].at != 0, tid);
-    stage_store(rb, Bs, P.seg[s].bt != 0, tid);
+    chunk_store<TM, BK>(ra, As, P.seg[s].at, tid);
+    chunk_store<TN, BK>(rb, Bs, P.seg[s].bt, tid);
     __syncthreads();
     if (kk + 1 < total) load(kk + 1);
-    mma_tile(acc, As, Bs, tid);
+    chunk_mma<WM, WN, BK>(acc, As, Bs, tid);
   }
 
   // epilogue: final values first (Cin may alias Cout), then the stores
-  double* C = P.Cout + b0 * P.sC0 + b1 * P.sC1 + (int64_t)tm * 64 * P.ldc + tn * 64;
-  const double* Ci = P.Cin ? P.Cin + b0 * P.sC0 + b1 * P.sC1 + (int64_t)tm * 64 * P.ldc + tn * 64 : nullptr;
-  const bool diag_tile = (tm == tn);
+  const int w = tid >> 6, lane = tid & 63;
+  const int rw = 16 * WM * (w >> 1), cw = 16 * WN * (w & 1);
+  const int64_t coff = b0 * P.sC0 + b1 * P.sC1;
+  double* Cb = P.Cout + coff;
+  const double* Cib = P.Cin ? P.Cin + coff : nullptr;
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < WM; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < WN; ++bj)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int r = tile_row(tid, bi, e), c = tile_col(tid, bj);
+        const int r = rw + 16 * bi + acc_row(lane, e), c = cw + 16 * bj + acc_col(lane);
+        const int gr = m0 + r, gc = n0 + c;
         double v = P.alpha * acc.v[bi][bj][e];
-        const bool live = r < mext && c < next && !(P.store != ST_FULL && diag_tile && c > r);
-        if (live && P.beta != 0.0) v += P.beta * Ci[(int64_t)r * P.ldc + c];
+        const bool live = r < mext && c < next && !(P.store != ST_FULL && gc > gr);
+        if (live && P.beta != 0.0) v += P.beta * Cib[(int64_t)gr * P.ldc + gc];
         acc.v[bi][bj][e] = v;
       }
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < WM; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < WN; ++bj)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int r = tile_row(tid, bi, e), c = tile_col(tid, bj);
+        const int r = rw + 16 * bi + acc_row(lane, e), c = cw + 16 * bj + acc_col(lane);
+        const int gr = m0 + r, gc = n0 + c;
         if (r >= mext || c >= next) continue;
-        if (P.store != ST_FULL && diag_tile && c > r) continue;
-        C[(int64_t)r * P.ldc + c] = acc.v[bi][bj][e];
+        if (P.store != ST_FULL && gc > gr) continue;
+        Cb[(int64_t)gr * P.ldc + gc] = acc.v[bi][bj][e];
+        if (P.store == ST_LOWER_MIRROR && gc < gr) Cb[(int64_t)gc * P.ldc + gr] = acc.v[bi][bj][e];
       }
-  if (P.store == ST_LOWER_MIRROR) {
-    // mirror into the transposed position (c, r) of the global matrix
-    double* Ct = P.Cout + b0 * P.sC0 + b1 * P.sC1 + (int64_t)tn * 64 * P.ldc + tm * 64;
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = tile_row(tid, bi, e), c = tile_col(tid, bj);
-          if (r >= mext || c >= next) continue;
-          if (diag_tile && c >= r) continue;
-          Ct[(int64_t)c * P.ldc + r] = acc.v[bi][bj][e];
-        }
-  }
+}
+
+__global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs args) {
+  __shared__ double As[64 * 66];
+  __shared__ double Bs[64 * 66];
+  gemm_tile_body<2, 2, 64>(args, blockIdx.x, threadIdx.x, As, Bs);
+}
+
+__global__ __launch_bounds__(NT, 1) void gemm128_kernel(GemmArgs args) {
+  __shared__ double As[128 * 34];
+  __shared__ double Bs[128 * 34];
+  gemm_tile_body<4, 4, 32>(args, blockIdx.x, threadIdx.x, As, Bs);
 }
 
 thread_local DryRecorder* g_dry = nullptr;
@@ -179,30 +297,53 @@ static void record_gemm(const GProb& p) {
     }
 }
 
-hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream) {
-  if (g_dry) {
-    for (int i = 0; i < nprob; ++i)
-      if (probs[i].M > 0 && probs[i].N > 0) record_gemm(probs[i]);
-    return hipSuccess;
-  }
-  GemmArgs args{};
+static long long plan_tiles(GemmArgs& args, GProb* probs, int nprob, int TM, int TN) {
   args.nprob = 0;
   long long total = 0;
   for (int i = 0; i < nprob; ++i) {
     GProb p = probs[i];
     if (p.M <= 0 || p.N <= 0 || p.nb0 <= 0 || p.nb1 <= 0) continue;
-    p.ntm = (p.M + 63) / 64;
-    p.ntn = (p.N + 63) / 64;
-    p.tiles_per_batch = p.lower_tiles ? p.ntm * (p.ntm + 1) / 2 : p.ntm * p.ntn;
+    p.ntm = (p.M + TM - 1) / TM;
+    p.ntn = (p.N + TN - 1) / TN;
+    if (p.lower_tiles) {
+      long long cnt = 0;
+      for (int tm = 0; tm < p.ntm; ++tm) cnt += std::min(p.ntn, (tm * TM + TM - 1) / TN + 1);
+      p.tiles_per_batch = (int)cnt;
+    } else {
+      p.tiles_per_batch = p.ntm * p.ntn;
+    }
     p.tile_begin = total;
     total += (long long)p.tiles_per_batch * p.nb0 * p.nb1;
     args.p[args.nprob++] = p;
     if (args.nprob == GEMM_MAX_PROBS) break;
   }
   args.ntiles = total;
-  if (total == 0) return hipSuccess;
+  return total;
+}
+
+hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream) {
+  if (g_dry) {
+    for (int i = 0; i < nprob; ++i)
+      if (probs[i].M > 0 && probs[i].N > 0) record_gemm(probs[i]);
+    return hipSuccess;
+  }
+  // 128 x 128 tiles when they alone give at least ~one tile per CU and every
+  // problem is at least 128 on both sides; 64 x 64 tiles otherwise.
+  GemmArgs big{}, small{};
+  const long long t128 = plan_tiles(big, probs, nprob, 128, 128);
+  bool use_big = t128 >= 200;
+  for (int i = 0; i < big.nprob; ++i)
+    if (big.p[i].M < 128 && big.p[i].N < 128) use_big = false;
+  if (use_big) {
+    timing_mark(KT_GEMM, true, stream);
+    hipLaunchKernelGGL(gemm128_kernel, dim3((unsigned)t128), dim3(NT), 0, stream, big);
+    timing_mark(KT_GEMM, false, stream);
+    return hipGetLastError();
+  }
+  const long long t64 = plan_tiles(small, probs, nprob, 64, 64);
+  if (t64 == 0) return hipSuccess;
   timing_mark(KT_GEMM, true, stream);
-  hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)total), dim3(NT), 0, stream, args);
+  hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)t64), dim3(NT), 0, stream, small);
   timing_mark(KT_GEMM, false, stream);
   return hipGetLastError();
 }
