@@ -113,6 +113,30 @@ BTA_API int bta_solve(int64_t n, int64_t b, int64_t a,
 BTA_API int bta_logdet(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT,
                double* d_out, void* work, size_t work_bytes, bta_stream_t stream);
 
+/*
+ * f = log det A + sum_j y_j^T x_j, where x = A^{-1} y comes from bta_solve
+ * (the objective log det Q + y^T Q^{-1} y of Gaussian models).  y and x are
+ * [N][nrhs] row-major device arrays (they may be the same array); d_out is a
+ * device double.  Workspace: bta_workspace_bytes(BTA_OP_LOGDET, ...).
+ */
+BTA_API int bta_logdet_quad(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT,
+                    const double* y, const double* x, int64_t nrhs, double* d_out,
+                    void* work, size_t work_bytes, bta_stream_t stream);
+
+/*
+ * Gradient of f = log det Q + sum_j y_j^T Q^{-1} y_j with respect to the block
+ * arrays, from the selected inverse X (bta_selinv) and x = Q^{-1} y:
+ * G = Sigma - sum_j x_j x_j^T on the BTA pattern, returned as
+ *   GD = s*G_D, GB = 2s*G_B, GR = 2s*G_R, GT = s*G_T
+ * (the lower and arrow blocks also stand at their mirrored positions of Q),
+ * and gy = 2s*x when gy is not NULL.  s = *d_scale (device double), or 1 when
+ * d_scale is NULL.  Elementwise: G* may alias X* exactly (in place).
+ */
+BTA_API int bta_grad_logdet_quad(int64_t n, int64_t b, int64_t a,
+                    const double* XD, const double* XB, const double* XR, const double* XT,
+                    const double* x, int64_t nrhs, const double* d_scale,
+                    double* GD, double* GB, double* GR, double* GT, double* gy, bta_stream_t stream);
+
 /* Static text for a status code. */
 BTA_API const char* bta_status_string(int status);
 

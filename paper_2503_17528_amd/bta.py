@@ -23,7 +23,7 @@ BTA_OK, BTA_EINVAL, BTA_ENOTPD, BTA_EHIP, BTA_ENOTSUP = 0, 1, 2, 3, 4
 BTA_OP_FACTOR, BTA_OP_SELINV, BTA_OP_SOLVE, BTA_OP_LOGDET = 0, 1, 2, 3
 
 EXPORTED = ("bta_workspace_bytes", "bta_factor", "bta_selinv", "bta_solve", "bta_logdet",
-            "bta_status_string", "bta_last_error")
+            "bta_logdet_quad", "bta_grad_logdet_quad", "bta_status_string", "bta_last_error")
 
 _lib = None
 
@@ -59,6 +59,10 @@ def lib() -> ctypes.CDLL:
     L.bta_solve.restype = ctypes.c_int
     L.bta_logdet.argtypes = [i64, i64, i64, vp, vp, vp, vp, sz, vp]
     L.bta_logdet.restype = ctypes.c_int
+    L.bta_logdet_quad.argtypes = [i64, i64, i64, vp, vp, vp, vp, i64, vp, vp, sz, vp]
+    L.bta_logdet_quad.restype = ctypes.c_int
+    L.bta_grad_logdet_quad.argtypes = [i64, i64, i64] + [vp] * 5 + [i64, vp] + [vp] * 5 + [vp]
+    L.bta_grad_logdet_quad.restype = ctypes.c_int
     L.bta_status_string.argtypes = [ctypes.c_int]
     L.bta_status_string.restype = ctypes.c_char_p
     L.bta_last_error.argtypes = []
@@ -88,6 +92,14 @@ def bta_solve(n, b, a, LD, LB, LR, LT, rhs, nrhs, work, work_bytes, stream) -> i
 
 def bta_logdet(n, b, a, LD, LT, d_out, work, work_bytes, stream) -> int:
     return int(lib().bta_logdet(n, b, a, LD, LT, d_out, work, work_bytes, stream))
+
+
+def bta_logdet_quad(n, b, a, LD, LT, y, x, nrhs, d_out, work, work_bytes, stream) -> int:
+    return int(lib().bta_logdet_quad(n, b, a, LD, LT, y, x, nrhs, d_out, work, work_bytes, stream))
+
+
+def bta_grad_logdet_quad(n, b, a, XD, XB, XR, XT, x, nrhs, d_scale, GD, GB, GR, GT, gy, stream) -> int:
+    return int(lib().bta_grad_logdet_quad(n, b, a, XD, XB, XR, XT, x, nrhs, d_scale, GD, GB, GR, GT, gy, stream))
 
 
 def bta_status_string(status: int) -> str:
@@ -227,3 +239,52 @@ def logdet(LD, LT, work=None, stream=None):
     st = bta_logdet(n, b, a, _ptr(LD), _ptr(LT), out.data_ptr(), work.data_ptr(), nbytes, _stream(stream))
     _check(st, "bta_logdet")
     return out
+
+
+def logdet_quad(LD, LT, y, x, work=None, stream=None):
+    """log det A + sum(y * x) (x = A^{-1} y) as a 0-dim float64 device tensor."""
+    import torch
+
+    n, b = int(LD.shape[0]), int(LD.shape[1])
+    a = int(LT.shape[0]) if LT is not None else 0
+    N = n * b + a
+    y2 = y.reshape(N, -1)
+    x2 = x.reshape(N, -1)
+    nrhs = int(y2.shape[1])
+    _validate(y2, (N, nrhs), "y")
+    _validate(x2, (N, nrhs), "x")
+    out = torch.empty((), dtype=torch.float64, device=LD.device)
+    if work is None:
+        work, nbytes = workspace(BTA_OP_LOGDET, n, b, a, LD.device)
+    else:
+        nbytes = work.numel()
+    st = bta_logdet_quad(n, b, a, _ptr(LD), _ptr(LT), y2.data_ptr(), x2.data_ptr(), nrhs, out.data_ptr(),
+                         work.data_ptr(), nbytes, _stream(stream))
+    _check(st, "bta_logdet_quad")
+    return out
+
+
+def grad_logdet_quad(X, x, scale=None, out=None, want_gy=True, stream=None):
+    """Gradient blocks (GD, GB, GR, GT, gy) of log det Q + y^T Q^{-1} y from the
+    selected inverse X = (XD, XB, XR, XT) and x = Q^{-1} y.  ``scale`` is an
+    optional 0-dim device tensor multiplying every gradient; ``out`` may be X
+    itself (in place)."""
+    import torch
+
+    XD, XB, XR, XT = X
+    n, b, a = _dims(XD, XR, XT)
+    N = n * b + a
+    x2 = x.reshape(N, -1)
+    nrhs = int(x2.shape[1])
+    _validate(x2, (N, nrhs), "x")
+    if out is None:
+        out = tuple(torch.empty_like(t) for t in X)
+    GD, GB, GR, GT = out
+    gy = torch.empty_like(x2) if want_gy else None
+    if scale is not None:
+        _validate(scale, (), "scale")
+    st = bta_grad_logdet_quad(n, b, a, _ptr(XD), _ptr(XB), _ptr(XR), _ptr(XT), x2.data_ptr(), nrhs,
+                              _ptr(scale) if scale is not None else None, _ptr(GD), _ptr(GB), _ptr(GR), _ptr(GT),
+                              _ptr(gy), _stream(stream))
+    _check(st, "bta_grad_logdet_quad")
+    return GD, GB, GR, GT, (gy.reshape(x.shape) if gy is not None else None)

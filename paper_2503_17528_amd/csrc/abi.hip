@@ -175,6 +175,44 @@ int bta_logdet(int64_t n, int64_t b, int64_t a, const double* LD, const double* 
   return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_logdet launch");
 }
 
+int bta_logdet_quad(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT, const double* y, const double* x,
+                    int64_t nrhs, double* d_out, void* work, size_t work_bytes, bta_stream_t stream) {
+  if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
+  if (nrhs < 1 || nrhs > (1 << 20)) return fail(BTA_EINVAL, "invalid nrhs=%lld", (long long)nrhs);
+  const int64_t N = n * b + a;
+  const Arr arr[5] = {{LD, blk_bytes(n, b, b), "LD"}, {LT, blk_bytes(1, a, a), "LT"}, {y, blk_bytes(1, N, nrhs), "y"},
+                      {x, blk_bytes(1, N, nrhs), "x"}, {d_out, 8, "d_out"}};
+  const int pair[5] = {-1, -1, 3, 2, -1};  // y and x may coincide (f = logdet + y^T y)
+  int st = check_arrays(arr, 5, pair);
+  if (st) return st;
+  st = check_work(work, work_bytes, bta::logdet_work_bytes(n, b, a));
+  if (st) return st;
+  st = device_ok();
+  if (st) return st;
+  hipError_t e = bta::logdet_quad_launch(n, b, a, LD, LT, y, x, nrhs, d_out, work, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_logdet_quad launch");
+}
+
+int bta_grad_logdet_quad(int64_t n, int64_t b, int64_t a, const double* XD, const double* XB, const double* XR,
+                         const double* XT, const double* x, int64_t nrhs, const double* d_scale, double* GD, double* GB,
+                         double* GR, double* GT, double* gy, bta_stream_t stream) {
+  if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
+  if (nrhs < 1 || nrhs > (1 << 20)) return fail(BTA_EINVAL, "invalid nrhs=%lld", (long long)nrhs);
+  const int64_t N = n * b + a;
+  const Arr arr[11] = {{XD, blk_bytes(n, b, b), "XD"}, {XB, blk_bytes(n - 1, b, b), "XB"}, {XR, blk_bytes(n, a, b), "XR"},
+                       {XT, blk_bytes(1, a, a), "XT"}, {GD, blk_bytes(n, b, b), "GD"}, {GB, blk_bytes(n - 1, b, b), "GB"},
+                       {GR, blk_bytes(n, a, b), "GR"}, {GT, blk_bytes(1, a, a), "GT"}, {x, blk_bytes(1, N, nrhs), "x"},
+                       {d_scale, d_scale ? 8u : 0u, "d_scale"}, {gy, gy ? blk_bytes(1, N, nrhs) : 0u, "gy"}};
+  const int pair[11] = {4, 5, 6, 7, 0, 1, 2, 3, -1, -1, -1};
+  int st = check_arrays(arr, 11, pair);
+  if (st) return st;
+  st = device_ok();
+  if (st) return st;
+  hipError_t e = bta::grad_launch(n, b, a, XD, XB, XR, XT, x, nrhs, d_scale, GD, GB, GR, GT, gy,
+                                  reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_grad_logdet_quad launch");
+}
+
 const char* bta_status_string(int status) {
   switch (status) {
     case BTA_OK: return "BTA_OK";

@@ -81,6 +81,11 @@ hipError_t solve_launch(int64_t n, int64_t b, int64_t a, const double* LD, const
 size_t logdet_work_bytes(int64_t n, int64_t b, int64_t a);
 hipError_t logdet_launch(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT,
                          double* out, void* work, hipStream_t stream);
+hipError_t logdet_quad_launch(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT, const double* y,
+                              const double* x, int64_t nrhs, double* out, void* work, hipStream_t stream);
+hipError_t grad_launch(int64_t n, int64_t b, int64_t a, const double* XD, const double* XB, const double* XR,
+                       const double* XT, const double* x, int64_t nrhs, const double* scale, double* GD, double* GB,
+                       double* GR, double* GT, double* gy, hipStream_t stream);
 
 // ---------------------------------------------------------------- shared small kernels
 // Triangular inverse of 64 x 64 diagonal tiles: for batch index (blk, t),

@@ -45,7 +45,124 @@ __global__ __launch_bounds__(256) void logdet_final_kernel(const double* partial
   if (threadIdx.x == 0) *out = 2.0 * red[0];
 }
 
-size_t logdet_work_bytes(int64_t n, int64_t b, int64_t a) { return 8 * (size_t)(n + 1) + 256; }
+size_t logdet_work_bytes(int64_t n, int64_t b, int64_t a) { return 8 * (size_t)(n + 1 + 1024) + 256; }
+
+// ---------------------------------------------------------------- quadratic term and gradient
+
+// partial[blk] = sum over a fixed slice of the elementwise product y * x
+__global__ __launch_bounds__(256) void dot_partial_kernel(const double* y, const double* x, int64_t count, int nslices,
+                                                          double* partial) {
+  __shared__ double red[256];
+  const int64_t per = (count + nslices - 1) / nslices;
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = std::min<int64_t>(count, lo + per);
+  double s = 0.0;
+  for (int64_t k = lo + threadIdx.x; k < hi; k += 256) s += y[k] * x[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// out = 2 * sum(logs) + sum(dots), every partial summed in a fixed order
+__global__ __launch_bounds__(256) void logdet_quad_final_kernel(const double* plog, int64_t nlog, const double* pdot,
+                                                                int ndot, double* out) {
+  __shared__ double red[256];
+  double s = 0.0, t = 0.0;
+  for (int64_t k = threadIdx.x; k < nlog; k += 256) s += plog[k];
+  for (int64_t k = threadIdx.x; k < ndot; k += 256) t += pdot[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double ls = red[0];
+  __syncthreads();
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = 2.0 * ls + red[0];
+}
+
+hipError_t logdet_quad_launch(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT, const double* y,
+                              const double* x, int64_t nrhs, double* out, void* work, hipStream_t stream) {
+  double* plog = static_cast<double*>(work);
+  double* pdot = plog + (n + 1);
+  const int64_t nb = n + (a > 0 ? 1 : 0);
+  hipLaunchKernelGGL(logdet_partial_kernel, dim3((unsigned)nb), dim3(256), 0, stream, LD, LT, n, b, a, plog);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t count = (n * b + a) * nrhs;
+  const int nslices = (int)std::min<int64_t>(1024, (count + 4095) / 4096);
+  hipLaunchKernelGGL(dot_partial_kernel, dim3((unsigned)nslices), dim3(256), 0, stream, y, x, count, nslices, pdot);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(logdet_quad_final_kernel, dim3(1), dim3(256), 0, stream, plog, nb, pdot, nslices, out);
+  return hipGetLastError();
+}
+
+// G = s * f * (X - sum_j x_j x_j^T) on the pattern (f = 1 for the diagonal and
+// tip blocks, 2 for the lower and arrow blocks, which also stand at their
+// mirrored positions), gy = 2 s x.  Elementwise: G may alias X.
+struct GradParams {
+  int64_t n, b, a, nrhs;
+  const double* XD; const double* XB; const double* XR; const double* XT;
+  const double* x;
+  const double* scale;
+  double* GD; double* GB; double* GR; double* GT;
+  double* gy;
+};
+
+__global__ __launch_bounds__(256) void grad_pattern_kernel(GradParams p) {
+  const int64_t n = p.n, b = p.b, a = p.a, nr = p.nrhs;
+  const int64_t bb = b * b, ab = a * b;
+  const int64_t nD = n * bb, nB = (n - 1) * bb, nR = n * ab, nT = a * a, N = n * b + a;
+  const int64_t total = nD + nB + nR + nT + (p.gy ? N * nr : 0);
+  const double s = p.scale ? *p.scale : 1.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t k = e;
+    int64_t row, col;  // global row / column indices into x
+    const double* X;
+    double* G;
+    double f;
+    if (k < nD) {
+      const int64_t i = k / bb, rc = k - i * bb, r = rc / b, c = rc - r * b;
+      row = i * b + r; col = i * b + c; X = p.XD; G = p.GD; f = 1.0;
+    } else if ((k -= nD) < nB) {
+      const int64_t i = k / bb, rc = k - i * bb, r = rc / b, c = rc - r * b;
+      row = (i + 1) * b + r; col = i * b + c; X = p.XB; G = p.GB; f = 2.0;
+    } else if ((k -= nB) < nR) {
+      const int64_t i = k / ab, rc = k - i * ab, r = rc / b, c = rc - r * b;
+      row = n * b + r; col = i * b + c; X = p.XR; G = p.GR; f = 2.0;
+    } else if ((k -= nR) < nT) {
+      const int64_t r = k / a, c = k - r * a;
+      row = n * b + r; col = n * b + c; X = p.XT; G = p.GT; f = 1.0;
+    } else {
+      k -= nT;
+      p.gy[k] = 2.0 * s * p.x[k];
+      continue;
+    }
+    double o = 0.0;
+    for (int64_t j = 0; j < nr; ++j) o += p.x[row * nr + j] * p.x[col * nr + j];
+    G[k] = s * f * (X[k] - o);
+  }
+}
+
+hipError_t grad_launch(int64_t n, int64_t b, int64_t a, const double* XD, const double* XB, const double* XR,
+                       const double* XT, const double* x, int64_t nrhs, const double* scale, double* GD, double* GB,
+                       double* GR, double* GT, double* gy, hipStream_t stream) {
+  GradParams p{n, b, a, nrhs, XD, XB, XR, XT, x, scale, GD, GB, GR, GT, gy};
+  const int64_t total = n * b * b + (n - 1) * b * b + n * a * b + a * a + (gy ? (n * b + a) * nrhs : 0);
+  const unsigned grid = (unsigned)std::min<int64_t>(16384, (total + 255) / 256);
+  hipLaunchKernelGGL(grad_pattern_kernel, dim3(grid), dim3(256), 0, stream, p);
+  return hipGetLastError();
+}
 
 hipError_t logdet_launch(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT, double* out, void* work,
                          hipStream_t stream) {

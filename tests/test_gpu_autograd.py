@@ -1,0 +1,154 @@
+"""GPU checks of the differentiable f(Q) = log det Q + y^T Q^{-1} y.
+
+* tiny sizes: value and every gradient against dense torch autograd (CPU FP64)
+  through the same assembly convention;
+* the autograd workload (n=256, b=512, a=4): value and gradient blocks against
+  the oracle (CPU FP64, 1e-10 relative Frobenius per block);
+* directional central finite differences (h = 1e-6) of the GPU forward;
+* y = 0 gives G = Sigma on the pattern.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_17528_amd import synth
+from tests.gpu_util import TOL, errs, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2503_17528_amd import bta
+
+    bta.lib()
+    return torch
+
+
+def _dense_f(torch, D, B, R, T, y):
+    n, b = D.shape[0], D.shape[1]
+    a = T.shape[0]
+    N = n * b + a
+    Q = torch.zeros((N, N), dtype=torch.float64)
+    for i in range(n):
+        s = slice(i * b, (i + 1) * b)
+        Q[s, s] = 0.5 * (D[i] + D[i].T)
+        if i < n - 1:
+            s1 = slice((i + 1) * b, (i + 2) * b)
+            Q[s1, s] = B[i]
+            Q[s, s1] = B[i].T
+        Q[n * b:, s] = R[i]
+        Q[s, n * b:] = R[i].T
+    Q[n * b:, n * b:] = 0.5 * (T + T.T)
+    return torch.logdet(Q) + y @ torch.linalg.solve(Q, y)
+
+
+@pytest.mark.parametrize("n,b,a", [(3, 8, 2), (2, 70, 0), (4, 33, 5), (1, 20, 3)])
+def test_gradient_vs_dense_autograd(torch_cuda, n, b, a):
+    torch = torch_cuda
+    from paper_2503_17528_amd.autograd import logdet_quad
+
+    say(f"case autograd dense n={n} b={b} a={a}")
+    wl = synth.workload(n, b, a)
+    Q = synth.make_np(wl, 2)
+    y = synth.rhs_np(wl, 2)[:, 0]
+    cpu = [torch.tensor(Q[k], requires_grad=True) for k in "DBRT"] + [torch.tensor(y, requires_grad=True)]
+    fd = _dense_f(torch, *cpu)
+    fd.backward()
+    dev = [torch.tensor(Q[k], device="cuda", requires_grad=True) for k in "DBRT"] + \
+          [torch.tensor(y, device="cuda", requires_grad=True)]
+    fg = logdet_quad(*dev)
+    fg.backward()
+    torch.cuda.synchronize()
+    say(f"   f gpu {fg.item()} dense {fd.item()}")
+    assert abs(fg.item() - fd.item()) < 1e-11 * abs(fd.item())
+    for k, (tc, tg) in enumerate(zip(cpu, dev)):
+        ref = tc.grad.numpy()
+        if ref.size == 0:
+            continue
+        got = tg.grad.cpu().numpy()
+        e = np.max(np.abs(got - ref)) / max(1.0, np.max(np.abs(ref)))
+        say(f"   grad[{k}] max err {e:.3e}")
+        assert e < 1e-11
+
+
+def test_gradient_autograd_workload_vs_oracle(torch_cuda):
+    torch = torch_cuda
+    from paper_2503_17528_amd.autograd import logdet_quad
+
+    wl = synth.AUTOGRAD
+    n, b, a = wl.n, wl.b, wl.a
+    say(f"case autograd {wl.name}")
+    Q = synth.make_np(wl, 0)
+    y = synth.rhs_np(wl, 0)[:, 0]
+    F = oracle.pobtaf(Q["D"], Q["B"], Q["R"], Q["T"])
+    X = oracle.pobtasi(F["LD"], F["LB"], F["LR"], F["LT"])
+    x = oracle.pobtas(F["LD"], F["LB"], F["LR"], F["LT"], y)
+    fo = oracle.logdet(F["LD"], F["LT"]) + float(y @ x)
+    Go = oracle.grad_logdet_quad(X, x, n, b, a)
+    dev = [torch.tensor(Q[k], device="cuda", requires_grad=True) for k in "DBRT"] + \
+          [torch.tensor(y, device="cuda", requires_grad=True)]
+    f = logdet_quad(*dev)
+    f.backward()
+    torch.cuda.synchronize()
+    say(f"   f gpu {f.item():.15e} oracle {fo:.15e}")
+    assert abs(f.item() - fo) <= TOL * abs(fo)
+    got = {k: dev[i].grad.cpu().numpy() for i, k in enumerate("DBRT")}
+    e = errs(got, Go, lower=())
+    say(f"   gradient blocks vs oracle: {e}")
+    assert max(e.values()) < TOL
+    gy = dev[4].grad.cpu().numpy()
+    assert np.linalg.norm(gy - 2 * x) / np.linalg.norm(2 * x) < TOL
+
+
+def test_gradient_directional_fd(torch_cuda):
+    torch = torch_cuda
+    from paper_2503_17528_amd import bta
+    from paper_2503_17528_amd.autograd import logdet_quad
+
+    n, b, a = 8, 96, 3
+    say(f"case autograd FD n={n} b={b} a={a}")
+    wl = synth.workload(n, b, a)
+    Q = synth.make_np(wl, 5)
+    y = synth.rhs_np(wl, 5)[:, 0]
+    rng = np.random.default_rng(6)
+    V = {k: rng.standard_normal(Q[k].shape) for k in "DBRT"}
+    V["D"] = 0.5 * (V["D"] + np.transpose(V["D"], (0, 2, 1)))
+    V["T"] = 0.5 * (V["T"] + V["T"].T)
+    dev = [torch.tensor(Q[k], device="cuda", requires_grad=True) for k in "DBRT"] + [torch.tensor(y, device="cuda")]
+    f = logdet_quad(*dev)
+    f.backward()
+    inner = sum(float(np.sum(dev[i].grad.cpu().numpy() * V[k])) for i, k in enumerate("DBRT"))
+    h = 1e-6
+
+    def fval(sign):
+        t = [torch.tensor(Q[k] + sign * h * V[k], device="cuda") for k in "DBRT"] + [torch.tensor(y, device="cuda")]
+        with torch.no_grad():
+            return logdet_quad(*t).item()
+
+    fdv = (fval(+1) - fval(-1)) / (2 * h)
+    say(f"   <G,V> {inner:.10e}  central FD {fdv:.10e}")
+    assert abs(fdv - inner) < 1e-6 * max(1.0, abs(inner))
+
+
+def test_gradient_at_zero_rhs_is_selected_inverse(torch_cuda):
+    torch = torch_cuda
+    from paper_2503_17528_amd.autograd import logdet_quad
+
+    n, b, a = 5, 64, 2
+    say(f"case autograd y=0 n={n} b={b} a={a}")
+    wl = synth.workload(n, b, a)
+    Q = synth.make_np(wl, 7)
+    F = oracle.pobtaf(Q["D"], Q["B"], Q["R"], Q["T"])
+    X = oracle.pobtasi(F["LD"], F["LB"], F["LR"], F["LT"])
+    dev = [torch.tensor(Q[k], device="cuda", requires_grad=True) for k in "DBRT"] + \
+          [torch.zeros(wl.N, dtype=torch.float64, device="cuda")]
+    logdet_quad(*dev).backward()
+    got = {k: dev[i].grad.cpu().numpy() for i, k in enumerate("DBRT")}
+    ref = {"D": X["XD"], "B": 2 * X["XB"], "R": 2 * X["XR"], "T": X["XT"]}
+    e = errs(got, ref, lower=())
+    say(f"   G vs Sigma: {e}")
+    assert max(e.values()) < TOL

@@ -50,23 +50,23 @@ def _sigma_q_identities(torch, Q, X, n, b, a, js):
     for j in js:
         acc = XD[j] @ D[j]
         if a:
-            acc += XR[j].T @ R[j]
+            acc += XR[j].T.contiguous() @ R[j]
         if j > 0:
-            acc += XB[j - 1] @ B[j - 1].T
+            acc += XB[j - 1] @ B[j - 1].T.contiguous()
         if j < n - 1:
             acc += XB[j].T.contiguous() @ B[j]
         worst = max(worst, (acc - I_b).abs().max().item())
         if a:
             acc = XR[j] @ D[j] + XT @ R[j]
             if j > 0:
-                acc += XR[j - 1] @ B[j - 1].T
+                acc += XR[j - 1] @ B[j - 1].T.contiguous()
             if j < n - 1:
                 acc += XR[j + 1] @ B[j]
             worst = max(worst, acc.abs().max().item())
     if a:
         acc = XT @ T
         for j in range(n):
-            acc += XR[j] @ R[j].T
+            acc += XR[j] @ R[j].T.contiguous()
         worst = max(worst, (acc - torch.eye(a, dtype=torch.float64, device=D.device)).abs().max().item())
     return worst
 
@@ -177,7 +177,7 @@ def test_largest_workload_in_place(torch_cuda):
     dev = 0.0
     for j in js[1:-1]:
         Dj, Bj, Rj = keep[j]
-        acc = XD[j] @ Dj + XR[j].T @ Rj + XB[j - 1] @ keep_prev[j].T + XB[j].T.contiguous() @ Bj
+        acc = XD[j] @ Dj + XR[j].T.contiguous() @ Rj + XB[j - 1] @ keep_prev[j].T.contiguous() + XB[j].T.contiguous() @ Bj
         dev = max(dev, (acc - torch.eye(b, dtype=torch.float64, device="cuda")).abs().max().item())
     acc = XT @ Tin
     say(f"   Sigma Q diagonal identities at blocks {js[1:-1]}: max abs deviation {dev:.3e}")
