@@ -137,6 +137,36 @@ BTA_API int bta_grad_logdet_quad(int64_t n, int64_t b, int64_t a,
                     const double* x, int64_t nrhs, const double* d_scale,
                     double* GD, double* GB, double* GR, double* GT, double* gy, bta_stream_t stream);
 
+/*
+ * Batched interface: many independent BTA matrices of different n, b, a.
+ * The descriptor array lives in host memory; every pointer in it is a device
+ * pointer with the same conventions as the single-matrix calls (exact
+ * in-place aliasing allowed within a matrix; arrays of different matrices
+ * must not overlap).  d_info is that matrix's device int64 info.
+ */
+typedef struct {
+  int64_t n, b, a;
+  const double *D, *B, *R, *T;   /* A blocks (bta_factor_batched input) */
+  double *LD, *LB, *LR, *LT;     /* L blocks (factor output, selinv input) */
+  double *XD, *XB, *XR, *XT;     /* selected-inverse blocks (selinv output) */
+  int64_t* d_info;
+} bta_desc;
+
+/* Workspace bytes for a batched op (BTA_OP_FACTOR or BTA_OP_SELINV); 0 on invalid input. */
+BTA_API size_t bta_batched_workspace_bytes(int op, int count, const bta_desc* descs);
+
+/* POBTAF for every matrix of the batch, all in one persistent kernel launch. */
+BTA_API int bta_factor_batched(int count, const bta_desc* descs, void* work, size_t work_bytes,
+                               bta_stream_t stream);
+
+/* POBTASI for every matrix of the batch: the launches of all matrices are
+ * merged stage by stage (one grouped launch per stage across the batch), the
+ * tile shape of every merged GEMM launch is chosen by the autotuner (measured
+ * on first use of a shape class), and the whole launch sequence is captured
+ * once in a HIP graph per descriptor set and replayed. */
+BTA_API int bta_selinv_batched(int count, const bta_desc* descs, void* work, size_t work_bytes,
+                               bta_stream_t stream);
+
 /* Static text for a status code. */
 BTA_API const char* bta_status_string(int status);
 

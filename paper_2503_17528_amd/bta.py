@@ -23,7 +23,14 @@ BTA_OK, BTA_EINVAL, BTA_ENOTPD, BTA_EHIP, BTA_ENOTSUP = 0, 1, 2, 3, 4
 BTA_OP_FACTOR, BTA_OP_SELINV, BTA_OP_SOLVE, BTA_OP_LOGDET = 0, 1, 2, 3
 
 EXPORTED = ("bta_workspace_bytes", "bta_factor", "bta_selinv", "bta_solve", "bta_logdet",
-            "bta_logdet_quad", "bta_grad_logdet_quad", "bta_status_string", "bta_last_error")
+            "bta_logdet_quad", "bta_grad_logdet_quad", "bta_batched_workspace_bytes", "bta_factor_batched",
+            "bta_selinv_batched", "bta_status_string", "bta_last_error")
+
+
+class bta_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("b", ctypes.c_int64), ("a", ctypes.c_int64)] + \
+               [(k, ctypes.c_void_p) for k in ("D", "B", "R", "T", "LD", "LB", "LR", "LT", "XD", "XB", "XR", "XT",
+                                               "d_info")]
 
 _lib = None
 
@@ -63,6 +70,12 @@ def lib() -> ctypes.CDLL:
     L.bta_logdet_quad.restype = ctypes.c_int
     L.bta_grad_logdet_quad.argtypes = [i64, i64, i64] + [vp] * 5 + [i64, vp] + [vp] * 5 + [vp]
     L.bta_grad_logdet_quad.restype = ctypes.c_int
+    L.bta_batched_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int, vp]
+    L.bta_batched_workspace_bytes.restype = sz
+    L.bta_factor_batched.argtypes = [ctypes.c_int, vp, vp, sz, vp]
+    L.bta_factor_batched.restype = ctypes.c_int
+    L.bta_selinv_batched.argtypes = [ctypes.c_int, vp, vp, sz, vp]
+    L.bta_selinv_batched.restype = ctypes.c_int
     L.bta_status_string.argtypes = [ctypes.c_int]
     L.bta_status_string.restype = ctypes.c_char_p
     L.bta_last_error.argtypes = []
@@ -100,6 +113,18 @@ def bta_logdet_quad(n, b, a, LD, LT, y, x, nrhs, d_out, work, work_bytes, stream
 
 def bta_grad_logdet_quad(n, b, a, XD, XB, XR, XT, x, nrhs, d_scale, GD, GB, GR, GT, gy, stream) -> int:
     return int(lib().bta_grad_logdet_quad(n, b, a, XD, XB, XR, XT, x, nrhs, d_scale, GD, GB, GR, GT, gy, stream))
+
+
+def bta_batched_workspace_bytes(op, count, descs) -> int:
+    return int(lib().bta_batched_workspace_bytes(op, count, descs))
+
+
+def bta_factor_batched(count, descs, work, work_bytes, stream) -> int:
+    return int(lib().bta_factor_batched(count, descs, work, work_bytes, stream))
+
+
+def bta_selinv_batched(count, descs, work, work_bytes, stream) -> int:
+    return int(lib().bta_selinv_batched(count, descs, work, work_bytes, stream))
 
 
 def bta_status_string(status: int) -> str:
@@ -288,3 +313,49 @@ def grad_logdet_quad(X, x, scale=None, out=None, want_gy=True, stream=None):
                               _ptr(gy), _stream(stream))
     _check(st, "bta_grad_logdet_quad")
     return GD, GB, GR, GT, (gy.reshape(x.shape) if gy is not None else None)
+
+
+class Batch:
+    """A batch of independent BTA matrices held as torch tensors: ``mats`` is
+    a list of dicts with keys D, B, R, T (inputs).  Allocates L and X outputs
+    and per-matrix info tensors, builds the descriptor array once, and runs
+    the batched entry points."""
+
+    def __init__(self, mats, inplace: bool = False):
+        import torch
+
+        self.mats = mats
+        self.count = len(mats)
+        arr = (bta_desc * self.count)()
+        self.L, self.X, self.info = [], [], []
+        for m, q in enumerate(mats):
+            D, B, R, T = q["D"], q["B"], q["R"], q["T"]
+            n, b, a = _dims(D, R, T)
+            L = (D, B, R, T) if inplace else tuple(torch.empty_like(t) for t in (D, B, R, T))
+            X = L if inplace else tuple(torch.empty_like(t) for t in (D, B, R, T))
+            info = torch.zeros((), dtype=torch.int64, device=D.device)
+            self.L.append(L); self.X.append(X); self.info.append(info)
+            arr[m] = bta_desc(n, b, a, _ptr(D), _ptr(B), _ptr(R), _ptr(T), _ptr(L[0]), _ptr(L[1]), _ptr(L[2]),
+                              _ptr(L[3]), _ptr(X[0]), _ptr(X[1]), _ptr(X[2]), _ptr(X[3]), info.data_ptr())
+        self.descs = arr
+        dev = mats[0]["D"].device
+        nf = bta_batched_workspace_bytes(BTA_OP_FACTOR, self.count, ctypes.byref(arr))
+        ns = bta_batched_workspace_bytes(BTA_OP_SELINV, self.count, ctypes.byref(arr))
+        self.wf = torch.empty(max(nf, 1), dtype=torch.uint8, device=dev)
+        self.ws = torch.empty(max(ns, 1), dtype=torch.uint8, device=dev)
+        self.nf, self.ns = nf, ns
+
+    def factor(self, stream=None, check: bool = True):
+        st = bta_factor_batched(self.count, ctypes.byref(self.descs), self.wf.data_ptr(), self.nf, _stream(stream))
+        _check(st, "bta_factor_batched")
+        if check:
+            for m, info in enumerate(self.info):
+                v = int(info.item())
+                if v != 0:
+                    raise BTAError(BTA_ENOTPD, f"matrix {m}: info={v}")
+        return self.L
+
+    def selinv(self, stream=None):
+        st = bta_selinv_batched(self.count, ctypes.byref(self.descs), self.ws.data_ptr(), self.ns, _stream(stream))
+        _check(st, "bta_selinv_batched")
+        return self.X

@@ -2,6 +2,8 @@
 // dispatch to the launchers.  Validation happens before any HIP call, so the
 // argument checks work on a host without a GPU.
 #include <algorithm>
+#include <utility>
+#include <vector>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -211,6 +213,99 @@ int bta_grad_logdet_quad(int64_t n, int64_t b, int64_t a, const double* XD, cons
   hipError_t e = bta::grad_launch(n, b, a, XD, XB, XR, XT, x, nrhs, d_scale, GD, GB, GR, GT, gy,
                                   reinterpret_cast<hipStream_t>(stream));
   return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_grad_logdet_quad launch");
+}
+
+namespace {
+
+int validate_batch(int count, const bta_desc* d, bool factor) {
+  if (count < 1 || count > (1 << 20)) return fail(BTA_EINVAL, "invalid batch count %d", count);
+  if (!d) return fail(BTA_EINVAL, "descriptor array is NULL");
+  std::vector<std::pair<uintptr_t, uintptr_t>> spans;
+  for (int m = 0; m < count; ++m) {
+    const int64_t n = d[m].n, b = d[m].b, a = d[m].a;
+    if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "matrix %d: invalid sizes n=%lld b=%lld a=%lld", m, (long long)n, (long long)b, (long long)a);
+    int st;
+    if (factor) {
+      const Arr arr[9] = {{d[m].D, blk_bytes(n, b, b), "D"},   {d[m].B, blk_bytes(n - 1, b, b), "B"}, {d[m].R, blk_bytes(n, a, b), "R"},
+                          {d[m].T, blk_bytes(1, a, a), "T"},   {d[m].LD, blk_bytes(n, b, b), "LD"}, {d[m].LB, blk_bytes(n - 1, b, b), "LB"},
+                          {d[m].LR, blk_bytes(n, a, b), "LR"}, {d[m].LT, blk_bytes(1, a, a), "LT"}, {d[m].d_info, 8, "d_info"}};
+      const int pair[9] = {4, 5, 6, 7, 0, 1, 2, 3, -1};
+      st = check_arrays(arr, 9, pair);
+      if (st) return fail(st, "matrix %d: %s", m, g_last_error.c_str());
+      for (const Arr& x : arr)
+        if (x.bytes) spans.push_back({reinterpret_cast<uintptr_t>(x.p), reinterpret_cast<uintptr_t>(x.p) + x.bytes});
+    } else {
+      const Arr arr[8] = {{d[m].LD, blk_bytes(n, b, b), "LD"}, {d[m].LB, blk_bytes(n - 1, b, b), "LB"}, {d[m].LR, blk_bytes(n, a, b), "LR"},
+                          {d[m].LT, blk_bytes(1, a, a), "LT"}, {d[m].XD, blk_bytes(n, b, b), "XD"}, {d[m].XB, blk_bytes(n - 1, b, b), "XB"},
+                          {d[m].XR, blk_bytes(n, a, b), "XR"}, {d[m].XT, blk_bytes(1, a, a), "XT"}};
+      const int pair[8] = {4, 5, 6, 7, 0, 1, 2, 3};
+      st = check_arrays(arr, 8, pair);
+      if (st) return fail(st, "matrix %d: %s", m, g_last_error.c_str());
+      for (const Arr& x : arr)
+        if (x.bytes) spans.push_back({reinterpret_cast<uintptr_t>(x.p), reinterpret_cast<uintptr_t>(x.p) + x.bytes});
+    }
+  }
+  // arrays of different matrices must not overlap (exact in-place pairs repeat the same span)
+  std::sort(spans.begin(), spans.end());
+  spans.erase(std::unique(spans.begin(), spans.end()), spans.end());
+  for (size_t i = 1; i < spans.size(); ++i)
+    if (spans[i].first < spans[i - 1].second) return fail(BTA_EINVAL, "arrays of the batch overlap");
+  return BTA_OK;
+}
+
+void batch_sizes(int count, const bta_desc* d, std::vector<int64_t>& n, std::vector<int64_t>& b, std::vector<int64_t>& a) {
+  n.resize(count); b.resize(count); a.resize(count);
+  for (int m = 0; m < count; ++m) { n[m] = d[m].n; b[m] = d[m].b; a[m] = d[m].a; }
+}
+
+std::vector<bta::BatchMatrix> batch_mats(int count, const bta_desc* d) {
+  std::vector<bta::BatchMatrix> v(count);
+  for (int m = 0; m < count; ++m)
+    v[m] = bta::BatchMatrix{d[m].n, d[m].b, d[m].a, d[m].D, d[m].B, d[m].R, d[m].T, d[m].LD, d[m].LB, d[m].LR, d[m].LT,
+                            d[m].XD, d[m].XB, d[m].XR, d[m].XT, d[m].d_info};
+  return v;
+}
+
+}  // namespace
+
+size_t bta_batched_workspace_bytes(int op, int count, const bta_desc* descs) {
+  if (count < 1 || !descs) return 0;
+  for (int m = 0; m < count; ++m)
+    if (!dims_ok(descs[m].n, descs[m].b, descs[m].a)) return 0;
+  std::vector<int64_t> n, b, a;
+  batch_sizes(count, descs, n, b, a);
+  if (op == BTA_OP_FACTOR) return bta::factor_batch_plan(count, n.data(), b.data(), a.data()).bytes;
+  if (op == BTA_OP_SELINV) return bta::selinv_batch_bytes(count, n.data(), b.data(), a.data());
+  return 0;
+}
+
+int bta_factor_batched(int count, const bta_desc* descs, void* work, size_t work_bytes, bta_stream_t stream) {
+  int st = validate_batch(count, descs, true);
+  if (st) return st;
+  std::vector<int64_t> n, b, a;
+  batch_sizes(count, descs, n, b, a);
+  const bta::FactorBatchPlan bp = bta::factor_batch_plan(count, n.data(), b.data(), a.data());
+  st = check_work(work, work_bytes, bp.bytes);
+  if (st) return st;
+  st = device_ok();
+  if (st) return st;
+  const std::vector<bta::BatchMatrix> mats = batch_mats(count, descs);
+  hipError_t e = bta::factor_batch_launch(bp, mats.data(), work, reinterpret_cast<hipStream_t>(stream), bta::device_cu_count());
+  return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_factor_batched launch");
+}
+
+int bta_selinv_batched(int count, const bta_desc* descs, void* work, size_t work_bytes, bta_stream_t stream) {
+  int st = validate_batch(count, descs, false);
+  if (st) return st;
+  std::vector<int64_t> n, b, a;
+  batch_sizes(count, descs, n, b, a);
+  st = check_work(work, work_bytes, bta::selinv_batch_bytes(count, n.data(), b.data(), a.data()));
+  if (st) return st;
+  st = device_ok();
+  if (st) return st;
+  const std::vector<bta::BatchMatrix> mats = batch_mats(count, descs);
+  hipError_t e = bta::selinv_batch_launch(count, mats.data(), work, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_selinv_batched launch");
 }
 
 const char* bta_status_string(int status) {

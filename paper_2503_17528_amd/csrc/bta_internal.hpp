@@ -4,6 +4,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <array>
 #include <vector>
 
 namespace bta {
@@ -18,7 +19,29 @@ FactorPlan factor_plan(int64_t n, int64_t b, int64_t a);
 hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
                          const double* D, const double* B, const double* R, const double* T,
                          double* LD, double* LB, double* LR, double* LT,
-                         void* work, int64_t* info, hipStream_t stream, int num_cus);
+                         void* work, int64_t* info, hipStream_t stream, int num_cus,
+                         unsigned long long* trace = nullptr);
+
+// One matrix of a batch (sizes and the pointers of include/bta.h's bta_desc).
+struct BatchMatrix {
+  int64_t n, b, a;
+  const double *D, *B, *R, *T;
+  double *LD, *LB, *LR, *LT;
+  double *XD, *XB, *XR, *XT;
+  int64_t* info;
+};
+
+struct FactorBatchPlan {
+  int count = 0;
+  std::vector<FactorPlan> plans;
+  std::vector<long long> flag_off;
+  std::vector<std::array<size_t, 2>> ws_off;
+  long long nflags = 0, ntasks = 0, nseg = 0;
+  size_t off_ctl = 0, off_mats = 0, off_segs = 0, off_flags = 0, bytes = 0;
+};
+FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b, const int64_t* a);
+hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mats, void* work, hipStream_t stream,
+                               int num_cus);
 
 // ---------------------------------------------------------------- grouped GEMM
 // One product term: sum_k A(m,k) B(c,k) over a k range.  A(m,k) is
@@ -72,6 +95,10 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
                          const double* LD, const double* LB, const double* LR, const double* LT,
                          double* XD, double* XB, double* XR, double* XT,
                          void* work, hipStream_t stream);
+
+// batched selected inversion
+size_t selinv_batch_bytes(int count, const int64_t* n, const int64_t* b, const int64_t* a);
+hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, hipStream_t stream);
 
 // ---------------------------------------------------------------- solve / logdet
 size_t solve_work_bytes(int64_t n, int64_t b, int64_t a, int64_t nrhs);

@@ -25,6 +25,7 @@
 // for tasks with smaller tickets, which are owned by running workgroups: the
 // schedule cannot deadlock whatever the number of resident workgroups.  Every
 // wait is bounded; a stuck wait raises an abort flag that releases all waits.
+#include <algorithm>
 #include <vector>
 
 #include "bta_device.hpp"
@@ -49,6 +50,7 @@ struct FactorParams {
   long long ntasks;
   long long step_full, step_last;  // tasks per step (with / without SUB)
   long long spin_limit;
+  unsigned long long* trace;  // optional: 4 words per ticket (start, k loop done, end, type | workgroup << 8)
 };
 
 struct Task {
@@ -275,16 +277,13 @@ __device__ __forceinline__ void publish(int* flag, int tid) {
   if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
-  __shared__ Shared sh;
-  const int tid = threadIdx.x;
-  for (;;) {
-    if (tid == 0) sh.ticket = (long long)atomicAdd((unsigned long long*)p.ctl, 1ULL);
-    __syncthreads();
-    const long long tk = uni64(sh.ticket);
-    if (tk >= p.ntasks) break;
+// One task of one matrix: accumulate, finish, publish.
+__device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Shared& sh, int tid) {
+  {
     Task t = decode(p, tk);
     t.type = uni(t.type); t.i = uni(t.i); t.r = uni(t.r); t.c = uni(t.c);
+    unsigned long long tr0 = 0, tr1 = 0;
+    if (p.trace && tid == 0) tr0 = __builtin_amdgcn_s_memrealtime();
     const int T = p.T, b = p.b, a = p.a;
     const int64_t bb = (int64_t)b * b, ab = (int64_t)a * b;
 
@@ -397,6 +396,7 @@ __global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
       }
     }
     __syncthreads();
+    if (p.trace && tid == 0) tr1 = __builtin_amdgcn_s_memrealtime();
 
     // ---- finish the tile
     if (t.type == T_TUPD) {
@@ -449,6 +449,81 @@ __global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
       }
     }
     publish(my_flag, tid);
+    if (p.trace && tid == 0) {
+      unsigned long long* rec = p.trace + 4 * tk;
+      rec[0] = tr0;
+      rec[1] = tr1;
+      rec[2] = __builtin_amdgcn_s_memrealtime();
+      rec[3] = (unsigned long long)t.type | ((unsigned long long)blockIdx.x << 8);
+    }
+  }
+}
+
+__global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
+  __shared__ Shared sh;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) sh.ticket = (long long)atomicAdd((unsigned long long*)p.ctl, 1ULL);
+    __syncthreads();
+    const long long tk = uni64(sh.ticket);
+    if (tk >= p.ntasks) break;
+    run_task(p, tk, sh, tid);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Many independent BTA matrices in one persistent launch.  Tickets run over a
+// segment table that interleaves the matrices step by step (segment = the
+// tasks of one block step of one matrix, the last step of a matrix carries its
+// tip tasks); inside a matrix the order is the single-matrix topological order,
+// and matrices do not depend on each other, so the schedule stays deadlock free.
+struct BatchSeg {
+  long long t0;      // first global ticket of the segment
+  long long local0;  // first ticket of the segment inside its matrix
+  int mat;
+  int pad;
+};
+
+struct FactorBatchArgs {
+  const FactorParams* mats;
+  const BatchSeg* segs;
+  int nseg;
+  long long ntasks;
+  int* ctl;
+};
+
+__global__ __launch_bounds__(NT, 2) void factor_batched_kernel(FactorBatchArgs args) {
+  __shared__ Shared sh;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) sh.ticket = (long long)atomicAdd((unsigned long long*)args.ctl, 1ULL);
+    __syncthreads();
+    const long long tk = uni64(sh.ticket);
+    if (tk >= args.ntasks) break;
+    int lo = 0, hi = args.nseg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (args.segs[mid].t0 <= tk) lo = mid; else hi = mid - 1;
+    }
+    lo = uni(lo);
+    const long long local = uni64(args.segs[lo].local0 + (tk - args.segs[lo].t0));
+    const FactorParams p = args.mats[uni(args.segs[lo].mat)];
+    run_task(p, local, sh, tid);
+  }
+}
+
+__global__ void factor_batched_reset_kernel(int* flags, long long nflags, int* ctl, const FactorParams* mats, int count) {
+  const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (long long i = i0; i < nflags; i += (long long)gridDim.x * blockDim.x) flags[i] = 0;
+  if (i0 < 4) ctl[i0] = 0;
+  for (long long m = i0; m < count; m += (long long)gridDim.x * blockDim.x) *mats[m].info = 0x7fffffffffffffffLL;
+}
+
+__global__ void factor_batched_finish_kernel(const int* ctl, const FactorParams* mats, int count) {
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < count; m += gridDim.x * blockDim.x) {
+    int64_t* info = mats[m].info;
+    if (ctl[2] != 0) *info = -1;
+    else if (*info == 0x7fffffffffffffffLL) *info = 0;
   }
 }
 
@@ -493,7 +568,7 @@ FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
 hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
                          const double* D, const double* B, const double* R, const double* T,
                          double* LD, double* LB, double* LR, double* LT,
-                         void* work, int64_t* info, hipStream_t stream, int num_cus) {
+                         void* work, int64_t* info, hipStream_t stream, int num_cus, unsigned long long* trace) {
   char* w = static_cast<char*>(work);
   FactorParams p;
   p.n = (int)n; p.b = (int)b; p.a = (int)a; p.T = fp.T; p.TA = fp.TA;
@@ -508,6 +583,7 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
   p.ntasks = fp.ntasks;
   p.step_full = fp.step_full;
   p.step_last = fp.step_last;
+  p.trace = trace;
   p.spin_limit = 1LL << 22;  // a few seconds of polling without progress before the watchdog fires
   const int rgrid = (int)std::min<long long>(1024, (fp.nflags + 255) / 256 + 1);
   hipLaunchKernelGGL(factor_reset_kernel, dim3(rgrid), dim3(256), 0, stream, p.flags, fp.nflags, p.ctl, info);
@@ -520,6 +596,121 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(factor_finish_kernel, dim3(1), dim3(64), 0, stream, p.ctl, info);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Step-major interleaving of the matrices of a batch: segment (step s, matrix m)
+// holds the tasks of block step s of matrix m; the last step also carries the
+// tip tasks.  *total receives the number of tickets.
+static std::vector<BatchSeg> batch_segments(const FactorBatchPlan& bp, const int64_t* n, long long* total) {
+  std::vector<BatchSeg> segs;
+  segs.reserve((size_t)bp.nseg);
+  int64_t maxn = 0;
+  for (int m = 0; m < bp.count; ++m) maxn = std::max<int64_t>(maxn, n[m]);
+  long long t = 0;
+  for (int64_t st = 0; st < maxn; ++st) {
+    for (int m = 0; m < bp.count; ++m) {
+      if (st >= n[m]) continue;
+      const FactorPlan& fp = bp.plans[m];
+      const long long local0 = st * fp.step_full;
+      const long long len = (st < n[m] - 1) ? fp.step_full : fp.ntasks - local0;
+      segs.push_back(BatchSeg{t, local0, m, 0});
+      t += len;
+    }
+  }
+  *total = t;
+  return segs;
+}
+
+// Batched host plan.
+FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b, const int64_t* a) {
+  FactorBatchPlan bp;
+  bp.count = count;
+  bp.plans.resize(count);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
+  bp.off_ctl = take(64);
+  bp.off_mats = take(sizeof(FactorParams) * (size_t)count);
+  // segments: one per (step, matrix) with n_m > step
+  int64_t maxn = 0, nseg = 0;
+  for (int m = 0; m < count; ++m) { maxn = std::max<int64_t>(maxn, n[m]); nseg += n[m]; }
+  bp.nseg = nseg;
+  bp.off_segs = take(sizeof(BatchSeg) * (size_t)nseg);
+  long long nflags = 0;
+  bp.flag_off.resize(count);
+  bp.ws_off.resize(count);
+  for (int m = 0; m < count; ++m) {
+    bp.plans[m] = factor_plan(n[m], b[m], a[m]);
+    bp.flag_off[m] = nflags;
+    nflags += bp.plans[m].nflags;
+  }
+  bp.nflags = nflags;
+  bp.off_flags = take(sizeof(int) * (size_t)std::max<long long>(nflags, 1));
+  for (int m = 0; m < count; ++m) {
+    const FactorPlan& fp = bp.plans[m];
+    bp.ws_off[m][0] = take(fp.off_P - fp.off_Wd);          // Wd + Wt
+    bp.ws_off[m][1] = take(fp.bytes - fp.off_P);           // P
+  }
+  bp.bytes = off;
+  long long t = 0;
+  for (int m = 0; m < count; ++m) t += bp.plans[m].ntasks;
+  bp.ntasks = t;
+  return bp;
+}
+
+hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mats, void* work, hipStream_t stream,
+                               int num_cus) {
+  char* w = static_cast<char*>(work);
+  int* ctl = reinterpret_cast<int*>(w + bp.off_ctl);
+  int* flags = reinterpret_cast<int*>(w + bp.off_flags);
+  std::vector<FactorParams> hp(bp.count);
+  for (int m = 0; m < bp.count; ++m) {
+    const FactorPlan& fp = bp.plans[m];
+    FactorParams& p = hp[m];
+    p = FactorParams{};
+    p.n = (int)mats[m].n; p.b = (int)mats[m].b; p.a = (int)mats[m].a; p.T = fp.T; p.TA = fp.TA;
+    p.D = mats[m].D; p.B = mats[m].B; p.R = mats[m].R; p.Tt = mats[m].T;
+    p.LD = mats[m].LD; p.LB = mats[m].LB; p.LR = mats[m].LR; p.LT = mats[m].LT;
+    char* wd = w + bp.ws_off[m][0];
+    p.Wd = reinterpret_cast<double*>(wd);
+    p.Wt = reinterpret_cast<double*>(wd + (fp.off_Wt - fp.off_Wd));
+    p.P = reinterpret_cast<double*>(w + bp.ws_off[m][1]);
+    p.flags = flags + bp.flag_off[m];
+    p.ctl = ctl;
+    p.info = mats[m].info;
+    p.ntasks = fp.ntasks;
+    p.step_full = fp.step_full;
+    p.step_last = fp.step_last;
+    p.spin_limit = 1LL << 22;
+    p.trace = nullptr;
+  }
+  std::vector<int64_t> ns(bp.count);
+  for (int m = 0; m < bp.count; ++m) ns[m] = mats[m].n;
+  long long t = 0;
+  const std::vector<BatchSeg> segs = batch_segments(bp, ns.data(), &t);
+  hipError_t e = hipMemcpyAsync(w + bp.off_mats, hp.data(), sizeof(FactorParams) * hp.size(), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(w + bp.off_segs, segs.data(), sizeof(BatchSeg) * segs.size(), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return e;
+  const FactorParams* dmats = reinterpret_cast<const FactorParams*>(w + bp.off_mats);
+  const int rgrid = (int)std::min<long long>(1024, (bp.nflags + 255) / 256 + 1);
+  hipLaunchKernelGGL(factor_batched_reset_kernel, dim3(rgrid), dim3(256), 0, stream, flags, bp.nflags, ctl, dmats, bp.count);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  FactorBatchArgs args;
+  args.mats = dmats;
+  args.segs = reinterpret_cast<const BatchSeg*>(w + bp.off_segs);
+  args.nseg = (int)segs.size();
+  args.ntasks = t;
+  args.ctl = ctl;
+  const long long grid = std::min<long long>(t, 2LL * num_cus);
+  timing_mark(KT_FACTOR, true, stream);
+  hipLaunchKernelGGL(factor_batched_kernel, dim3((unsigned)grid), dim3(NT), 0, stream, args);
+  timing_mark(KT_FACTOR, false, stream);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(factor_batched_finish_kernel, dim3((bp.count + 255) / 256), dim3(256), 0, stream, ctl, dmats, bp.count);
   return hipGetLastError();
 }
 
@@ -594,6 +785,47 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
 }
 
 }  // namespace bta
+
+// bta_factor with a per-task trace buffer of 4 * ntasks words (device memory);
+// the number of tasks is returned through *ntasks when the pointer is set.
+extern "C" __attribute__((visibility("default"))) int bta_internal_factor_traced(
+    int64_t n, int64_t b, int64_t a, const double* D, const double* B, const double* R, const double* T, double* LD,
+    double* LB, double* LR, double* LT, void* work, int64_t* info, unsigned long long* trace, long long* ntasks,
+    hipStream_t stream) {
+  const bta::FactorPlan fp = bta::factor_plan(n, b, a);
+  if (ntasks) *ntasks = fp.ntasks;
+  if (!trace) return 0;
+  return bta::factor_launch(fp, n, b, a, D, B, R, T, LD, LB, LR, LT, work, info, stream, bta::device_cu_count(), trace) ==
+                 hipSuccess
+             ? 0
+             : 1;
+}
+
+// Host check of the batch interleaving: every ticket maps (by the kernel's
+// binary search) to a matrix and a local ticket; per matrix the local tickets
+// come out as 0, 1, 2, ... ntasks-1 exactly once, in order.
+extern "C" __attribute__((visibility("default"))) int bta_internal_factor_batch_check(int count, const int64_t* n,
+                                                                                       const int64_t* b, const int64_t* a) {
+  const bta::FactorBatchPlan bp = bta::factor_batch_plan(count, n, b, a);
+  long long total = 0;
+  const std::vector<bta::BatchSeg> segs = bta::batch_segments(bp, n, &total);
+  if (total != bp.ntasks) return 1;
+  std::vector<long long> next(count, 0);
+  for (long long tk = 0; tk < total; ++tk) {
+    int lo = 0, hi = (int)segs.size() - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (segs[mid].t0 <= tk) lo = mid; else hi = mid - 1;
+    }
+    const int m = segs[lo].mat;
+    const long long local = segs[lo].local0 + (tk - segs[lo].t0);
+    if (m < 0 || m >= count || local != next[m]) return 2;
+    ++next[m];
+  }
+  for (int m = 0; m < count; ++m)
+    if (next[m] != bp.plans[m].ntasks) return 3;
+  return 0;
+}
 
 extern "C" __attribute__((visibility("default"))) int bta_internal_factor_schedule_check(int64_t n, int64_t b, int64_t a,
                                                                                           long long* counts) {

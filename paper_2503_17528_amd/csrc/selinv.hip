@@ -250,6 +250,24 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// Batched selected inversion (matrices one after another; the workspace of the
+// largest matrix is reused).
+size_t selinv_batch_bytes(int count, const int64_t* n, const int64_t* b, const int64_t* a) {
+  size_t mx = 0;
+  for (int m = 0; m < count; ++m) mx = std::max(mx, selinv_plan(n[m], b[m], a[m]).bytes);
+  return mx;
+}
+
+hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, hipStream_t stream) {
+  for (int m = 0; m < count; ++m) {
+    const BatchMatrix& x = mats[m];
+    const SelinvPlan sp = selinv_plan(x.n, x.b, x.a);
+    BTA_TRY(selinv_launch(sp, x.n, x.b, x.a, x.LD, x.LB, x.LR, x.LT, x.XD, x.XB, x.XR, x.XT, work, stream));
+  }
+  return hipSuccess;
+}
+
 // Host dry run of selinv_launch with fake, widely separated array bases:
 // every window any launch would touch must lie inside one array (inputs are
 // never written).  Returns 0 when all windows are in bounds.

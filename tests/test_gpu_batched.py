@@ -1,0 +1,98 @@
+"""GPU parity of the batched entry points (many BTA matrices of uneven n, b,
+a in one persistent factor launch, then the batched selected inversion),
+every matrix against the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_17528_amd import synth
+from tests.gpu_util import TOL, errs, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2503_17528_amd import bta
+
+    bta.lib()
+    return torch
+
+
+def _check_matrix(Q, Lg, Xg, m):
+    F = oracle.pobtaf(Q["D"], Q["B"], Q["R"], Q["T"])
+    Xo = oracle.pobtasi(F["LD"], F["LB"], F["LR"], F["LT"])
+    eL = errs(dict(zip("DBRT", to_np(Lg))), {"D": F["LD"], "B": F["LB"], "R": F["LR"], "T": F["LT"]})
+    eX = errs(dict(zip("DBRT", to_np(Xg))), {"D": Xo["XD"], "B": Xo["XB"], "R": Xo["XR"], "T": Xo["XT"]}, lower=())
+    worst = max(max(eL.values()), max(eX.values()))
+    return worst, eL, eX
+
+
+@pytest.mark.parametrize("inplace", [False, True])
+def test_small_mixed_batch(torch_cuda, inplace):
+    torch = torch_cuda
+    from paper_2503_17528_amd import bta
+
+    shapes = [(1, 5, 0), (3, 64, 2), (2, 130, 70), (5, 40, 1), (4, 200, 0), (6, 64, 4)]
+    say(f"case batched small inplace={inplace}")
+    Qs = [synth.make_np(synth.workload(*s), 10 + k) for k, s in enumerate(shapes)]
+    mats = [{k: torch.from_numpy(q[k]).to("cuda") for k in "DBRT"} for q in Qs]
+    batch = bta.Batch(mats, inplace=inplace)
+    batch.factor()
+    if not inplace:
+        Ls = [tuple(t.clone() for t in L) for L in batch.L]
+    batch.selinv()
+    torch.cuda.synchronize()
+    for m, (s, Q) in enumerate(zip(shapes, Qs)):
+        if inplace:
+            F = oracle.pobtaf(Q["D"], Q["B"], Q["R"], Q["T"])
+            Xo = oracle.pobtasi(F["LD"], F["LB"], F["LR"], F["LT"])
+            e = errs(dict(zip("DBRT", to_np(batch.X[m]))), {"D": Xo["XD"], "B": Xo["XB"], "R": Xo["XR"], "T": Xo["XT"]},
+                     lower=())
+            worst = max(e.values())
+        else:
+            worst, _, _ = _check_matrix(Q, Ls[m], batch.X[m], m)
+        say(f"   matrix {m} {s}: max rel err {worst:.3e}")
+        assert worst < TOL
+
+
+def test_hyperparameter_sweep_batch(torch_cuda):
+    """64 matrices, n ~ U{16..96}, b in {128, 256, 384}, a in {2, 4, 6}."""
+    torch = torch_cuda
+    from paper_2503_17528_amd import bta
+
+    wls = synth.batched_workloads(0)
+    say(f"case batched sweep: {len(wls)} matrices, {sum(w.block_bytes() for w in wls) / 1e9:.2f} GB")
+    mats = [synth.make_torch(w, 100 + k, "cuda") for k, w in enumerate(wls)]
+    batch = bta.Batch(mats)
+    batch.factor()
+    Ls = [tuple(t.clone() for t in L) for L in batch.L]
+    batch.selinv()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    sample = sorted(set([0, len(wls) - 1] + list(rng.choice(len(wls), 6, replace=False))))
+    for m in sample:
+        Q = {k: mats[m][k].cpu().numpy() for k in "DBRT"}
+        worst, eL, eX = _check_matrix(Q, Ls[m], batch.X[m], m)
+        say(f"   matrix {m} {wls[m].name}: max rel err {worst:.3e}")
+        assert worst < TOL
+
+
+def test_failure_is_reported_per_matrix(torch_cuda):
+    torch = torch_cuda
+    from paper_2503_17528_amd import bta
+
+    shapes = [(3, 64, 2), (4, 80, 3), (2, 64, 0)]
+    Qs = [synth.make_np(synth.workload(*s), 20 + k) for k, s in enumerate(shapes)]
+    Qs[1]["D"][2][7, 7] = -1e6
+    expect = oracle.pobtaf(Qs[1]["D"], Qs[1]["B"], Qs[1]["R"], Qs[1]["T"])["info"]
+    mats = [{k: torch.from_numpy(q[k]).to("cuda") for k in "DBRT"} for q in Qs]
+    batch = bta.Batch(mats)
+    batch.factor(check=False)
+    torch.cuda.synchronize()
+    infos = [int(i.item()) for i in batch.info]
+    say(f"case batched failure: infos {infos}, expected matrix 1 -> {expect}")
+    assert infos == [0, expect, 0]

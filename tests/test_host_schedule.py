@@ -43,3 +43,18 @@ def test_factor_schedule_workload_sizes(L, n, b, a):
 @pytest.mark.parametrize("n,b,a", SHAPES + [(128, 2048, 8), (256, 4096, 16), (256, 512, 4), (33, 384, 6)])
 def test_selinv_launch_windows_in_bounds(L, n, b, a):
     assert L.bta_internal_selinv_dry_check(n, b, a) == 0
+
+
+def test_batched_factor_interleaving(L):
+    from paper_2503_17528_amd import synth
+
+    L.bta_internal_factor_batch_check.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 3
+    for seed in range(3):
+        wls = synth.batched_workloads(seed)
+        arr = lambda xs: (ctypes.c_int64 * len(xs))(*xs)
+        n = arr([w.n for w in wls]); b = arr([w.b for w in wls]); a = arr([w.a for w in wls])
+        assert L.bta_internal_factor_batch_check(len(wls), n, b, a) == 0
+    mixed = [(1, 5, 0), (3, 64, 2), (2, 130, 70), (5, 1, 1), (4, 200, 0)]
+    arr = lambda xs: (ctypes.c_int64 * len(xs))(*xs)
+    assert L.bta_internal_factor_batch_check(len(mixed), arr([m[0] for m in mixed]), arr([m[1] for m in mixed]),
+                                             arr([m[2] for m in mixed])) == 0
