@@ -128,6 +128,9 @@ hipError_t copy2d_launch(const double* src, int64_t lds, int64_t ss, double* dst
                          int rows, int cols, int nb, hipStream_t stream);
 
 int device_cu_count();
+// Library-owned side stream and reusable events of the current device.
+hipStream_t side_stream();
+hipEvent_t event_at(int k);
 
 // Host dry run: when a recorder is installed on this thread, the launchers
 // above only record what they would touch (no HIP calls).  Used to check

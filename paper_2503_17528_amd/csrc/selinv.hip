@@ -15,6 +15,9 @@
 // sequential backward sweep is then two MFMA GEMM launches per step.
 //   X_{n,n} = L_nn^{-T} L_nn^{-1} comes from the same inverse + product.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <vector>
 
 #include "bta_device.hpp"
 #include "bta_internal.hpp"
@@ -109,6 +112,39 @@ static hipError_t trtri_batched(const double* L, int64_t ldL, int64_t sL, double
   return hipSuccess;
 }
 
+// Library-owned side stream and events (one set per device, default priority,
+// created on first use; no device memory).
+namespace {
+struct DevSync {
+  hipStream_t side = nullptr;
+  std::vector<hipEvent_t> ev;
+};
+std::mutex g_sync_mu;
+std::map<int, DevSync> g_sync;
+}  // namespace
+
+hipStream_t side_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_sync_mu);
+  DevSync& d = g_sync[dev];
+  if (!d.side && hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking) != hipSuccess) d.side = nullptr;
+  return d.side;
+}
+
+hipEvent_t event_at(int k) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_sync_mu);
+  DevSync& d = g_sync[dev];
+  while ((int)d.ev.size() <= k) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    d.ev.push_back(e);
+  }
+  return d.ev[k];
+}
+
 SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a) {
   SelinvPlan sp{};
   const int64_t T = (b + 63) / 64;
@@ -160,12 +196,23 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
     BTA_TRY(gemm_launch(&p, 1, s));
   }
 
-  // ---- per-block preprocessing, chunk by chunk
-  for (int64_t i0 = 0; i0 < n; i0 += sp.chunk) {
-    const int nblk = (int)std::min<int64_t>(sp.chunk, n - i0);
+  // ---- per-block preprocessing on a side stream, chunk by chunk from the
+  // last block down, so that the backward sweep (on `s`) can start on the
+  // first finished chunk while later chunks fill the CUs the sweep leaves idle.
+  const bool dry = g_dry != nullptr;
+  hipStream_t sa = dry ? s : side_stream();
+  if (!dry) {
+    if (!sa) return hipErrorInvalidResourceHandle;
+    BTA_TRY(hipEventRecord(event_at(0), s));
+    BTA_TRY(hipStreamWaitEvent(sa, event_at(0), 0));
+  }
+  const int64_t nchunks = (n + sp.chunk - 1) / sp.chunk;
+  for (int64_t k = 0; k < nchunks; ++k) {
+    const int64_t i1 = n - k * sp.chunk, i0 = std::max<int64_t>(0, i1 - sp.chunk);
+    const int nblk = (int)(i1 - i0);
     const int nsub = (int)std::min<int64_t>(nblk, (n - 1) - i0);  // blocks of the chunk with an L_{i+1,i}
-    BTA_TRY(fill_zero_launch(Ws, (size_t)bb * nblk, s));
-    BTA_TRY(trtri_batched(LD + i0 * bb, b, bb, Ws, T1, b, bb, ib, nblk, s));
+    BTA_TRY(fill_zero_launch(Ws, (size_t)bb * nblk, sa));
+    BTA_TRY(trtri_batched(LD + i0 * bb, b, bb, Ws, T1, b, bb, ib, nblk, sa));
     GProb pr[3];
     int np = 0;
     if (nsub > 0) {  // P_B = L_{i+1,i} W_i
@@ -194,13 +241,16 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       p.store = ST_LOWER;
       pr[np++] = p;
     }
-    BTA_TRY(gemm_launch(pr, np, s));
-    BTA_TRY(copy2d_launch(Pw, b, pb, XB + i0 * bb, b, bb, ib, ib, nsub, s));
-    if (a > 0) BTA_TRY(copy2d_launch(Pw + bb, b, pb, XR + i0 * ab, b, ab, ia, ib, nblk, s));
+    BTA_TRY(gemm_launch(pr, np, sa));
+    BTA_TRY(copy2d_launch(Pw, b, pb, XB + i0 * bb, b, bb, ib, ib, nsub, sa));
+    if (a > 0) BTA_TRY(copy2d_launch(Pw + bb, b, pb, XR + i0 * ab, b, ab, ia, ib, nblk, sa));
+    if (!dry) BTA_TRY(hipEventRecord(event_at(1 + (int)k), sa));
   }
 
   // ---- backward sweep
   for (int64_t i = n - 1; i >= 0; --i) {
+    // first step of a preprocessing chunk: wait for that chunk
+    if (!dry && (n - 1 - i) % sp.chunk == 0) BTA_TRY(hipStreamWaitEvent(s, event_at(1 + (int)((n - 1 - i) / sp.chunk)), 0));
     const bool has_sub = i < n - 1;
     const double* PB = has_sub ? XB + i * bb : nullptr;
     const double* PR = a > 0 ? XR + i * ab : nullptr;
