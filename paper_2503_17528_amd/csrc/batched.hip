@@ -1,0 +1,383 @@
+// Batched selected inversion: the launch sequences of all matrices are
+// recorded as stage-keyed operations (the stage key names the position of an
+// operation in the per-matrix sequence: tip, preprocessing chunk/level, backward
+// step), operations with the same key are independent across matrices and are
+// merged into one list-driven launch, and the merged sequence is captured once
+// per descriptor set in a HIP graph and replayed.  For every merged GEMM launch
+// an autotuner picks the tile shape (64 x 64 or 128 x 128) by timing both on
+// first use of its shape class (only for stages whose outputs do not feed their
+// own inputs, so the second run reproduces the first); the choice is cached
+// per process.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bta_device.hpp"
+#include "bta_internal.hpp"
+
+#define BTA_TRY_E(x)                    \
+  do {                                  \
+    hipError_t e_ = (x);                \
+    if (e_ != hipSuccess) return e_;    \
+  } while (0)
+
+namespace bta {
+
+// ---------------------------------------------------------------- list kernels
+
+__global__ void fill_list_kernel(const FillOp* ops) {
+  const FillOp f = ops[blockIdx.y];
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < f.count; e += (long long)gridDim.x * blockDim.x)
+    f.p[e] = 0.0;
+}
+
+__global__ void copy_list_kernel(const CopyOp* ops) {
+  const CopyOp c = ops[blockIdx.y];
+  const long long per = (long long)c.rows * c.cols, total = per * c.nb;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const long long bi = e / per, rc = e - bi * per;
+    const int r = (int)(rc / c.cols), q = (int)(rc - (long long)r * c.cols);
+    c.dst[bi * c.sd + (int64_t)r * c.ldd + q] = c.src[bi * c.ss + (int64_t)r * c.lds + q];
+  }
+}
+
+// one workgroup per 64 x 64 diagonal tile of one block of one entry
+__global__ __launch_bounds__(NT) void trinv_list_kernel(const TrinvOp* ops, const long long* wg_begin, int nops) {
+  __shared__ double S[TS * LDS_LD];
+  const int tid = threadIdx.x;
+  int lo = 0, hi = nops - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wg_begin[mid] <= (long long)blockIdx.x) lo = mid; else hi = mid - 1;
+  }
+  const TrinvOp op = ops[lo];
+  const long long local = blockIdx.x - wg_begin[lo];
+  const int T = (op.m + 63) / 64;
+  const int blk = (int)(local / T), t = (int)(local - (long long)blk * T);
+  const int ext = min(64, op.m - t * 64);
+  const double* Lt = op.L + blk * op.sL + (int64_t)t * 64 * op.ldL + t * 64;
+  for (int e = tid; e < 64 * 64; e += NT) {
+    const int rr = e >> 6, cc = e & 63;
+    double v;
+    if (rr < ext && cc < ext) v = (cc <= rr) ? Lt[(int64_t)rr * op.ldL + cc] : 0.0;
+    else v = (rr == cc) ? 1.0 : 0.0;
+    S[rr * LDS_LD + cc] = v;
+  }
+  __syncthreads();
+  double w[16];
+  trinv_tile(S, w, tid);
+  const int r = tid & 63, q = tid >> 6;
+  double* Wt = op.W + blk * op.sW + (int64_t)t * 64 * op.ldW + t * 64;
+  if (r < ext) {
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) {
+      const int c = 16 * q + mm;
+      if (c < ext) Wt[(int64_t)r * op.ldW + c] = (c <= r) ? w[mm] : 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- merged plan
+
+namespace {
+
+struct StageExec {
+  int kind;           // 0 gemm, 1 fill, 2 copy, 3 trinv
+  size_t off;         // op array offset in the table region (gemm: problems with 64-tile metadata)
+  size_t off_pre;     // prefix array offset (gemm: 64-tile prefix; trinv: workgroup prefix)
+  size_t off_p128;    // gemm: problems with 128-tile metadata
+  size_t off_pre128;  // gemm: 128-tile prefix
+  int count;          // number of ops / problems
+  long long work;   // trinv: workgroups; gemm: 64-tile count
+  long long work2;  // gemm: 128-tile count
+  bool pure;        // gemm: outputs do not feed the stage's inputs (safe to run twice)
+  std::string shape;
+};
+
+struct MergedPlan {
+  std::vector<StageExec> stages;
+  std::vector<char> table;  // host image of the device table region
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <class T>
+size_t append(std::vector<char>& tab, const std::vector<T>& v) {
+  const size_t off = align256(tab.size());
+  tab.resize(off + sizeof(T) * v.size());
+  if (!v.empty()) std::memcpy(tab.data() + off, v.data(), sizeof(T) * v.size());
+  return off;
+}
+
+bool windows_overlap(const double* a0, const double* a1, const double* b0, const double* b1) { return a0 < b1 && b0 < a1; }
+
+// coarse [first, last] address span of a problem operand / output
+void span_of(const double* base, int64_t rows, int64_t cols, int64_t ld, int64_t s0, int64_t s1, int nb0, int nb1,
+             const double*& lo, const double*& hi) {
+  lo = base;
+  hi = base + (rows - 1) * ld + cols + (int64_t)(nb0 - 1) * s0 + (int64_t)(nb1 - 1) * s1;
+}
+
+bool stage_pure(const std::vector<GProb>& ps) {
+  for (const GProb& p : ps)
+    if (p.beta != 0.0) return false;
+  for (const GProb& o : ps) {
+    const double *c0, *c1;
+    span_of(o.Cout, o.store == ST_LOWER_MIRROR ? std::max(o.M, o.N) : o.M, o.store == ST_LOWER_MIRROR ? std::max(o.M, o.N) : o.N,
+            o.ldc, o.sC0, o.sC1, o.nb0, o.nb1, c0, c1);
+    for (const GProb& p : ps)
+      for (int s = 0; s < p.nseg; ++s) {
+        const GSeg& g = p.seg[s];
+        const double *a0, *a1, *b0, *b1;
+        span_of(g.A, g.at ? g.K : p.M, g.at ? p.M : g.K, g.lda, g.sA0, g.sA1, p.nb0, p.nb1, a0, a1);
+        span_of(g.B, g.bt ? g.K : p.N, g.bt ? p.N : g.K, g.ldb, g.sB0, g.sB1, p.nb0, p.nb1, b0, b1);
+        if (windows_overlap(c0, c1, a0, a1) || windows_overlap(c0, c1, b0, b1)) return false;
+      }
+  }
+  return true;
+}
+
+std::string shape_key(const std::vector<GProb>& ps) {
+  std::map<std::string, long long> hist;
+  for (const GProb& p : ps) {
+    int K = 0;
+    for (int s = 0; s < p.nseg; ++s) K += p.seg[s].K;
+    const std::string k = std::to_string(p.M) + "x" + std::to_string(p.N) + "x" + std::to_string(K) + "/" +
+                          std::to_string(p.lower_tiles) + std::to_string(p.store) + std::to_string(p.nseg);
+    hist[k] += (long long)p.nb0 * p.nb1;
+  }
+  std::string key;
+  for (auto& kv : hist) key += kv.first + "*" + std::to_string(kv.second) + ";";
+  return key;
+}
+
+MergedPlan build_plan(const StageRecorder& rec) {
+  MergedPlan mp;
+  for (const auto& kv : rec.stages) {
+    const StageRecorder::Stage& st = kv.second;
+    StageExec ex{};
+    ex.kind = st.kind;
+    if (st.kind == 0) {
+      std::vector<GProb> p64 = st.gemms, p128 = st.gemms;
+      std::vector<long long> pre64, pre128;
+      long long t64 = 0, t128 = 0;
+      for (size_t i = 0; i < p64.size(); ++i) {
+        pre64.push_back(t64);
+        t64 += gemm_prob_tiles(p64[i], 64);
+        pre128.push_back(t128);
+        t128 += gemm_prob_tiles(p128[i], 128);
+      }
+      // the same problems with both tilings: store the 64-tile and 128-tile copies
+      ex.off = append(mp.table, p64);
+      ex.off_pre = append(mp.table, pre64);
+      ex.off_p128 = append(mp.table, p128);
+      ex.off_pre128 = append(mp.table, pre128);
+      ex.count = (int)p64.size();
+      ex.work = t64;
+      ex.work2 = t128;
+      ex.pure = stage_pure(st.gemms);
+      ex.shape = shape_key(st.gemms);
+      mp.stages.push_back(ex);
+    } else if (st.kind == 1) {
+      ex.off = append(mp.table, st.fills);
+      ex.count = (int)st.fills.size();
+      mp.stages.push_back(ex);
+    } else if (st.kind == 2) {
+      ex.off = append(mp.table, st.copies);
+      ex.count = (int)st.copies.size();
+      mp.stages.push_back(ex);
+    } else if (st.kind == 3) {
+      std::vector<long long> pre;
+      long long wgs = 0;
+      for (const TrinvOp& t : st.trinvs) {
+        pre.push_back(wgs);
+        wgs += (long long)((t.m + 63) / 64) * t.nblk;
+      }
+      ex.off = append(mp.table, st.trinvs);
+      ex.off_pre = append(mp.table, pre);
+      ex.count = (int)st.trinvs.size();
+      ex.work = wgs;
+      mp.stages.push_back(ex);
+    }
+  }
+  mp.table.resize(align256(mp.table.size()));
+  return mp;
+}
+
+// ---------------------------------------------------------------- autotuner / graph cache
+
+std::mutex g_mu;
+std::map<std::string, int> g_tuned;           // shape class -> 0 (64 tiles) / 1 (128 tiles)
+std::map<std::string, hipGraphExec_t> g_graphs;  // descriptor set -> graph
+
+int heuristic_big(const StageExec& ex) { return ex.work2 >= 200 ? 1 : 0; }
+
+hipError_t launch_stage(const StageExec& ex, char* dtab, int big, hipStream_t s) {
+  switch (ex.kind) {
+    case 0: {
+      if (big)
+        return gemm_list_launch(reinterpret_cast<const GProb*>(dtab + ex.off_p128),
+                                reinterpret_cast<const long long*>(dtab + ex.off_pre128), ex.count, ex.work2, 1, s);
+      return gemm_list_launch(reinterpret_cast<const GProb*>(dtab + ex.off), reinterpret_cast<const long long*>(dtab + ex.off_pre),
+                              ex.count, ex.work, 0, s);
+    }
+    case 1:
+      hipLaunchKernelGGL(fill_list_kernel, dim3(64, (unsigned)ex.count), dim3(256), 0, s, reinterpret_cast<const FillOp*>(dtab + ex.off));
+      return hipGetLastError();
+    case 2:
+      hipLaunchKernelGGL(copy_list_kernel, dim3(64, (unsigned)ex.count), dim3(256), 0, s, reinterpret_cast<const CopyOp*>(dtab + ex.off));
+      return hipGetLastError();
+    case 3:
+      if (ex.work == 0) return hipSuccess;
+      hipLaunchKernelGGL(trinv_list_kernel, dim3((unsigned)ex.work), dim3(NT), 0, s, reinterpret_cast<const TrinvOp*>(dtab + ex.off),
+                         reinterpret_cast<const long long*>(dtab + ex.off_pre), ex.count);
+      return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+std::string tune_key(const StageExec& ex) { return ex.shape; }
+
+}  // namespace
+
+// Workspace: per-matrix selected-inversion slices, then the table region.
+struct BatchLayout {
+  std::vector<size_t> slice;
+  size_t table_off = 0, bytes = 0;
+};
+
+static BatchLayout batch_layout(int count, const int64_t* n, const int64_t* b, const int64_t* a, size_t table_bytes) {
+  BatchLayout L;
+  size_t off = 0;
+  for (int m = 0; m < count; ++m) {
+    L.slice.push_back(off);
+    off += align256(selinv_plan(n[m], b[m], a[m]).bytes);
+  }
+  L.table_off = off;
+  L.bytes = off + table_bytes;
+  return L;
+}
+
+static hipError_t record_batch(int count, const BatchMatrix* mats, char* work, const BatchLayout& L, StageRecorder& rec) {
+  g_rec = &rec;
+  hipError_t e = hipSuccess;
+  for (int m = 0; m < count && e == hipSuccess; ++m) {
+    const BatchMatrix& x = mats[m];
+    e = selinv_launch(selinv_plan(x.n, x.b, x.a), x.n, x.b, x.a, x.LD, x.LB, x.LR, x.LT, x.XD, x.XB, x.XR, x.XT,
+                      work + L.slice[m], nullptr);
+  }
+  g_rec = nullptr;
+  return e;
+}
+
+size_t selinv_batch_bytes(int count, const int64_t* n, const int64_t* b, const int64_t* a) {
+  // record with placeholder pointers to size the table region
+  std::vector<BatchMatrix> mats(count);
+  const uintptr_t G = uintptr_t(1) << 40;
+  for (int m = 0; m < count; ++m) {
+    double* base = reinterpret_cast<double*>((uintptr_t)(m + 1) * G);
+    mats[m] = BatchMatrix{n[m], b[m], a[m], nullptr, nullptr, nullptr, nullptr, base, base, base, base, base, base, base, base, nullptr};
+  }
+  BatchLayout L0 = batch_layout(count, n, b, a, 0);
+  StageRecorder rec;
+  if (record_batch(count, mats.data(), reinterpret_cast<char*>(uintptr_t(1) << 50), L0, rec) != hipSuccess) return 0;
+  const MergedPlan mp = build_plan(rec);
+  return batch_layout(count, n, b, a, mp.table.size()).bytes;
+}
+
+hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, hipStream_t stream) {
+  std::vector<int64_t> n(count), b(count), a(count);
+  for (int m = 0; m < count; ++m) { n[m] = mats[m].n; b[m] = mats[m].b; a[m] = mats[m].a; }
+  char* w = static_cast<char*>(work);
+  const BatchLayout L0 = batch_layout(count, n.data(), b.data(), a.data(), 0);
+  StageRecorder rec;
+  BTA_TRY_E(record_batch(count, mats, w, L0, rec));
+  const MergedPlan mp = build_plan(rec);
+  char* dtab = w + L0.table_off;
+  BTA_TRY_E(hipMemcpyAsync(dtab, mp.table.data(), mp.table.size(), hipMemcpyHostToDevice, stream));
+
+  // descriptor-set signature: the table image holds every pointer and size
+  std::string sig(mp.table.begin(), mp.table.end());
+  sig += std::to_string(reinterpret_cast<uintptr_t>(work));
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_graphs.find(sig);
+    if (it != g_graphs.end()) return hipGraphLaunch(it->second, stream);
+  }
+
+  // first use: run eagerly, timing both tilings of untuned pure GEMM stages
+  std::vector<int> choice(mp.stages.size(), 0);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  for (size_t k = 0; k < mp.stages.size(); ++k) {
+    const StageExec& ex = mp.stages[k];
+    if (ex.kind != 0) {
+      BTA_TRY_E(launch_stage(ex, dtab, 0, stream));
+      continue;
+    }
+    int tuned = -1;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      auto it = g_tuned.find(tune_key(ex));
+      if (it != g_tuned.end()) tuned = it->second;
+    }
+    if (tuned < 0 && ex.pure && ex.work2 > 0) {
+      if (!e0) {
+        BTA_TRY_E(hipEventCreate(&e0));
+        BTA_TRY_E(hipEventCreate(&e1));
+      }
+      float t[2] = {0.f, 0.f};
+      for (int big = 0; big < 2; ++big) {
+        BTA_TRY_E(hipEventRecord(e0, stream));
+        BTA_TRY_E(launch_stage(ex, dtab, big, stream));
+        BTA_TRY_E(hipEventRecord(e1, stream));
+        BTA_TRY_E(hipEventSynchronize(e1));
+        BTA_TRY_E(hipEventElapsedTime(&t[big], e0, e1));
+      }
+      tuned = t[1] < t[0] ? 1 : 0;
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_tuned[tune_key(ex)] = tuned;
+    } else {
+      if (tuned < 0) tuned = heuristic_big(ex);
+      BTA_TRY_E(launch_stage(ex, dtab, tuned, stream));
+    }
+    choice[k] = tuned;
+  }
+  if (e0) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); }
+
+  // capture the merged sequence for the next calls with this descriptor set
+  hipStream_t cap = capture_stream();
+  if (!cap) return hipErrorInvalidResourceHandle;
+  BTA_TRY_E(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  hipError_t ce = hipSuccess;
+  for (size_t k = 0; k < mp.stages.size() && ce == hipSuccess; ++k) ce = launch_stage(mp.stages[k], dtab, choice[k], cap);
+  hipGraph_t graph = nullptr;
+  hipError_t ee = hipStreamEndCapture(cap, &graph);
+  if (ce != hipSuccess) return ce;
+  if (ee != hipSuccess) return ee;
+  hipGraphExec_t exec = nullptr;
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return ie;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_graphs[sig] = exec;
+  return hipSuccess;
+}
+
+// Autotuner decisions recorded so far (for inspection): writes up to `cap`
+// bytes of "shape class=choice" lines.
+extern "C" __attribute__((visibility("default"))) int bta_internal_autotune_dump(char* out, int cap) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  std::string s;
+  for (auto& kv : g_tuned) s += kv.first + "=" + (kv.second ? "128" : "64") + "\n";
+  const int n = (int)std::min<size_t>(s.size(), cap > 0 ? (size_t)cap - 1 : 0);
+  if (cap > 0) {
+    std::memcpy(out, s.data(), n);
+    out[n] = 0;
+  }
+  return (int)g_tuned.size();
+}
+
+}  // namespace bta

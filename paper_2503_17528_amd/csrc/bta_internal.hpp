@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <array>
+#include <map>
 #include <vector>
 
 namespace bta {
@@ -130,6 +131,7 @@ hipError_t copy2d_launch(const double* src, int64_t lds, int64_t ss, double* dst
 int device_cu_count();
 // Library-owned side stream and reusable events of the current device.
 hipStream_t side_stream();
+hipStream_t capture_stream();
 hipEvent_t event_at(int k);
 
 // Host dry run: when a recorder is installed on this thread, the launchers
@@ -144,6 +146,45 @@ struct DryRecorder {
   std::vector<Window> windows;
 };
 extern thread_local DryRecorder* g_dry;
+
+// Stage recorder (batched selected inversion): while installed, the launchers
+// record their work under the current stage key instead of launching.
+struct FillOp { double* p; long long count; };
+struct CopyOp { const double* src; int64_t lds, ss; double* dst; int64_t ldd, sd; int rows, cols, nb; };
+struct TrinvOp { const double* L; int64_t ldL, sL; double* W; int64_t ldW, sW; int m, nblk; };
+struct StageKey {
+  int phase, major, minor;
+  bool operator<(const StageKey& o) const {
+    if (phase != o.phase) return phase < o.phase;
+    if (major != o.major) return major < o.major;
+    return minor < o.minor;
+  }
+};
+struct StageRecorder {
+  StageKey key{0, 0, 0};
+  struct Stage {
+    int kind = -1;  // 0 gemm, 1 fill, 2 copy, 3 trinv
+    std::vector<GProb> gemms;
+    std::vector<FillOp> fills;
+    std::vector<CopyOp> copies;
+    std::vector<TrinvOp> trinvs;
+  };
+  std::map<StageKey, Stage> stages;
+  void gemm(const GProb& p) { Stage& s = stages[key]; s.kind = 0; s.gemms.push_back(p); }
+  void fill(const FillOp& f) { Stage& s = stages[key]; s.kind = 1; s.fills.push_back(f); }
+  void copy(const CopyOp& c) { Stage& s = stages[key]; s.kind = 2; s.copies.push_back(c); }
+  void trinv(const TrinvOp& t) { Stage& s = stages[key]; s.kind = 3; s.trinvs.push_back(t); }
+};
+extern thread_local StageRecorder* g_rec;
+inline void set_stage(int phase, int major, int minor) {
+  if (g_rec) g_rec->key = StageKey{phase, major, minor};
+}
+inline bool recording() { return g_dry != nullptr || g_rec != nullptr; }
+
+// problem-list GEMM launch (device-resident problem array and tile prefix)
+hipError_t gemm_list_launch(const GProb* d_probs, const long long* d_tile_begin, int nprob, long long ntiles, int big,
+                            hipStream_t stream);
+long long gemm_prob_tiles(GProb& p, int tile);
 
 // Optional per-kernel timing with HIP events recorded on the launch stream
 // around each launch of the main kernels (off unless enabled).

@@ -126,13 +126,9 @@ __device__ __forceinline__ void chunk_mma(AccT<WM, WN>& acc, const double* As, c
 }
 
 template <int WM, int WN, int BK>
-__device__ __forceinline__ void gemm_tile_body(const GemmArgs& args, long long t, int tid, double* As, double* Bs) {
+__device__ __forceinline__ void gemm_tile_body(const GProb& P, long long local, int tid, double* As, double* Bs) {
   using C = GemmCfg<WM, WN, BK>;
   constexpr int TM = C::TM, TN = C::TN;
-  int j = 0;
-  while (j + 1 < args.nprob && t >= args.p[j + 1].tile_begin) ++j;
-  const GProb& P = args.p[j];
-  const long long local = t - P.tile_begin;
   const int batch = (int)(local / P.tiles_per_batch);
   const int tile = (int)(local - (long long)batch * P.tiles_per_batch);
   const int b0 = batch / P.nb1, b1 = batch - b0 * P.nb1;
@@ -243,19 +239,78 @@ __device__ __forceinline__ void gemm_tile_body(const GemmArgs& args, long long t
       }
 }
 
+__device__ __forceinline__ int find_prob(const GemmArgs& args, long long t) {
+  int j = 0;
+  while (j + 1 < args.nprob && t >= args.p[j + 1].tile_begin) ++j;
+  return j;
+}
+
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs args) {
   __shared__ double As[64 * 66];
   __shared__ double Bs[64 * 66];
-  gemm_tile_body<2, 2, 64>(args, blockIdx.x, threadIdx.x, As, Bs);
+  const int j = find_prob(args, blockIdx.x);
+  gemm_tile_body<2, 2, 64>(args.p[j], blockIdx.x - args.p[j].tile_begin, threadIdx.x, As, Bs);
 }
 
 __global__ __launch_bounds__(NT, 1) void gemm128_kernel(GemmArgs args) {
   __shared__ double As[128 * 34];
   __shared__ double Bs[128 * 34];
-  gemm_tile_body<4, 4, 32>(args, blockIdx.x, threadIdx.x, As, Bs);
+  const int j = find_prob(args, blockIdx.x);
+  gemm_tile_body<4, 4, 32>(args.p[j], blockIdx.x - args.p[j].tile_begin, threadIdx.x, As, Bs);
+}
+
+// The same tile bodies over a problem list in device memory (batched launches):
+// tile_begin[] holds the first tile of every problem.
+__device__ __forceinline__ int find_prob_list(const long long* tile_begin, int nprob, long long t) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_begin[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+__global__ __launch_bounds__(NT, 2) void gemm_list_kernel(const GProb* probs, const long long* tile_begin, int nprob) {
+  __shared__ double As[64 * 66];
+  __shared__ double Bs[64 * 66];
+  const int j = find_prob_list(tile_begin, nprob, blockIdx.x);
+  const GProb P = probs[j];
+  gemm_tile_body<2, 2, 64>(P, blockIdx.x - tile_begin[j], threadIdx.x, As, Bs);
+}
+
+__global__ __launch_bounds__(NT, 1) void gemm128_list_kernel(const GProb* probs, const long long* tile_begin, int nprob) {
+  __shared__ double As[128 * 34];
+  __shared__ double Bs[128 * 34];
+  const int j = find_prob_list(tile_begin, nprob, blockIdx.x);
+  const GProb P = probs[j];
+  gemm_tile_body<4, 4, 32>(P, blockIdx.x - tile_begin[j], threadIdx.x, As, Bs);
+}
+
+hipError_t gemm_list_launch(const GProb* d_probs, const long long* d_tile_begin, int nprob, long long ntiles, int big,
+                            hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  if (big)
+    hipLaunchKernelGGL(gemm128_list_kernel, dim3((unsigned)ntiles), dim3(NT), 0, stream, d_probs, d_tile_begin, nprob);
+  else
+    hipLaunchKernelGGL(gemm_list_kernel, dim3((unsigned)ntiles), dim3(NT), 0, stream, d_probs, d_tile_begin, nprob);
+  return hipGetLastError();
+}
+
+long long gemm_prob_tiles(GProb& p, int tile) {
+  p.ntm = (p.M + tile - 1) / tile;
+  p.ntn = (p.N + tile - 1) / tile;
+  if (p.lower_tiles) {
+    long long cnt = 0;
+    for (int tm = 0; tm < p.ntm; ++tm) cnt += std::min(p.ntn, (tm * tile + tile - 1) / tile + 1);
+    p.tiles_per_batch = (int)cnt;
+  } else {
+    p.tiles_per_batch = p.ntm * p.ntn;
+  }
+  return (long long)p.tiles_per_batch * p.nb0 * p.nb1;
 }
 
 thread_local DryRecorder* g_dry = nullptr;
+thread_local StageRecorder* g_rec = nullptr;
 
 // ---------------------------------------------------------------- kernel timer
 namespace {
@@ -273,6 +328,8 @@ bool timing_on() { return g_timer.on; }
 
 void timing_mark(int kind, bool start, hipStream_t stream) {
   if (!g_timer.on || g_timer.used >= g_timer.pool.size()) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
   const size_t e = g_timer.used++;
   (void)hipEventRecord(g_timer.pool[e], stream);
   if (start) g_timer.open_start[kind] = e;
@@ -322,6 +379,11 @@ static long long plan_tiles(GemmArgs& args, GProb* probs, int nprob, int TM, int
 }
 
 hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream) {
+  if (g_rec) {
+    for (int i = 0; i < nprob; ++i)
+      if (probs[i].M > 0 && probs[i].N > 0 && probs[i].nb0 > 0 && probs[i].nb1 > 0) g_rec->gemm(probs[i]);
+    return hipSuccess;
+  }
   if (g_dry) {
     for (int i = 0; i < nprob; ++i)
       if (probs[i].M > 0 && probs[i].N > 0) record_gemm(probs[i]);
@@ -382,6 +444,10 @@ hipError_t trinv_diag_tiles_launch(const double* L, int64_t ldL, int64_t sL, dou
                                    int m, int nblk, hipStream_t stream) {
   const int T = (m + 63) / 64;
   if (T == 0 || nblk == 0) return hipSuccess;
+  if (g_rec) {
+    g_rec->trinv(TrinvOp{L, ldL, sL, W, ldW, sW, m, nblk});
+    return hipSuccess;
+  }
   if (g_dry) {
     for (int blk = 0; blk < nblk; ++blk) {
       g_dry->windows.push_back(Window{L + blk * sL, m, m, ldL, false});
@@ -401,6 +467,10 @@ __global__ void fill_zero_kernel(double* p, size_t count) {
 
 hipError_t fill_zero_launch(double* p, size_t count, hipStream_t stream) {
   if (count == 0) return hipSuccess;
+  if (g_rec) {
+    g_rec->fill(FillOp{p, (long long)count});
+    return hipSuccess;
+  }
   if (g_dry) {
     g_dry->windows.push_back(Window{p, 1, (int64_t)count, (int64_t)count, true});
     return hipSuccess;
@@ -425,6 +495,10 @@ __global__ void copy2d_kernel(const double* src, int64_t lds, int64_t ss, double
 hipError_t copy2d_launch(const double* src, int64_t lds, int64_t ss, double* dst, int64_t ldd, int64_t sd,
                          int rows, int cols, int nb, hipStream_t stream) {
   if (rows <= 0 || cols <= 0 || nb <= 0) return hipSuccess;
+  if (g_rec) {
+    g_rec->copy(CopyOp{src, lds, ss, dst, ldd, sd, rows, cols, nb});
+    return hipSuccess;
+  }
   if (g_dry) {
     for (int b = 0; b < nb; ++b) {
       g_dry->windows.push_back(Window{src + b * ss, rows, cols, lds, false});

@@ -55,10 +55,12 @@ static GSeg seg(const double* A, int64_t lda, int at, const double* B, int64_t l
 // scratch.  64-tile inverses first, then doubling: for neighbouring groups of
 // g tiles, W21 = -W22 (L21 W11).
 static hipError_t trtri_batched(const double* L, int64_t ldL, int64_t sL, double* W, double* T1, int64_t ldW, int64_t sW,
-                                int m, int nblk, hipStream_t s) {
+                                int m, int nblk, hipStream_t s, int phase, int major) {
+  set_stage(phase, major, 1);
   BTA_TRY(trinv_diag_tiles_launch(L, ldL, sL, W, ldW, sW, m, nblk, s));
   const int T = (m + 63) / 64;
-  for (int g = 1; g < T; g *= 2) {
+  int lg = 0;
+  for (int g = 1; g < T; g *= 2, ++lg) {
     // groups start at tiles 0, 2g, 4g, ... and exist while start + g < T; all
     // but possibly the last have g + g full 64-row tiles
     const int ngroups = (T - g + 2 * g - 1) / (2 * g);
@@ -72,6 +74,7 @@ static hipError_t trtri_batched(const double* L, int64_t ldL, int64_t sL, double
     const int64_t gstepW = (int64_t)2 * g * 64 * (ldW + 1);
     GProb pr[2];
     int np = 0;
+    set_stage(phase, major, 2 + 2 * lg);
     // T1 = L21 * W11
     for (int which = 0; which < 2; ++which) {
       const int s0 = which == 0 ? 0 : s_part;
@@ -90,6 +93,7 @@ static hipError_t trtri_batched(const double* L, int64_t ldL, int64_t sL, double
     }
     BTA_TRY(gemm_launch(pr, np, s));
     np = 0;
+    set_stage(phase, major, 3 + 2 * lg);
     // W21 = -W22 * T1
     for (int which = 0; which < 2; ++which) {
       const int s0 = which == 0 ? 0 : s_part;
@@ -117,6 +121,7 @@ static hipError_t trtri_batched(const double* L, int64_t ldL, int64_t sL, double
 namespace {
 struct DevSync {
   hipStream_t side = nullptr;
+  hipStream_t capture = nullptr;
   std::vector<hipEvent_t> ev;
 };
 std::mutex g_sync_mu;
@@ -130,6 +135,15 @@ hipStream_t side_stream() {
   DevSync& d = g_sync[dev];
   if (!d.side && hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking) != hipSuccess) d.side = nullptr;
   return d.side;
+}
+
+hipStream_t capture_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_sync_mu);
+  DevSync& d = g_sync[dev];
+  if (!d.capture && hipStreamCreateWithFlags(&d.capture, hipStreamNonBlocking) != hipSuccess) d.capture = nullptr;
+  return d.capture;
 }
 
 hipEvent_t event_at(int k) {
@@ -184,8 +198,10 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
   // ---- tip: X_nn = W_T^T W_T
   if (a > 0) {
     double* WTt = WT + a * a;
+    set_stage(0, 0, 0);
     BTA_TRY(fill_zero_launch(WT, (size_t)(2 * a * a), s));
-    BTA_TRY(trtri_batched(LT, a, 0, WT, WTt, a, 0, ia, 1, s));
+    BTA_TRY(trtri_batched(LT, a, 0, WT, WTt, a, 0, ia, 1, s, 0, 0));
+    set_stage(0, 0, 100);
     GProb p = prob_init();
     p.seg[0] = seg(WT, a, 1, WT, a, 1, ia, TRI_K_GE_ROW);
     p.nseg = 1;
@@ -199,7 +215,7 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
   // ---- per-block preprocessing on a side stream, chunk by chunk from the
   // last block down, so that the backward sweep (on `s`) can start on the
   // first finished chunk while later chunks fill the CUs the sweep leaves idle.
-  const bool dry = g_dry != nullptr;
+  const bool dry = recording();
   hipStream_t sa = dry ? s : side_stream();
   if (!dry) {
     if (!sa) return hipErrorInvalidResourceHandle;
@@ -211,8 +227,10 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
     const int64_t i1 = n - k * sp.chunk, i0 = std::max<int64_t>(0, i1 - sp.chunk);
     const int nblk = (int)(i1 - i0);
     const int nsub = (int)std::min<int64_t>(nblk, (n - 1) - i0);  // blocks of the chunk with an L_{i+1,i}
+    set_stage(1, (int)k, 0);
     BTA_TRY(fill_zero_launch(Ws, (size_t)bb * nblk, sa));
-    BTA_TRY(trtri_batched(LD + i0 * bb, b, bb, Ws, T1, b, bb, ib, nblk, sa));
+    BTA_TRY(trtri_batched(LD + i0 * bb, b, bb, Ws, T1, b, bb, ib, nblk, sa, 1, (int)k));
+    set_stage(1, (int)k, 100);
     GProb pr[3];
     int np = 0;
     if (nsub > 0) {  // P_B = L_{i+1,i} W_i
@@ -242,7 +260,9 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       pr[np++] = p;
     }
     BTA_TRY(gemm_launch(pr, np, sa));
+    set_stage(1, (int)k, 101);
     BTA_TRY(copy2d_launch(Pw, b, pb, XB + i0 * bb, b, bb, ib, ib, nsub, sa));
+    set_stage(1, (int)k, 102);
     if (a > 0) BTA_TRY(copy2d_launch(Pw + bb, b, pb, XR + i0 * ab, b, ab, ia, ib, nblk, sa));
     if (!dry) BTA_TRY(hipEventRecord(event_at(1 + (int)k), sa));
   }
@@ -252,6 +272,8 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
     // first step of a preprocessing chunk: wait for that chunk
     if (!dry && (n - 1 - i) % sp.chunk == 0) BTA_TRY(hipStreamWaitEvent(s, event_at(1 + (int)((n - 1 - i) / sp.chunk)), 0));
     const bool has_sub = i < n - 1;
+    const int step = (int)(n - 1 - i);
+    set_stage(2, step, 0);
     const double* PB = has_sub ? XB + i * bb : nullptr;
     const double* PR = a > 0 ? XR + i * ab : nullptr;
     GProb pr[2];
@@ -282,6 +304,7 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       pr[np++] = p;
     }
     BTA_TRY(gemm_launch(pr, np, s));
+    set_stage(2, step, 1);
     {  // X_ii = V_i - [X_{i+1,i}; X_{n,i}]^T P_i  (lower, mirrored)
       GProb p = prob_init();
       p.nseg = 0;
@@ -294,26 +317,10 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       p.store = ST_LOWER_MIRROR;
       BTA_TRY(gemm_launch(&p, 1, s));
     }
+    set_stage(2, step, 2);
     if (has_sub) BTA_TRY(copy2d_launch(Xp, b, 0, XB + i * bb, b, 0, ib, ib, 1, s));
+    set_stage(2, step, 3);
     if (a > 0) BTA_TRY(copy2d_launch(Xp + bb, b, 0, XR + i * ab, b, 0, ia, ib, 1, s));
-  }
-  return hipSuccess;
-}
-
-// ---------------------------------------------------------------------------
-// Batched selected inversion (matrices one after another; the workspace of the
-// largest matrix is reused).
-size_t selinv_batch_bytes(int count, const int64_t* n, const int64_t* b, const int64_t* a) {
-  size_t mx = 0;
-  for (int m = 0; m < count; ++m) mx = std::max(mx, selinv_plan(n[m], b[m], a[m]).bytes);
-  return mx;
-}
-
-hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, hipStream_t stream) {
-  for (int m = 0; m < count; ++m) {
-    const BatchMatrix& x = mats[m];
-    const SelinvPlan sp = selinv_plan(x.n, x.b, x.a);
-    BTA_TRY(selinv_launch(sp, x.n, x.b, x.a, x.LD, x.LB, x.LR, x.LT, x.XD, x.XB, x.XR, x.XT, work, stream));
   }
   return hipSuccess;
 }
