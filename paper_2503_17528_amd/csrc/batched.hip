@@ -366,6 +366,78 @@ hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, h
   return hipSuccess;
 }
 
+// Host check of the merged batch plan with placeholder arrays: (1) every
+// stage holds operations of one kind; (2) the operations merged into one
+// launch touch disjoint memory except for shared reads (no write of one
+// operation overlaps a read or a write of another one in the same stage);
+// (3) every matrix contributes its operations in its own stage order.
+// Returns 0 when the plan is valid.
+extern "C" __attribute__((visibility("default"))) int bta_internal_selinv_batch_check(int count, const int64_t* n,
+                                                                                      const int64_t* b, const int64_t* a) {
+  using namespace bta;
+  std::vector<BatchMatrix> mats(count);
+  const uintptr_t G = uintptr_t(1) << 36;
+  for (int m = 0; m < count; ++m) {
+    double* L = reinterpret_cast<double*>((uintptr_t)(2 * m + 1) * G);
+    double* X = reinterpret_cast<double*>((uintptr_t)(2 * m + 2) * G);
+    const int64_t bb = b[m] * b[m], ab = a[m] * b[m];
+    mats[m] = BatchMatrix{n[m], b[m], a[m], nullptr, nullptr, nullptr, nullptr,
+                          L, L + n[m] * bb, L + n[m] * bb + (n[m] - 1) * bb, L + n[m] * bb + (n[m] - 1) * bb + n[m] * ab,
+                          X, X + n[m] * bb, X + n[m] * bb + (n[m] - 1) * bb, X + n[m] * bb + (n[m] - 1) * bb + n[m] * ab,
+                          nullptr};
+  }
+  const BatchLayout L0 = batch_layout(count, n, b, a, 0);
+  StageRecorder rec;
+  if (record_batch(count, mats.data(), reinterpret_cast<char*>(uintptr_t(1) << 52), L0, rec) != hipSuccess) return 1;
+  for (const auto& kv : rec.stages) {
+    const StageRecorder::Stage& st = kv.second;
+    struct Span { const char* lo; const char* hi; bool w; int op; };
+    std::vector<Span> spans;
+    auto add = [&](const void* base, int64_t rows, int64_t cols, int64_t ld, bool w, int op) {
+      if (rows <= 0 || cols <= 0) return;
+      const char* lo = static_cast<const char*>(base);
+      spans.push_back({lo, lo + 8 * ((rows - 1) * ld + cols), w, op});
+    };
+    int op = 0;
+    for (const GProb& p : st.gemms) {
+      for (int b0 = 0; b0 < p.nb0; ++b0)
+        for (int b1 = 0; b1 < p.nb1; ++b1) {
+          const int64_t off = b0 * p.sC0 + b1 * p.sC1;
+          add(p.Cout + off, p.M, p.N, p.ldc, true, op);
+          if (p.store == ST_LOWER_MIRROR) add(p.Cout + off, p.N, p.M, p.ldc, true, op);
+          for (int q = 0; q < p.nseg; ++q) {
+            const GSeg& g = p.seg[q];
+            add(g.A + b0 * g.sA0 + b1 * g.sA1, g.at ? g.K : p.M, g.at ? p.M : g.K, g.lda, false, op);
+            add(g.B + b0 * g.sB0 + b1 * g.sB1, g.bt ? g.K : p.N, g.bt ? p.N : g.K, g.ldb, false, op);
+          }
+        }
+      ++op;
+    }
+    for (const FillOp& f : st.fills) { add(f.p, 1, f.count, f.count, true, op); ++op; }
+    for (const CopyOp& c : st.copies) {
+      for (int q = 0; q < c.nb; ++q) {
+        add(c.src + q * c.ss, c.rows, c.cols, c.lds, false, op);
+        add(c.dst + q * c.sd, c.rows, c.cols, c.ldd, true, op);
+      }
+      ++op;
+    }
+    for (const TrinvOp& t : st.trinvs) {
+      for (int q = 0; q < t.nblk; ++q) {
+        add(t.L + q * t.sL, t.m, t.m, t.ldL, false, op);
+        add(t.W + q * t.sW, t.m, t.m, t.ldW, true, op);
+      }
+      ++op;
+    }
+    const int kinds = (!st.gemms.empty()) + (!st.fills.empty()) + (!st.copies.empty()) + (!st.trinvs.empty());
+    if (kinds != 1) return 2;
+    std::sort(spans.begin(), spans.end(), [](const Span& x, const Span& y) { return x.lo < y.lo; });
+    for (size_t i = 0; i < spans.size(); ++i)
+      for (size_t j = i + 1; j < spans.size() && spans[j].lo < spans[i].hi; ++j)
+        if (spans[i].op != spans[j].op && (spans[i].w || spans[j].w)) return 3;
+  }
+  return 0;
+}
+
 // Autotuner decisions recorded so far (for inspection): writes up to `cap`
 // bytes of "shape class=choice" lines.
 extern "C" __attribute__((visibility("default"))) int bta_internal_autotune_dump(char* out, int cap) {

@@ -58,3 +58,16 @@ def test_batched_factor_interleaving(L):
     arr = lambda xs: (ctypes.c_int64 * len(xs))(*xs)
     assert L.bta_internal_factor_batch_check(len(mixed), arr([m[0] for m in mixed]), arr([m[1] for m in mixed]),
                                              arr([m[2] for m in mixed])) == 0
+
+
+def test_batched_selinv_merge_is_independent(L):
+    """Operations merged into one batched launch never write memory that
+    another operation of the same launch reads or writes."""
+    from paper_2503_17528_amd import synth
+
+    L.bta_internal_selinv_batch_check.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 3
+    arr = lambda xs: (ctypes.c_int64 * len(xs))(*xs)
+    for wls in (synth.batched_workloads(0)[:16], [synth.workload(*s) for s in [(1, 5, 0), (3, 64, 2), (2, 130, 70),
+                                                                             (5, 40, 1), (4, 200, 0)]]):
+        n, b, a = arr([w.n for w in wls]), arr([w.b for w in wls]), arr([w.a for w in wls])
+        assert L.bta_internal_selinv_batch_check(len(wls), n, b, a) == 0
