@@ -120,16 +120,19 @@ def main():
     # timed region: K steps between synchronizations; per-kernel HIP events on the launch stream
     L.bta_internal_timing(1, 4096 * max(1, args.steps))
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps + 1)]
     t_wall0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        info = step()
-    ev1.record()
+    evs[0].record()
+    for k in range(args.steps):
+        LD, LB, LR, LT, info = bta.factor(D, B, R, T, out=outL, work=wf, check=False)
+        evs[2 * k + 1].record()
+        bta.selinv(LD, LB, LR, LT, out=outX, work=ws)
+        evs[2 * k + 2].record()
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall0
-    ms_total = ev0.elapsed_time(ev1)
+    ms_total = evs[0].elapsed_time(evs[-1])
+    ms_factor = sum(evs[2 * k].elapsed_time(evs[2 * k + 1]) for k in range(args.steps)) / args.steps
+    ms_selinv = sum(evs[2 * k + 1].elapsed_time(evs[2 * k + 2]) for k in range(args.steps)) / args.steps
     kms = (ctypes.c_double * 4)()
     kcnt = (ctypes.c_longlong * 4)()
     rd = L.bta_internal_timing_read(kms, kcnt)
@@ -185,6 +188,9 @@ def main():
         "config": {"workload": wl.name, "n": n, "b": b, "a": a, "reading": reading, "seed": args.seed,
                    "flops_per_step": fl["total"], "flops_factor": fl["factor"], "flops_selinv": fl["selinv"]},
         "pct_fp64_peak": round(100.0 * tflops / PEAK_FP64_TFLOPS, 2),
+        "phases": {"factor_ms": round(ms_factor, 3), "selinv_ms": round(ms_selinv, 3),
+                   "factor_tflops": round(fl["factor"] / (ms_factor * 1e-3) / 1e12, 3),
+                   "selinv_tflops": round(fl["selinv"] / (ms_selinv * 1e-3) / 1e12, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()} for k, v in kern.items()},

@@ -106,6 +106,28 @@ __device__ __forceinline__ void stage_zero(Stage& s) {
   for (int j = 0; j < 16; ++j) s.v[j] = 0.0;
 }
 
+// Device-coherent (agent scope, sc1) element access for data exchanged between
+// workgroups of one persistent kernel: such loads and stores do not depend on
+// the per-XCD L2 being written back or invalidated.
+__device__ __forceinline__ double ld_dev(const double* p) {
+  const unsigned long long v =
+      __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_bit_cast(double, v);
+}
+__device__ __forceinline__ void st_dev(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// stage_load for tiles produced by other workgroups of the same kernel
+__device__ __forceinline__ void stage_load_dev(Stage& s, const OpTile& t, int tid) {
+  const int m = tid >> 2, k0 = (tid & 3) * 16;
+  const double* src = t.p + (int64_t)m * t.ld + k0;
+  const bool row_ok = m < t.rows;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) s.v[j] = (row_ok && k0 + j < t.cols) ? ld_dev(src + j) : 0.0;
+}
+
 // LDS image of an operand: row m (output row or column index), k contiguous.
 __device__ __forceinline__ void stage_store(const Stage& s, double* lds, bool trans, int tid) {
   if (!trans) {
@@ -173,6 +195,20 @@ __device__ __forceinline__ void acc_load(Acc& c, const double* p, int64_t ld, in
       for (int j = 0; j < 4; ++j) {
         const int r = tile_row(tid, bi, j), q = tile_col(tid, bj);
         c.v[bi][bj][j] = (r < rows && q < cols) ? scale * p[(int64_t)r * ld + q] : 0.0;
+      }
+}
+
+// acc_store with device-coherent stores (tiles read by other workgroups of
+// the same kernel)
+__device__ __forceinline__ void acc_store_dev(const Acc& c, double* p, int64_t ld, int rows, int cols, double scale, int tid) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = tile_row(tid, bi, j), q = tile_col(tid, bj);
+        if (r < rows && q < cols) st_dev(p + (int64_t)r * ld + q, scale * c.v[bi][bj][j]);
       }
 }
 

@@ -144,7 +144,8 @@ struct Shared {
   double pivbuf[2];
   long long ticket;
   int fail;
-  int ok;
+  int ok;    // result of wait_ready
+  int upto;  // end of the run of final k tiles (k loop)
 };
 
 // One k step of a left-looking task: operand tiles and their completion flags.
@@ -358,7 +359,7 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
           for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-              acc.v[bi][bj][j] += Pi[tile_row(tid, bi, j) * 64 + tile_col(tid, bj)];
+              acc.v[bi][bj][j] += ld_dev(Pi + tile_row(tid, bi, j) * 64 + tile_col(tid, bj));
       }
     }
 
@@ -373,15 +374,16 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
       if (!wait_ready(p, s0.fa, s0.fb, sh, tid)) aborted = true;
       upto = 1;
       Stage ra, rb;
-      stage_load(ra, s0.a, tid);
-      stage_load(rb, s0.b, tid);
+      stage_load_dev(ra, s0.a, tid);
+      stage_load_dev(rb, s0.b, tid);
       for (int kk = 0; kk < nk && !aborted; ++kk) {
         __syncthreads();  // previous MFMAs are done with the LDS operands
         stage_store(ra, sh.As, false, tid);
         stage_store(rb, sh.Bs, false, tid);
-        if (tid == 0) sh.ok = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, t, kk + 1, nk) : upto;
+        if (tid == 0) sh.upto = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, t, kk + 1, nk) : upto;
         __syncthreads();
-        upto = uni(sh.ok) > upto ? uni(sh.ok) : upto;
+        const int u = uni(sh.upto);
+        upto = u > upto ? u : upto;
         if (kk + 1 < nk) {
           KSrc sn;
           ksources(p, t, kk + 1, &sn);
@@ -389,8 +391,8 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
             if (!wait_ready(p, sn.fa, sn.fb, sh, tid)) { aborted = true; }
             upto = kk + 2;
           }
-          stage_load(ra, sn.a, tid);
-          stage_load(rb, sn.b, tid);
+          stage_load_dev(ra, sn.a, tid);
+          stage_load_dev(rb, sn.b, tid);
         }
         mma_tile(acc, sh.As, sh.Bs, tid);
       }
@@ -400,7 +402,7 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
 
     // ---- finish the tile
     if (t.type == T_TUPD) {
-      acc_store(acc, out, 64, 64, 64, 1.0, 0, tid);
+      acc_store_dev(acc, out, 64, 64, 64, 1.0, tid);
     } else if (is_diag) {
       // LDS: As <- A - sum (the accumulator holds its negative); factor + invert in place
 #pragma unroll
@@ -419,8 +421,8 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
       double* Wout = (t.type == T_DIAG) ? p.Wd + ((int64_t)t.i * T + t.c) * 4096 : p.Wt + (int64_t)t.c * 4096;
       for (int e = tid; e < 64 * 64; e += NT) {
         const int rr = e >> 6, cc = e & 63;
-        if (rr < rows && cc < cols) out[(int64_t)rr * ld + cc] = sh.As[rr * LDS_LD + cc];
-        Wout[e] = sh.Bs[rr * LDS_LD + cc];
+        if (rr < rows && cc < cols) st_dev(out + (int64_t)rr * ld + cc, sh.As[rr * LDS_LD + cc]);
+        st_dev(Wout + e, sh.Bs[rr * LDS_LD + cc]);
       }
     } else {
       // X = (A - sum) W(c,c)^T
@@ -429,14 +431,14 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
       const int* fdiag = (t.type == T_TIPO) ? p.flags + fl_tip(p, t.c, t.c) : p.flags + fl_D(p, t.i, t.c, t.c);
       wait_ready(p, fdiag, fdiag, sh, tid);
       Stage rw;
-      stage_load(rw, OpTile{Wc, 64, 64, 64, false}, tid);
+      stage_load_dev(rw, OpTile{Wc, 64, 64, 64, false}, tid);
       acc_to_lds(acc, sh.As, tid);
       stage_store(rw, sh.Bs, false, tid);
       __syncthreads();
       Acc x;
       acc_zero(x);
       mma_tile(x, sh.As, sh.Bs, tid);
-      acc_store(x, out, ld, rows, cols, -1.0, 0, tid);
+      acc_store_dev(x, out, ld, rows, cols, -1.0, tid);
       // exact zeros in the mirrored (upper) tile of a diagonal block / the tip
       if (t.type == T_OFFD || t.type == T_TIPO) {
         double* up = (t.type == T_OFFD) ? p.LD + t.i * bb + (int64_t)t.c * 64 * b + t.r * 64
