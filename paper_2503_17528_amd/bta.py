@@ -78,6 +78,8 @@ def lib() -> ctypes.CDLL:
     L.bta_selinv_batched.restype = ctypes.c_int
     L.bta_status_string.argtypes = [ctypes.c_int]
     L.bta_status_string.restype = ctypes.c_char_p
+    L.bta_internal_gemm_mode.argtypes = [ctypes.c_int]
+    L.bta_internal_gemm_mode.restype = ctypes.c_int
     L.bta_last_error.argtypes = []
     L.bta_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -86,6 +88,13 @@ def lib() -> ctypes.CDLL:
 
 # ---------------------------------------------------------------- raw entry points (C names)
 
+
+
+def gemm_mode(mode: int = -1) -> int:
+    """Select the GEMM kernels of the selected inversion (0 automatic,
+    1 register-staged, 2 direct-to-LDS where the operands allow); -1 only
+    queries.  Returns the previous mode."""
+    return int(lib().bta_internal_gemm_mode(int(mode)))
 
 def bta_workspace_bytes(op: int, n: int, b: int, a: int, nrhs: int = 0) -> int:
     return int(lib().bta_workspace_bytes(op, n, b, a, nrhs))

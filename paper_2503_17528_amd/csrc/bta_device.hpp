@@ -175,6 +175,42 @@ __device__ __forceinline__ void mma_tile(Acc& c, const double* As, const double*
 }
 
 // Write the accumulator tile into LDS as a row-major 64 x 64 image (stride LDS_LD).
+// Two products sharing the left tile: c1 += A A^T and c2 += A B^T (64 x 64 x 64
+// each), one 16-wide k group at a time so that only one group of operands is
+// live in registers.
+__device__ __forceinline__ void mma_tile2(Acc& c1, Acc& c2, const double* As, const double* Bs, int tid) {
+  const int w = tid >> 6, lane = tid & 63;
+  const int r0 = 32 * (w >> 1) + (lane & 15);
+  const int c0 = 32 * (w & 1) + (lane & 15);
+  const int kl = (lane >> 4) * 4;
+#pragma unroll
+  for (int kg = 0; kg < 4; ++kg) {
+    d4 ar[2], ac[2], bc[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double* pr = As + (r0 + 16 * i) * LDS_LD + kg * 16 + kl;
+      const double* pc = As + (c0 + 16 * i) * LDS_LD + kg * 16 + kl;
+      const double* pb = Bs + (c0 + 16 * i) * LDS_LD + kg * 16 + kl;
+      const d2v r01 = *reinterpret_cast<const d2v*>(pr), r23 = *reinterpret_cast<const d2v*>(pr + 2);
+      const d2v c01 = *reinterpret_cast<const d2v*>(pc), c23 = *reinterpret_cast<const d2v*>(pc + 2);
+      const d2v b01 = *reinterpret_cast<const d2v*>(pb), b23 = *reinterpret_cast<const d2v*>(pb + 2);
+      ar[i] = d4{r01[0], r01[1], r23[0], r23[1]};
+      ac[i] = d4{c01[0], c01[1], c23[0], c23[1]};
+      bc[i] = d4{b01[0], b01[1], b23[0], b23[1]};
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          c1.v[i][j] = mfma16(ar[i][s], ac[j][s], c1.v[i][j]);
+          c2.v[i][j] = mfma16(ar[i][s], bc[j][s], c2.v[i][j]);
+        }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 __device__ __forceinline__ void acc_to_lds(const Acc& c, double* lds, int tid) {
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -321,6 +357,149 @@ __device__ int chol_inv_tile(double* S, double* Wl, double* colbuf /* [2][64] */
     Wl[r * LDS_LD + c] = (c <= r) ? w[m] : 0.0;
   }
   __syncthreads();
+  const int f = *fail_sh;
+  return f == 0x7fffffff ? 0 : f;
+}
+
+// 1/sqrt(d) from the hardware estimate refined by two Newton steps (a few
+// ulp), and sqrt(d) = d * rsqrt(d); the pivot of a positive definite tile is
+// a normal positive number, everything else is reported as a failed pivot.
+__device__ __forceinline__ double rsqrt_refined(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+  y = y * (1.5 - h * y * y);
+  y = y * (1.5 - h * y * y);
+  return y;
+}
+
+// Blocked variant of chol_inv_tile (same contract).  The tile is processed in
+// four panels of 16 columns.  Panel p lives in wave p (thread (r, q) keeps
+// row r, columns 16q .. 16q+15): wave p factors its 64 x 16 panel alone, with
+// cross-lane reads and no barrier; the panel goes to LDS; the waves to its
+// right apply the rank-16 update to their columns.  The inverse then follows
+// blockwise: the four 16 x 16 diagonal blocks are inverted in parallel (one
+// per wave), and the off-diagonal blocks come from
+// W(I,J) = -W(I,I) * sum_{K=J}^{I-1} L(I,K) W(K,J), level by level, as
+// 16 x 16 x 16 MFMA products.
+__device__ __forceinline__ void mfma_16x16x16(d4& c, const double* A, int lda, bool a_trans, const double* B, int ldb,
+                                              bool b_trans, double sign, int lane) {
+  // c += sign * op(A) * op(B)^T over k = 0..15 with op(A)(m,k) = a_trans ? A[k*lda+m] : A[m*lda+k]
+  // and op(B)(n,k) = b_trans ? B[k*ldb+n] : B[n*ldb+k]; lane supplies row/col lane%16 and k = 4*(lane/16)+s
+  const int mn = lane & 15, kb = (lane >> 4) * 4;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = kb + s;
+    const double a = a_trans ? A[k * lda + mn] : A[mn * lda + k];
+    const double b = b_trans ? B[k * ldb + mn] : B[mn * ldb + k];
+    c = mfma16(sign * a, b, c);
+  }
+}
+
+__device__ int chol_inv_tile_blocked(double* S, double* Wl, double* pan /* [64][17] */, int* fail_sh, int tid) {
+  const int r = tid & 63, q = tid >> 6;
+  double s[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) s[m] = S[r * LDS_LD + 16 * q + m];
+  if (tid == 0) *fail_sh = 0x7fffffff;
+  int fail = 0;
+  for (int p = 0; p < 4; ++p) {
+    if (q == p) {
+      // factor the 64 x 16 panel in registers
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int k = 16 * p + m;
+        const double d = rd_lane(s[m], k);
+        const bool ok = (d > 0.0) && (d <= 1.7976931348623157e308);
+        if (!ok && fail == 0) fail = k + 1;
+        const double rinv = rsqrt_refined(d);
+        const double lv = (r > k) ? s[m] * rinv : ((r == k) ? d * rinv : 0.0);
+        s[m] = lv;
+#pragma unroll
+        for (int mm = m + 1; mm < 16; ++mm) s[mm] -= lv * rd_lane(lv, 16 * p + mm);
+      }
+#pragma unroll
+      for (int m = 0; m < 16; ++m) pan[r * 17 + m] = s[m];
+    }
+    __syncthreads();
+    if (q > p) {
+      // rank-16 update of columns 16q .. 16q+15 with panel p
+      double lr[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) lr[m] = pan[r * 17 + m];
+#pragma unroll
+      for (int mm = 0; mm < 16; ++mm) {
+        const double* lc = pan + (16 * q + mm) * 17;
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) acc += lr[m] * lc[m];
+        s[mm] -= acc;
+      }
+    }
+    __syncthreads();
+  }
+  if (fail != 0 && (tid & 63) == 0) atomicMin(fail_sh, fail);
+  // L back to LDS (lower, zeros above)
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int c = 16 * q + m;
+    S[r * LDS_LD + c] = (c <= r) ? s[m] : 0.0;
+  }
+  __syncthreads();
+  // ---- W = L^{-1}: diagonal 16 x 16 blocks, one per wave (lanes 0..15 = rows)
+  {
+    const int q0 = 16 * q;
+    double w[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) w[m] = (r == m) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const double lkk = S[(q0 + k) * LDS_LD + q0 + k];
+      if (r == k) {
+        const double inv = 1.0 / lkk;
+#pragma unroll
+        for (int m = 0; m <= k; ++m) w[m] *= inv;
+      }
+      const double lrk = (r < 16) ? S[(q0 + r) * LDS_LD + q0 + k] : 0.0;
+#pragma unroll
+      for (int m = 0; m <= k; ++m) {
+        const double wk = rd_lane(w[m], k);
+        if (r > k && r < 16) w[m] -= lrk * wk;
+      }
+    }
+    // write W(Q,Q) and zero the rest of the tile's block row Q of W
+    if (r < 16) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) Wl[(q0 + r) * LDS_LD + q0 + m] = (m <= r) ? w[m] : 0.0;
+    }
+    for (int e = r; e < 16 * 64; e += 64) {
+      const int rr = q0 + (e >> 6), cc = e & 63;
+      if (cc < q0 || cc >= q0 + 16) Wl[rr * LDS_LD + cc] = 0.0;  // off-diagonal blocks are filled below (lower) or stay zero (upper)
+    }
+  }
+  __syncthreads();
+  // ---- off-diagonal blocks, level d = I - J = 1, 2, 3 (block (I, J) by wave J)
+  double* tmp = pan;  // 16 x 17 scratch per wave (pan has 64 x 17)
+  for (int d = 1; d < 4; ++d) {
+    const int J = q, I = q + d;
+    if (I < 4) {
+      const int lane = r;
+      // T = sum_{K=J}^{I-1} L(I,K) W(K,J)
+      d4 t = {0.0, 0.0, 0.0, 0.0};
+      for (int K = J; K < I; ++K)
+        mfma_16x16x16(t, S + (16 * I) * LDS_LD + 16 * K, LDS_LD, false, Wl + (16 * K) * LDS_LD + 16 * J, LDS_LD, true, 1.0, lane);
+      double* Tq = tmp + q * 16 * 17;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Tq[acc_row(lane, j) * 17 + acc_col(lane)] = t[j];
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      // W(I,J) = -W(I,I) T
+      d4 o = {0.0, 0.0, 0.0, 0.0};
+      mfma_16x16x16(o, Wl + (16 * I) * LDS_LD + 16 * I, LDS_LD, false, Tq, 17, true, -1.0, lane);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Wl[(16 * I + acc_row(lane, j)) * LDS_LD + 16 * J + acc_col(lane)] = o[j];
+    }
+    __syncthreads();
+  }
   const int f = *fail_sh;
   return f == 0x7fffffff ? 0 : f;
 }

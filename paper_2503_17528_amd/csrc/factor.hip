@@ -20,6 +20,12 @@
 // products with the inverse W of the 64 x 64 diagonal factor tile, so all the
 // arithmetic outside the diagonal tiles runs on FP64 MFMA.
 //
+// The diagonal tiles form the critical path (each needs the one before it).
+// A DIAG task therefore also computes the tile just left of its diagonal tile
+// in the band, L(g, g-1) (L_ii(c,c-1), or L_{i,i-1}(0,T-1) at c = 0), which the
+// diagonal tile needs last: the two share their left operands in one k loop,
+// and the chain of diagonal tiles takes one workgroup hop per tile.
+//
 // Workgroups take task tickets from an atomic counter in a fixed topological
 // order (column by column across the whole band), so a task only ever waits
 // for tasks with smaller tickets, which are owned by running workgroups: the
@@ -101,20 +107,24 @@ __host__ __device__ Task decode(const FactorParams& p, long long t) {
     }
     return k;
   }
-  const int Tb = has_sub ? T : 0;
+  // column c: DIAG, OFFD rows c+2 .. T-1 (row c+1 is fused into the next DIAG),
+  // SUB rows 0 .. T-1 (not row 0 of the last column: fused into the next
+  // step's first DIAG), ARW rows 0 .. TA-1
   for (int c = 0; c < T; ++c) {
-    const int g = (T - c) + Tb + TA;
+    const int nd = (c < T - 1) ? T - c - 1 : 1;
+    const int ns = has_sub ? (c == T - 1 ? T - 1 : T) : 0;
+    const int g = nd + ns + TA;
     if (rem < g) {
       k.c = c;
-      if (rem < T - c) {
+      if (rem < nd) {
         k.type = rem == 0 ? T_DIAG : T_OFFD;
-        k.r = c + (int)rem;
-      } else if (rem - (T - c) < Tb) {
+        k.r = rem == 0 ? c : c + 1 + (int)rem;
+      } else if (rem - nd < ns) {
         k.type = T_SUB;
-        k.r = (int)(rem - (T - c));
+        k.r = (int)(rem - nd) + (c == T - 1 ? 1 : 0);
       } else {
         k.type = T_ARW;
-        k.r = (int)(rem - (T - c) - Tb);
+        k.r = (int)(rem - nd - ns);
       }
       return k;
     }
@@ -140,8 +150,7 @@ __host__ __device__ inline int ext(int total, int t) { int e = total - 64 * t; r
 struct Shared {
   double As[TS * LDS_LD];
   double Bs[TS * LDS_LD];
-  double colbuf[2 * 64];
-  double pivbuf[2];
+  double pan[64 * 17];  // diagonal tile factorization workspace
   long long ticket;
   int fail;
   int ok;    // result of wait_ready
@@ -278,6 +287,149 @@ __device__ __forceinline__ void publish(int* flag, int tid) {
   if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Diagonal tile g = (block i, tile column c), fused with the tile left of it,
+// L(g, g-1).  One k loop over the k < g-1 shared by both accumulates
+//   acc1 = -(A(g,g) - sum_k L(g,k) L(g,k)^T),  acc2 = -(A(g,g-1) - sum_k L(g,k) L(g-1,k)^T);
+// then L(g,g-1) = -acc2 W(g-1)^T is stored and published, acc1 += L(g,g-1) L(g,g-1)^T,
+// and the diagonal tile is factored and inverted (L and W stored, flag published).
+__device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, Shared& sh, int tid,
+                                         unsigned long long& tr1) {
+  const int T = p.T, b = p.b;
+  const int64_t bb = (int64_t)b * b;
+  const int rows = ext(b, t.c);
+  const double* in = p.D + t.i * bb + (int64_t)t.c * 64 * b + t.c * 64;
+  double* out = p.LD + t.i * bb + (int64_t)t.c * 64 * b + t.c * 64;
+
+  // the tile left of the diagonal tile, described by the task that would produce it alone
+  const bool has_pre = t.c > 0 || t.i > 0;
+  Task pt{T_OFFD, t.i, t.c, t.c - 1};
+  const double* pin = nullptr;
+  double* pout = nullptr;
+  int prows = 0, pcols = 0;
+  int* pflag = nullptr;
+  const double* Wp = nullptr;
+  const int* fWp = nullptr;
+  if (t.c > 0) {
+    pin = p.D + t.i * bb + (int64_t)t.c * 64 * b + (t.c - 1) * 64;
+    pout = p.LD + t.i * bb + (int64_t)t.c * 64 * b + (t.c - 1) * 64;
+    prows = rows;
+    pcols = ext(b, t.c - 1);
+    pflag = p.flags + fl_D(p, t.i, t.c, t.c - 1);
+    Wp = p.Wd + ((int64_t)t.i * T + t.c - 1) * 4096;
+    fWp = p.flags + fl_D(p, t.i, t.c - 1, t.c - 1);
+  } else if (t.i > 0) {
+    pt = Task{T_SUB, t.i - 1, 0, T - 1};
+    pin = p.B + (t.i - 1) * bb + (T - 1) * 64;
+    pout = p.LB + (t.i - 1) * bb + (T - 1) * 64;
+    prows = ext(b, 0);
+    pcols = ext(b, T - 1);
+    pflag = p.flags + fl_B(p, t.i - 1, 0, T - 1);
+    Wp = p.Wd + ((int64_t)(t.i - 1) * T + T - 1) * 4096;
+    fWp = p.flags + fl_D(p, t.i - 1, T - 1, T - 1);
+  }
+
+  // accumulators; a padded diagonal tile gets -1 on the padded diagonal
+  Acc acc1, acc2;
+  acc_load(acc1, in, b, rows, rows, -1.0, tid);
+  if (rows < 64) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int rr = tile_row(tid, bi, j), cc = tile_col(tid, bj);
+          if (rr == cc && rr >= rows) acc1.v[bi][bj][j] = -1.0;
+        }
+  }
+  if (has_pre) acc_load(acc2, pin, b, prows, pcols, -1.0, tid);
+  else acc_zero(acc2);
+
+  // shared k loop (software pipelined like run_task's)
+  const int nk = has_pre ? uni(ksources(p, pt, -1, nullptr)) : 0;
+  bool aborted = false;
+  if (nk > 0) {
+    int upto = 0;
+    KSrc s0;
+    ksources(p, pt, 0, &s0);
+    if (!wait_ready(p, s0.fa, s0.fb, sh, tid)) aborted = true;
+    upto = 1;
+    Stage ra, rb;
+    stage_load_dev(ra, s0.a, tid);
+    stage_load_dev(rb, s0.b, tid);
+    for (int kk = 0; kk < nk && !aborted; ++kk) {
+      __syncthreads();
+      stage_store(ra, sh.As, false, tid);
+      stage_store(rb, sh.Bs, false, tid);
+      if (tid == 0) sh.upto = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, pt, kk + 1, nk) : upto;
+      __syncthreads();
+      const int u = uni(sh.upto);
+      upto = u > upto ? u : upto;
+      if (kk + 1 < nk) {
+        KSrc sn;
+        ksources(p, pt, kk + 1, &sn);
+        if (kk + 1 >= upto) {
+          if (!wait_ready(p, sn.fa, sn.fb, sh, tid)) aborted = true;
+          upto = kk + 2;
+        }
+        stage_load_dev(ra, sn.a, tid);
+        stage_load_dev(rb, sn.b, tid);
+      }
+      mma_tile2(acc1, acc2, sh.As, sh.Bs, tid);
+    }
+  }
+  __syncthreads();
+  if (p.trace && tid == 0) tr1 = __builtin_amdgcn_s_memrealtime();
+
+  if (has_pre) {
+    // L(g,g-1) = -acc2 W(g-1)^T
+    wait_ready(p, fWp, fWp, sh, tid);
+    Stage rw;
+    stage_load_dev(rw, OpTile{Wp, 64, 64, 64, false}, tid);
+    acc_to_lds(acc2, sh.As, tid);
+    stage_store(rw, sh.Bs, false, tid);
+    __syncthreads();
+    Acc x;  // -L(g,g-1)
+    acc_zero(x);
+    mma_tile(x, sh.As, sh.Bs, tid);
+    acc_store_dev(x, pout, b, prows, pcols, -1.0, tid);
+    if (t.c > 0) {  // exact zeros in the mirrored upper tile of the diagonal block
+      double* up = p.LD + t.i * bb + (int64_t)(t.c - 1) * 64 * b + t.c * 64;
+      for (int e = tid; e < 64 * 64; e += NT) {
+        const int rr = e >> 6, cc = e & 63;
+        if (rr < pcols && cc < prows) up[(int64_t)rr * b + cc] = 0.0;
+      }
+    }
+    __syncthreads();
+    acc_to_lds(x, sh.As, tid);
+    __syncthreads();
+    mma_tile(acc1, sh.As, sh.As, tid);  // + L(g,g-1) L(g,g-1)^T = x x^T
+    publish(pflag, tid);
+  }
+
+  // factor and invert A(g,g) - sum over all k < g (acc1 holds its negative)
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sh.As[tile_row(tid, bi, j) * LDS_LD + tile_col(tid, bj)] = -acc1.v[bi][bj][j];
+  __syncthreads();
+  const int f = uni(chol_inv_tile_blocked(sh.As, sh.Bs, sh.pan, &sh.fail, tid));
+  if (f != 0 && f <= rows && tid == 0) {
+    const long long row0 = (long long)t.i * b + (long long)t.c * 64;
+    atomicMin((unsigned long long*)p.info, (unsigned long long)(row0 + f));
+  }
+  double* Wout = p.Wd + ((int64_t)t.i * T + t.c) * 4096;
+  for (int e = tid; e < 64 * 64; e += NT) {
+    const int rr = e >> 6, cc = e & 63;
+    if (rr < rows && cc < rows) st_dev(out + (int64_t)rr * b + cc, sh.As[rr * LDS_LD + cc]);
+    st_dev(Wout + e, sh.Bs[rr * LDS_LD + cc]);
+  }
+  (void)aborted;
+  publish(p.flags + fl_D(p, t.i, t.c, t.c), tid);
+}
+
 // One task of one matrix: accumulate, finish, publish.
 __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Shared& sh, int tid) {
   {
@@ -285,6 +437,17 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
     t.type = uni(t.type); t.i = uni(t.i); t.r = uni(t.r); t.c = uni(t.c);
     unsigned long long tr0 = 0, tr1 = 0;
     if (p.trace && tid == 0) tr0 = __builtin_amdgcn_s_memrealtime();
+    if (t.type == T_DIAG) {
+      run_diag(p, t, sh, tid, tr1);
+      if (p.trace && tid == 0) {
+        unsigned long long* rec = p.trace + 4 * tk;
+        rec[0] = tr0;
+        rec[1] = tr1;
+        rec[2] = __builtin_amdgcn_s_memrealtime();
+        rec[3] = (unsigned long long)t.type | ((unsigned long long)blockIdx.x << 8);
+      }
+      return;
+    }
     const int T = p.T, b = p.b, a = p.a;
     const int64_t bb = (int64_t)b * b, ab = (int64_t)a * b;
 
@@ -327,7 +490,7 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
         my_flag = p.flags + fl_tip(p, t.r, t.c);
         break;
     }
-    const bool is_diag = (t.type == T_DIAG || t.type == T_TIPD);
+    const bool is_diag = (t.type == T_TIPD);  // DIAG tasks run in run_diag
 
     // ---- accumulator = -(input tile); a padded diagonal tile gets -1 on the padded diagonal
     Acc acc;
@@ -412,13 +575,12 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
 #pragma unroll
           for (int j = 0; j < 4; ++j) sh.As[tile_row(tid, bi, j) * LDS_LD + tile_col(tid, bj)] = -acc.v[bi][bj][j];
       __syncthreads();
-      const int f = uni(chol_inv_tile(sh.As, sh.Bs, sh.colbuf, sh.pivbuf, &sh.fail, tid));
+      const int f = uni(chol_inv_tile_blocked(sh.As, sh.Bs, sh.pan, &sh.fail, tid));
       if (f != 0 && f <= rows && tid == 0) {
-        const long long row0 = (t.type == T_DIAG) ? (long long)t.i * b + (long long)t.c * 64
-                                                  : (long long)p.n * b + (long long)t.c * 64;
+        const long long row0 = (long long)p.n * b + (long long)t.c * 64;
         atomicMin((unsigned long long*)p.info, (unsigned long long)(row0 + f));
       }
-      double* Wout = (t.type == T_DIAG) ? p.Wd + ((int64_t)t.i * T + t.c) * 4096 : p.Wt + (int64_t)t.c * 4096;
+      double* Wout = p.Wt + (int64_t)t.c * 4096;
       for (int e = tid; e < 64 * 64; e += NT) {
         const int rr = e >> 6, cc = e & 63;
         if (rr < rows && cc < cols) st_dev(out + (int64_t)rr * ld + cc, sh.As[rr * LDS_LD + cc]);
@@ -553,8 +715,10 @@ FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   fp.T = (int)T;
   fp.TA = (int)TA;
   fp.nflags = n * (2 * T * T + TA * T + TA * TA) + TA * TA;
-  fp.step_full = T * (T + 1) / 2 + T * T + T * TA + TA * (TA + 1) / 2;
-  fp.step_last = T * (T + 1) / 2 + T * TA + TA * (TA + 1) / 2;
+  // per step: DIAG + OFFD tasks T(T-1)/2 + 1 (the T-1 tiles L_ii(c+1,c) are
+  // computed by DIAG tasks), SUB T*T - 1 (L_{i+1,i}(0,T-1) likewise), ARW, TUPD
+  fp.step_full = T * (T - 1) / 2 + 1 + T * T - 1 + T * TA + TA * (TA + 1) / 2;
+  fp.step_last = T * (T - 1) / 2 + 1 + T * TA + TA * (TA + 1) / 2;
   fp.ntasks = (n - 1) * fp.step_full + fp.step_last + TA * (TA + 1) / 2;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
@@ -720,7 +884,9 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
 // Host replay of the task schedule: every ticket decodes to a distinct tile,
 // every flag a task waits on belongs to a task with a smaller ticket (so the
 // in-order ticket dispatch cannot deadlock), and every operand window lies
-// inside its array.  Returns 0 when the schedule is valid, else an error code.
+// inside its array.  counts[] receives the number of tiles of each kind (a
+// DIAG task also produces the tile left of its diagonal tile, counted under
+// OFFD or SUB).  Returns 0 when the schedule is valid, else an error code.
 int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* [7] or null */) {
   const FactorPlan fp = factor_plan(n, b, a);
   FactorParams p{};
@@ -757,6 +923,33 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
       default: f = fl_tip(p, t.r, t.c); break;
     }
     if (f < 0 || f >= fp.nflags || owner[(size_t)f] != -1) return 3;
+    if (t.type == T_DIAG && (t.c > 0 || t.i > 0)) {
+      // the fused tile L(g, g-1): its k sources, W(g-1), and its own flag
+      const Task pt = t.c > 0 ? Task{T_OFFD, t.i, t.c, t.c - 1} : Task{T_SUB, t.i - 1, 0, p.T - 1};
+      const int64_t pf = t.c > 0 ? fl_D(p, t.i, t.c, t.c - 1) : fl_B(p, t.i - 1, 0, p.T - 1);
+      const int64_t wf = t.c > 0 ? fl_D(p, t.i, t.c - 1, t.c - 1) : fl_D(p, t.i - 1, p.T - 1, p.T - 1);
+      if (pf < 0 || pf >= fp.nflags || owner[(size_t)pf] != -1) return 3;
+      const int pnk = ksources(p, pt, -1, nullptr);
+      if (pnk != ksources(p, t, -1, nullptr) - 1) return 10;
+      for (int kk = 0; kk < pnk; ++kk) {
+        KSrc s, sd;
+        ksources(p, pt, kk, &s);
+        ksources(p, t, kk, &sd);
+        if (s.a.p != sd.a.p || s.fa != sd.fa) return 10;  // shared left operand
+        const int64_t fa = s.fa - p.flags, fb = s.fb - p.flags;
+        if (fa < 0 || fa >= fp.nflags || fb < 0 || fb >= fp.nflags) return 4;
+        if (owner[(size_t)fa] < 0 || owner[(size_t)fb] < 0) return 5;
+        if (!inside(s.a) || !inside(s.b)) return 6;
+      }
+      KSrc last;
+      ksources(p, t, pnk, &last);  // the diagonal tile's last k source is the fused tile
+      if (last.fa - p.flags != pf || last.fb - p.flags != pf) return 10;
+      if (owner[(size_t)wf] < 0) return 7;
+      owner[(size_t)pf] = tk;
+      cnt[pt.type]++;
+      owner[(size_t)f] = tk;
+      continue;
+    }
     const int nk = ksources(p, t, -1, nullptr);
     for (int kk = 0; kk < nk; ++kk) {
       KSrc s;

@@ -239,6 +239,221 @@ __device__ __forceinline__ void gemm_tile_body(const GProb& P, long long local, 
       }
 }
 
+// ---------------------------------------------------------------- direct-to-LDS tile body
+// The same product with operands moved from global memory straight into LDS
+// (global_load_lds_dwordx4: each lane moves one 16-byte piece, the pieces of a
+// wave instruction land contiguously), two LDS stages of BK = 16, one barrier
+// per stage and no register staging.  Piece placement within a stage:
+//   k-contiguous operand (N): slot m*8 + (p ^ swzN(m)) holds k = 2p, 2p+1 of row m;
+//   m-contiguous operand (T): slot k*(TM/2) + (q ^ swzT(k)) holds m = 2q, 2q+1 of row k.
+// Both swizzles make the MFMA operand reads (16-byte reads of rows m for N,
+// 8-byte reads of 16 consecutive m for T) free of LDS bank conflicts.
+// Requirements (checked on the host by dl_ok): 16-byte aligned operand bases,
+// even leading dimensions and batch strides, even K, and even M (N) for a
+// transposed A (B), so that no piece straddles the edge of an operand.
+__device__ __align__(16) double g_zero_piece[2] = {0.0, 0.0};
+
+__device__ __forceinline__ int swzN(int m) { return (m ^ (m >> 3)) & 7; }
+__device__ __forceinline__ int swzT(int k) { return ((k >> 2) & 1) << 3; }
+
+__device__ __forceinline__ void load_piece_lds(const double* src, double* lds_wave) {
+  __builtin_amdgcn_global_load_lds(static_cast<const void*>(src),
+                                   (__attribute__((address_space(3))) void*)(lds_wave), 16, 0, 0);
+}
+
+template <int WM, int WN>
+struct DLCfg {
+  static constexpr int TM = 32 * WM, TN = 32 * WN, BK = 16;
+  static constexpr int SA = TM * BK, SB = TN * BK;          // doubles per stage and operand
+  static constexpr int IA = SA / 2 / NT, IB = SB / 2 / NT;  // pieces per thread per stage
+  static constexpr int STAGE = SA + SB;
+  static_assert(IA >= 1 && IB >= 1, "tile too small for the direct-load stage");
+};
+
+// One operand's pieces of stage (k .. k+kext) for the tile at row r0 (mext rows).
+template <int TR, int NI>
+__device__ __forceinline__ void stage_operand(const double* base, int64_t ld, int trans, int r0, int rext, int k,
+                                              int kext, double* dst, int wave, int lane) {
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int slot = (wave * NI + j) * 64 + lane;
+    const double* src = g_zero_piece;
+    if (!trans) {
+      const int m = slot >> 3, p = (slot & 7) ^ swzN(slot >> 3);
+      if (m < rext && 2 * p < kext) src = base + (int64_t)(r0 + m) * ld + k + 2 * p;
+    } else {
+      constexpr int PR = TR / 2;
+      const int kk = slot / PR, q = (slot % PR) ^ swzT(slot / PR);
+      if (kk < kext && 2 * q < rext) src = base + (int64_t)(k + kk) * ld + r0 + 2 * q;
+    }
+    load_piece_lds(src, dst + (wave * NI + j) * 128);
+  }
+}
+
+// Operand values of one stage for MFMA blocks i = 0..W-1 at rows r0 + 16 i + lane%16,
+// v[i][s] = X(row, 4*(lane/16) + s).
+template <int TR, int W>
+__device__ __forceinline__ void stage_read(double (&v)[W][4], const double* st, int trans, int r0, int lane) {
+  const int g = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    const int m = r0 + 16 * i + (lane & 15);
+    if (!trans) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const d2v x = *reinterpret_cast<const d2v*>(st + 2 * (m * 8 + ((2 * g + h) ^ swzN(m))));
+        v[i][2 * h] = x[0];
+        v[i][2 * h + 1] = x[1];
+      }
+    } else {
+      constexpr int PR = TR / 2;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = 4 * g + s;
+        v[i][s] = st[2 * (k * PR + ((m >> 1) ^ swzT(k))) + (m & 1)];
+      }
+    }
+  }
+}
+
+// Tile (tm, tn) of batch entry `local` of problem P; full-tile problems are
+// walked in groups of 4 tile rows, column by column, so that consecutive tiles
+// (which share an XCD, see xcd_tile) reuse A and B panels in that XCD's L2.
+template <int TM, int TN>
+__device__ __forceinline__ void tile_coords(const GProb& P, int tile, int& tm, int& tn) {
+  if (P.lower_tiles) {
+    tm = 0;
+    int rem = tile;
+    for (;;) {
+      const int w = min(P.ntn, (tm * TM + TM - 1) / TN + 1);
+      if (rem < w) break;
+      rem -= w;
+      ++tm;
+    }
+    tn = rem;
+  } else {
+    constexpr int G = 4;
+    const int grp = tile / (G * P.ntn);
+    const int rows = min(G, P.ntm - grp * G);
+    const int rem = tile - grp * G * P.ntn;
+    tm = grp * G + rem % rows;
+    tn = rem / rows;
+  }
+}
+
+template <int WM, int WN>
+__device__ __forceinline__ void gemm_tile_dl(const GProb& P, long long local, int tid, double* lds) {
+  using C = DLCfg<WM, WN>;
+  constexpr int TM = C::TM, TN = C::TN, BK = C::BK;
+  const int batch = (int)(local / P.tiles_per_batch);
+  const int tile = (int)(local - (long long)batch * P.tiles_per_batch);
+  const int b0 = batch / P.nb1, b1 = batch - b0 * P.nb1;
+  int tm, tn;
+  tile_coords<TM, TN>(P, tile, tm, tn);
+  const int m0 = tm * TM, n0 = tn * TN;
+  const int mext = min(TM, P.M - m0), next = min(TN, P.N - n0);
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+
+  // k ranges of the two segments (triangular operands clip them); plain
+  // scalars and selects, so that nothing is indexed by a run-time segment number
+  auto krange = [&](const GSeg& g, int& k0, int& k1) {
+    k0 = 0;
+    k1 = g.K;
+    switch (g.tri) {
+      case TRI_K_GE_COL: k0 = n0; break;
+      case TRI_K_GE_ROW: k0 = m0; break;
+      case TRI_K_LE_ROW: k1 = min(g.K, m0 + TM); break;
+      case TRI_K_LE_COL: k1 = min(g.K, n0 + TN); break;
+      default: break;
+    }
+    k0 = (k0 / BK) * BK;
+    if (k0 > k1) k0 = k1;
+  };
+  int kb0, ke0, kb1 = 0, ke1 = 0;
+  krange(P.seg[0], kb0, ke0);
+  if (P.nseg > 1) krange(P.seg[1], kb1, ke1);
+  const int nk0 = (ke0 - kb0 + BK - 1) / BK;
+  const int total = nk0 + (ke1 - kb1 + BK - 1) / BK;
+  const double* A0 = P.seg[0].A + b0 * P.seg[0].sA0 + b1 * P.seg[0].sA1;
+  const double* B0 = P.seg[0].B + b0 * P.seg[0].sB0 + b1 * P.seg[0].sB1;
+  const double* A1 = P.seg[1].A + b0 * P.seg[1].sA0 + b1 * P.seg[1].sA1;
+  const double* B1 = P.seg[1].B + b0 * P.seg[1].sB0 + b1 * P.seg[1].sB1;
+
+  auto issue = [&](int kk) {
+    const bool first = kk < nk0;
+    const int k = first ? kb0 + kk * BK : kb1 + (kk - nk0) * BK;
+    const int kext = min(BK, (first ? ke0 : ke1) - k);
+    double* st = lds + (kk & 1) * C::STAGE;
+    stage_operand<TM, C::IA>(first ? A0 : A1, first ? P.seg[0].lda : P.seg[1].lda, first ? P.seg[0].at : P.seg[1].at,
+                             m0, mext, k, kext, st, wave, lane);
+    stage_operand<TN, C::IB>(first ? B0 : B1, first ? P.seg[0].ldb : P.seg[1].ldb, first ? P.seg[0].bt : P.seg[1].bt,
+                             n0, next, k, kext, st + C::SA, wave, lane);
+  };
+
+  AccT<WM, WN> acc;
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int jj = 0; jj < WN; ++jj) acc.v[i][jj] = d4{0.0, 0.0, 0.0, 0.0};
+  const int rw = 16 * WM * (wave >> 1), cw = 16 * WN * (wave & 1);
+  if (total > 0) issue(0);
+  for (int kk = 0; kk < total; ++kk) {
+    // stage kk has landed for every wave, and every wave is done with stage kk-1
+    __syncthreads();
+    const bool first = kk < nk0;
+    const double* st = lds + (kk & 1) * C::STAGE;
+    double a[WM][4], b[WN][4];
+    stage_read<TM, WM>(a, st, first ? P.seg[0].at : P.seg[1].at, rw, lane);
+    stage_read<TN, WN>(b, st + C::SA, first ? P.seg[0].bt : P.seg[1].bt, cw, lane);
+    if (kk + 1 < total) issue(kk + 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < WN; ++jj) acc.v[i][jj] = mfma16(a[i][q], b[jj][q], acc.v[i][jj]);
+  }
+
+  const int64_t coff = b0 * P.sC0 + b1 * P.sC1;
+  double* Cb = P.Cout + coff;
+  const double* Cib = P.Cin ? P.Cin + coff : nullptr;
+#pragma unroll
+  for (int bi = 0; bi < WM; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < WN; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = rw + 16 * bi + acc_row(lane, e), c = cw + 16 * bj + acc_col(lane);
+        const int gr = m0 + r, gc = n0 + c;
+        double v = P.alpha * acc.v[bi][bj][e];
+        const bool live = r < mext && c < next && !(P.store != ST_FULL && gc > gr);
+        if (live && P.beta != 0.0) v += P.beta * Cib[(int64_t)gr * P.ldc + gc];
+        acc.v[bi][bj][e] = v;
+      }
+#pragma unroll
+  for (int bi = 0; bi < WM; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < WN; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = rw + 16 * bi + acc_row(lane, e), c = cw + 16 * bj + acc_col(lane);
+        const int gr = m0 + r, gc = n0 + c;
+        if (r >= mext || c >= next) continue;
+        if (P.store != ST_FULL && gc > gr) continue;
+        Cb[(int64_t)gr * P.ldc + gc] = acc.v[bi][bj][e];
+        if (P.store == ST_LOWER_MIRROR && gc < gr) Cb[(int64_t)gc * P.ldc + gr] = acc.v[bi][bj][e];
+      }
+}
+
+// Workgroups are dealt to the 8 XCDs round robin (workgroup i runs on XCD
+// i % 8); renumber them so that each XCD receives a contiguous range of tiles.
+__device__ __forceinline__ long long xcd_tile(long long bid, long long nblocks) {
+  constexpr int NX = 8;
+  const long long q = nblocks / NX, r = nblocks % NX;
+  const long long x = bid % NX, j = bid / NX;
+  return x * q + (x < r ? x : r) + j;
+}
+
 __device__ __forceinline__ int find_prob(const GemmArgs& args, long long t) {
   int j = 0;
   while (j + 1 < args.nprob && t >= args.p[j + 1].tile_begin) ++j;
@@ -257,6 +472,20 @@ __global__ __launch_bounds__(NT, 1) void gemm128_kernel(GemmArgs args) {
   __shared__ double Bs[128 * 34];
   const int j = find_prob(args, blockIdx.x);
   gemm_tile_body<4, 4, 32>(args.p[j], blockIdx.x - args.p[j].tile_begin, threadIdx.x, As, Bs);
+}
+
+__global__ __launch_bounds__(NT, 2) void gemm_dl128_kernel(GemmArgs args) {
+  __shared__ __align__(16) double lds[2 * DLCfg<4, 4>::STAGE];
+  const long long t = xcd_tile(blockIdx.x, gridDim.x);
+  const int j = find_prob(args, t);
+  gemm_tile_dl<4, 4>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
+}
+
+__global__ __launch_bounds__(NT, 4) void gemm_dl64_kernel(GemmArgs args) {
+  __shared__ __align__(16) double lds[2 * DLCfg<2, 2>::STAGE];
+  const long long t = xcd_tile(blockIdx.x, gridDim.x);
+  const int j = find_prob(args, t);
+  gemm_tile_dl<2, 2>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
 }
 
 // The same tile bodies over a problem list in device memory (batched launches):
@@ -378,6 +607,24 @@ static long long plan_tiles(GemmArgs& args, GProb* probs, int nprob, int TM, int
   return total;
 }
 
+// Operands the direct-to-LDS body can move in 16-byte pieces.
+static bool dl_ok(const GProb& p) {
+  auto al = [](const double* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+  for (int s = 0; s < p.nseg; ++s) {
+    const GSeg& g = p.seg[s];
+    if (!al(g.A) || !al(g.B)) return false;
+    if ((g.lda | g.ldb | g.sA0 | g.sA1 | g.sB0 | g.sB1) & 1) return false;
+    if (g.K & 1) return false;
+    if (g.at && (p.M & 1)) return false;
+    if (g.bt && (p.N & 1)) return false;
+  }
+  return true;
+}
+
+// 0: choose per launch; 1: register-staged kernels only; 2: direct-to-LDS
+// kernels wherever the operands allow (tests run both paths through this).
+static int g_gemm_mode = 0;
+
 hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream) {
   if (g_rec) {
     for (int i = 0; i < nprob; ++i)
@@ -389,23 +636,34 @@ hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream) {
       if (probs[i].M > 0 && probs[i].N > 0) record_gemm(probs[i]);
     return hipSuccess;
   }
-  // 128 x 128 tiles when they alone give at least ~one tile per CU and every
-  // problem is at least 128 on both sides; 64 x 64 tiles otherwise.
+  bool dl = g_gemm_mode != 1;
+  for (int i = 0; i < nprob; ++i) dl = dl && dl_ok(probs[i]);
   GemmArgs big{}, small{};
   const long long t128 = plan_tiles(big, probs, nprob, 128, 128);
-  bool use_big = t128 >= 200;
-  for (int i = 0; i < big.nprob; ++i)
-    if (big.p[i].M < 128 && big.p[i].N < 128) use_big = false;
-  if (use_big) {
+  const long long t64 = plan_tiles(small, probs, nprob, 64, 64);
+  if (t64 == 0) return hipSuccess;
+  if (dl) {
+    // makespan model: tiles are dealt evenly to the CUs, a 128-tile costs four 64-tiles
+    const long long cus = std::max(1, device_cu_count());
+    const long long c128 = 4 * ((t128 + cus - 1) / cus), c64 = (t64 + cus - 1) / cus;
     timing_mark(KT_GEMM, true, stream);
-    hipLaunchKernelGGL(gemm128_kernel, dim3((unsigned)t128), dim3(NT), 0, stream, big);
+    if (c128 <= c64)
+      hipLaunchKernelGGL(gemm_dl128_kernel, dim3((unsigned)t128), dim3(NT), 0, stream, big);
+    else
+      hipLaunchKernelGGL(gemm_dl64_kernel, dim3((unsigned)t64), dim3(NT), 0, stream, small);
     timing_mark(KT_GEMM, false, stream);
     return hipGetLastError();
   }
-  const long long t64 = plan_tiles(small, probs, nprob, 64, 64);
-  if (t64 == 0) return hipSuccess;
+  // 128 x 128 tiles when they alone give at least ~one tile per CU and every
+  // problem is at least 128 on both sides; 64 x 64 tiles otherwise.
+  bool use_big = t128 >= 200;
+  for (int i = 0; i < big.nprob; ++i)
+    if (big.p[i].M < 128 && big.p[i].N < 128) use_big = false;
   timing_mark(KT_GEMM, true, stream);
-  hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)t64), dim3(NT), 0, stream, small);
+  if (use_big)
+    hipLaunchKernelGGL(gemm128_kernel, dim3((unsigned)t128), dim3(NT), 0, stream, big);
+  else
+    hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)t64), dim3(NT), 0, stream, small);
   timing_mark(KT_GEMM, false, stream);
   return hipGetLastError();
 }
@@ -537,6 +795,14 @@ extern "C" __attribute__((visibility("default"))) int bta_internal_timing(int on
     if (hipEventCreate(&e) != hipSuccess) return 1;
   g_timer.on = true;
   return 0;
+}
+
+// Internal GEMM kernel selection (0 automatic, 1 register-staged only,
+// 2 direct-to-LDS where possible); returns the previous mode.
+extern "C" __attribute__((visibility("default"))) int bta_internal_gemm_mode(int mode) {
+  const int prev = bta::g_gemm_mode;
+  if (mode >= 0 && mode <= 2) bta::g_gemm_mode = mode;
+  return prev;
 }
 
 extern "C" __attribute__((visibility("default"))) int bta_internal_timing_read(double* ms, long long* launches) {

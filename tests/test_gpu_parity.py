@@ -71,6 +71,27 @@ def test_factor_selinv_parity(torch_cuda, n, b, a):
     _check(Lg, Xg, F, Xo, n, b, a)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("n,b,a", [(3, 384, 6), (2, 520, 8), (4, 136, 2), (2, 64, 130), (5, 192, 0)])
+def test_selinv_gemm_kernels(torch_cuda, n, b, a, mode):
+    """Both GEMM kernel families of the selected inversion (register-staged,
+    direct-to-LDS with 128 and 64 tiles) against the oracle."""
+    from paper_2503_17528_amd import bta
+
+    say(f"case selinv gemm mode={mode} n={n} b={b} a={a}")
+    wl = synth.workload(n, b, a)
+    Q = synth.make_np(wl, 4)
+    F = oracle.pobtaf(Q["D"], Q["B"], Q["R"], Q["T"])
+    Xo = oracle.pobtasi(F["LD"], F["LB"], F["LR"], F["LT"])
+    prev = bta.gemm_mode(mode)
+    try:
+        Lg, info, Xg = _run(torch_cuda, Q)
+    finally:
+        bta.gemm_mode(prev)
+    assert info == 0
+    _check(Lg, Xg, F, Xo, n, b, a)
+
+
 @pytest.mark.parametrize("n,b,a", [(4, 100, 3), (3, 64, 0), (2, 130, 70)])
 def test_inplace_matches(torch_cuda, n, b, a):
     say(f"case in-place n={n} b={b} a={a}")
