@@ -120,25 +120,75 @@ __device__ __forceinline__ void st_dev(double* p, double v) {
 }
 
 // stage_load for tiles produced by other workgroups of the same kernel
-__device__ __forceinline__ void stage_load_dev(Stage& s, const OpTile& t, int tid) {
-  const int m = tid >> 2, k0 = (tid & 3) * 16;
-  const double* src = t.p + (int64_t)m * t.ld + k0;
-  const bool row_ok = m < t.rows;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) s.v[j] = (row_ok && k0 + j < t.cols) ? ld_dev(src + j) : 0.0;
+// 16-byte device-coherent accesses through a buffer resource whose base is
+// the (wave-uniform) tile origin; sc1 makes them bypass the caches that are
+// not coherent across XCDs.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int CP_DEV = 16;  // cache policy bit sc1
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t dev_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ d2v ld_dev2(__amdgpu_buffer_rsrc_t rs, int byte_off) {
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, byte_off, 0, CP_DEV);
+  return __builtin_bit_cast(d2v, v);
+}
+__device__ __forceinline__ void st_dev2(__amdgpu_buffer_rsrc_t rs, int byte_off, d2v x) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x), rs, byte_off, 0, CP_DEV);
 }
 
-// LDS image of an operand: row m (output row or column index), k contiguous.
-__device__ __forceinline__ void stage_store(const Stage& s, double* lds, bool trans, int tid) {
-  if (!trans) {
-    const int m = tid >> 2, k0 = (tid & 3) * 16;
-    double* dst = lds + m * LDS_LD + k0;
+// Staging layout: thread tid holds rows 8 j + tid / 32 (j = 0..7), columns
+// 2 (tid % 32) and 2 (tid % 32) + 1, so that the lanes of a wave read two
+// whole rows (1 KB) per instruction.  The buffer's range is the tile's
+// extent, so pieces past it read as zero without touching memory; the
+// register masks zero the columns past a ragged edge.  Byte offsets within a
+// tile are 32-bit (leading dimensions below 2^22 doubles).
+__device__ __forceinline__ void stage_load_dev(Stage& s, const OpTile& t, int tid) {
+  const int c2 = (tid & 31) * 2, r0 = tid >> 5;
+  if (((t.ld & 1) == 0) && ((reinterpret_cast<uintptr_t>(t.p) & 15) == 0)) {
+    const int ldb = (int)t.ld * 8;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(t.p), (short)0,
+                                                                        (t.rows - 1) * ldb + t.cols * 8, 0x00020000);
+    const int off0 = r0 * ldb + c2 * 8;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) *reinterpret_cast<d2v*>(dst + 2 * j) = d2v{s.v[2 * j], s.v[2 * j + 1]};
+    for (int j = 0; j < 8; ++j) {
+      const d2v x = ld_dev2(rs, off0 + 8 * j * ldb);
+      const bool rok = 8 * j + r0 < t.rows;
+      s.v[2 * j] = (rok && c2 < t.cols) ? x[0] : 0.0;
+      s.v[2 * j + 1] = (rok && c2 + 1 < t.cols) ? x[1] : 0.0;
+    }
   } else {
-    const int k = tid >> 2, m0 = (tid & 3) * 16;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) lds[(m0 + j) * LDS_LD + k] = s.v[j];
+    for (int j = 0; j < 8; ++j) {
+      const int row = 8 * j + r0;
+      const double* src = t.p + (int64_t)row * t.ld + c2;
+      s.v[2 * j] = (row < t.rows && c2 < t.cols) ? ld_dev(src) : 0.0;
+      s.v[2 * j + 1] = (row < t.rows && c2 + 1 < t.cols) ? ld_dev(src + 1) : 0.0;
+    }
+  }
+}
+__device__ __forceinline__ void stage_store(const Stage& s, double* lds, int tid) {
+  const int c2 = (tid & 31) * 2, r0 = tid >> 5;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) *reinterpret_cast<d2v*>(lds + (8 * j + r0) * LDS_LD + c2) = d2v{s.v[2 * j], s.v[2 * j + 1]};
+}
+// Device-coherent store of the rows x cols corner of a 64 x 64 LDS tile.
+__device__ __forceinline__ void tile_store_dev(const double* lds, double* out, int64_t ld, int rows, int cols, int tid) {
+  const int c2 = (tid & 31) * 2, r0 = tid >> 5;
+  if (((cols & 1) == 0) && ((ld & 1) == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0)) {
+    const int ldb = (int)ld * 8;
+    const __amdgpu_buffer_rsrc_t rs = dev_rsrc(out);
+    const int off0 = r0 * ldb + c2 * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (8 * j + r0 < rows && c2 < cols)
+        st_dev2(rs, off0 + 8 * j * ldb, *reinterpret_cast<const d2v*>(lds + (8 * j + r0) * LDS_LD + c2));
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int row = 8 * j + r0;
+      if (row < rows && c2 < cols) st_dev(out + (int64_t)row * ld + c2, lds[row * LDS_LD + c2]);
+      if (row < rows && c2 + 1 < cols) st_dev(out + (int64_t)row * ld + c2 + 1, lds[row * LDS_LD + c2 + 1]);
+    }
   }
 }
 
@@ -370,6 +420,308 @@ __device__ __forceinline__ double rsqrt_refined(double d) {
   y = y * (1.5 - h * y * y);
   y = y * (1.5 - h * y * y);
   return y;
+}
+
+// ---------------------------------------------------------------- 64 x 64 Cholesky + inverse, MFMA-blocked
+// Broadcast of one lane's double to the whole wave: readlane (VALU, result via
+// SGPRs) or ds_bpermute (LDS crossbar, result straight in VGPRs).
+template <int BC>
+__device__ __forceinline__ double bcast(double x, int src) {
+  if (BC != 1) return rd_lane(x, src);
+  const int idx = src << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(idx, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(idx, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
+// c += sgn * A B^T for 16 x 16 blocks over 16 k, operands in LDS:
+// A(m,k) = A[m*lda + k]; B(n,k) = B[n*ldb + k] (bt false) or B[k*ldb + n] (bt true).
+// Lane l supplies row/col l%16 and k = 4*(l/16) + s for MFMA s (A rows 16-byte aligned).
+__device__ __forceinline__ void mma16x16(d4& c, const double* A, int lda, const double* B, int ldb, bool bt, double sgn,
+                                         int lane) {
+  const int mn = lane & 15, g = lane >> 4;
+  const double* pa = A + mn * lda + 4 * g;
+  const d2v a01 = *reinterpret_cast<const d2v*>(pa);
+  const d2v a23 = *reinterpret_cast<const d2v*>(pa + 2);
+  double b0, b1, b2, b3;
+  if (!bt) {
+    const double* pb = B + mn * ldb + 4 * g;
+    const d2v b01 = *reinterpret_cast<const d2v*>(pb);
+    const d2v b23 = *reinterpret_cast<const d2v*>(pb + 2);
+    b0 = b01[0]; b1 = b01[1]; b2 = b23[0]; b3 = b23[1];
+  } else {
+    const double* pb = B + (4 * g) * ldb + mn;
+    b0 = pb[0]; b1 = pb[ldb]; b2 = pb[2 * ldb]; b3 = pb[3 * ldb];
+  }
+  c = mfma16(sgn * a01[0], b0, c);
+  c = mfma16(sgn * a01[1], b1, c);
+  c = mfma16(sgn * a23[0], b2, c);
+  c = mfma16(sgn * a23[1], b3, c);
+}
+
+__device__ __forceinline__ void blk_load(d4& c, const double* X, int ld, int lane) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) c[j] = X[acc_row(lane, j) * ld + acc_col(lane)];
+}
+__device__ __forceinline__ void blk_store(const d4& c, double* X, int ld, int lane) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) X[acc_row(lane, j) * ld + acc_col(lane)] = c[j];
+}
+
+// Cholesky factor and inverse of the SPD tile S (64 x 64, LDS row stride
+// LDS_LD; only its lower triangle is read).  On return S holds L (zeros above
+// the diagonal) and Wl holds W = L^{-1} (zeros above the diagonal).  Returns 0,
+// or the 1-based column of the first pivot that is not a positive finite
+// number.  Right-looking by 16-column panels: wave p factors panel p alone
+// (lane r holds row r; pivots broadcast across the wave, no barrier), the
+// trailing lower blocks get the rank-16 update on MFMA.  W follows blockwise:
+// the four 16 x 16 diagonal inverses by column substitution (one lane per
+// column, reusing the pivots' reciprocal square roots), then the 2 x 2 block
+// recursion W21 = -W22 L21 W11, at 16 and at 32, on MFMA.
+// Scratch: rinv[64], tmp[4 * 16 * 17].
+template <int BC>
+__device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double* rinv, double* tmp, int* fail_sh, int tid) {
+  const int r = tid & 63, q = tid >> 6;
+  if (tid == 0) *fail_sh = 0x7fffffff;
+  int fail = 0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    if (q == p) {
+      double s[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) s[m] = S[r * LDS_LD + 16 * p + m];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int k = 16 * p + m;
+        const double d = rd_lane(s[m], k);
+        const bool ok = (d > 0.0) && (d <= 1.7976931348623157e308);
+        if (!ok && fail == 0) fail = k + 1;
+        const double ri = rsqrt_refined(d);
+        if (r == 0) rinv[k] = ri;
+        const double lv = (r > k) ? s[m] * ri : ((r == k) ? d * ri : 0.0);
+        s[m] = lv;
+        if (BC == 2) {
+          // column m+1 (the next pivot) by a cross-lane read; the other columns
+          // through a double-buffered LDS copy of the column (results in VGPRs,
+          // off the next pivot's critical path)
+          if (m + 1 < 16) s[m + 1] -= lv * rd_lane(lv, k + 1);
+          if (m + 2 < 16) {
+            double* cb = tmp + (m & 1) * 64;
+            cb[r] = lv;
+#pragma unroll
+            for (int mm = m + 2; mm < 16; ++mm) s[mm] -= lv * cb[16 * p + mm];
+          }
+        } else {
+#pragma unroll
+          for (int mm = m + 1; mm < 16; ++mm) s[mm] -= lv * bcast<BC>(lv, 16 * p + mm);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 16; ++m) S[r * LDS_LD + 16 * p + m] = (r >= 16 * p + m) ? s[m] : 0.0;
+    }
+    __syncthreads();
+    if (p < 3) {
+      // rank-16 update of the trailing lower blocks (I, J), p < J <= I
+      const int nb = (3 - p) * (4 - p) / 2;
+      for (int e = q; e < nb; e += 4) {
+        int J = p + 1, rem = e;
+        while (rem >= 4 - J) { rem -= 4 - J; ++J; }
+        const int I = J + rem;
+        d4 c;
+        blk_load(c, S + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
+        mma16x16(c, S + 16 * I * LDS_LD + 16 * p, LDS_LD, S + 16 * J * LDS_LD + 16 * p, LDS_LD, false, -1.0, r);
+        blk_store(c, S + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
+      }
+      __syncthreads();
+    }
+  }
+  if (fail != 0 && r == 0) atomicMin(fail_sh, fail);
+
+  // ---- W: diagonal 16 x 16 blocks, wave q inverts block q, lane j < 16 computes column j
+  {
+    const int Q = q, j = r;
+    double w[16], acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      w[i] = ((i == j ? 1.0 : 0.0) - acc[i]) * rinv[16 * Q + i];
+#pragma unroll
+      for (int i2 = i + 1; i2 < 16; ++i2) acc[i2] += S[(16 * Q + i2) * LDS_LD + 16 * Q + i] * w[i];
+    }
+    if (j < 16) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Wl[(16 * Q + i) * LDS_LD + 16 * Q + j] = (i >= j) ? w[i] : 0.0;
+    }
+    // the other blocks of block row Q: zero (the lower ones are overwritten below)
+    for (int e = r; e < 16 * 48; e += 64) {
+      const int rr = e / 48, cc = e - rr * 48;
+      const int col = cc < 16 * Q ? cc : cc + 16;
+      Wl[(16 * Q + rr) * LDS_LD + col] = 0.0;
+    }
+  }
+  __syncthreads();
+  // ---- level 16: W(1,0) = -W(1,1) L(1,0) W(0,0) (wave 0), W(3,2) = -W(3,3) L(3,2) W(2,2) (wave 1)
+  if (q < 2) {
+    const int I = 2 * q + 1, J = 2 * q;
+    double* T = tmp + q * 16 * 17;
+    d4 t = {0.0, 0.0, 0.0, 0.0};
+    mma16x16(t, S + 16 * I * LDS_LD + 16 * J, LDS_LD, Wl + 16 * J * LDS_LD + 16 * J, LDS_LD, true, 1.0, r);
+    blk_store(t, T, 17, r);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    d4 o = {0.0, 0.0, 0.0, 0.0};
+    mma16x16(o, Wl + 16 * I * LDS_LD + 16 * I, LDS_LD, T, 17, true, -1.0, r);
+    blk_store(o, Wl + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
+  }
+  __syncthreads();
+  // ---- level 32: U = L21 W11 (one 16 x 16 block per wave), then W21 = -W22 U
+  {
+    const int I = 2 + (q >> 1), J = q & 1;
+    double* U = tmp + q * 16 * 17;
+    d4 u = {0.0, 0.0, 0.0, 0.0};
+    for (int K = J; K < 2; ++K)
+      mma16x16(u, S + 16 * I * LDS_LD + 16 * K, LDS_LD, Wl + 16 * K * LDS_LD + 16 * J, LDS_LD, true, 1.0, r);
+    blk_store(u, U, 17, r);
+  }
+  __syncthreads();
+  {
+    const int I = 2 + (q >> 1), J = q & 1;
+    d4 o = {0.0, 0.0, 0.0, 0.0};
+    for (int K = 2; K <= I; ++K)
+      mma16x16(o, Wl + 16 * I * LDS_LD + 16 * K, LDS_LD, tmp + (2 * (K - 2) + J) * 16 * 17, 17, true, -1.0, r);
+    blk_store(o, Wl + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
+  }
+  __syncthreads();
+  const int f = *fail_sh;
+  return f == 0x7fffffff ? 0 : f;
+}
+
+// 1/d from the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp_refined(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, y, 1.0);
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-d, y, 1.0);
+  return __builtin_fma(y, e, y);
+}
+
+// Same contract as chol_inv_tile_mfma.  The panels are eliminated without
+// square roots: pivot k only needs 1/d_k, the Schur complement columns are
+// updated with t = a_k / d_k times the unscaled column a_k (broadcast through
+// LDS, the value for the next pivot's own row read across lanes), and the
+// finished panel is scaled by d_k^{-1/2} at the end, sixteen independent
+// reciprocal square roots instead of sixteen on the pivot chain.  The diagonal
+// blocks of W are computed left-looking, one lane per column, with the rows of
+// L read as broadcasts.
+// Scratch: rinv[64], tmp[4 * 16 * 17].
+__device__ __forceinline__ int chol_inv_tile_v4(double* S, double* Wl, double* rinv, double* tmp, int* fail_sh, int tid) {
+  const int r = tid & 63, q = tid >> 6;
+  if (tid == 0) *fail_sh = 0x7fffffff;
+  int fail = 0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    if (q == p) {
+      double s[16], dd[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) s[m] = S[r * LDS_LD + 16 * p + m];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int k = 16 * p + m;
+        double* cb = tmp + (m & 1) * 64;
+        if (m + 2 < 16) cb[r] = s[m];
+        const double d = rd_lane(s[m], k);
+        const double anext = (m + 1 < 16) ? rd_lane(s[m], k + 1) : 0.0;
+        dd[m] = d;
+        const bool ok = (d > 0.0) && (d <= 1.7976931348623157e308);
+        if (!ok && fail == 0) fail = k + 1;
+        const double t = s[m] * rcp_refined(d);
+        if (m + 1 < 16) s[m + 1] -= t * anext;
+#pragma unroll
+        for (int mm = m + 2; mm < 16; ++mm) s[mm] -= t * cb[16 * p + mm];
+      }
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const double ri = rsqrt_refined(dd[m]);
+        if (r == 0) rinv[16 * p + m] = ri;
+        S[r * LDS_LD + 16 * p + m] = (r >= 16 * p + m) ? s[m] * ri : 0.0;
+      }
+    }
+    __syncthreads();
+    if (p < 3) {
+      const int nb = (3 - p) * (4 - p) / 2;
+      for (int e = q; e < nb; e += 4) {
+        int J = p + 1, rem = e;
+        while (rem >= 4 - J) { rem -= 4 - J; ++J; }
+        const int I = J + rem;
+        d4 c;
+        blk_load(c, S + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
+        mma16x16(c, S + 16 * I * LDS_LD + 16 * p, LDS_LD, S + 16 * J * LDS_LD + 16 * p, LDS_LD, false, -1.0, r);
+        blk_store(c, S + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
+      }
+      __syncthreads();
+    }
+  }
+  if (fail != 0 && r == 0) atomicMin(fail_sh, fail);
+
+  // ---- W: diagonal 16 x 16 blocks, wave q inverts block q, lane j < 16 computes column j (left-looking)
+  {
+    const int Q = q, j = r;
+    double w[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const double* row = S + (16 * Q + i) * LDS_LD + 16 * Q;
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) {
+        if (k & 1) a1 += row[k] * w[k];
+        else a0 += row[k] * w[k];
+      }
+      w[i] = ((i == j ? 1.0 : 0.0) - (a0 + a1)) * rinv[16 * Q + i];
+    }
+    if (j < 16) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Wl[(16 * Q + i) * LDS_LD + 16 * Q + j] = (i >= j) ? w[i] : 0.0;
+    }
+    for (int e = r; e < 16 * 48; e += 64) {
+      const int rr = e / 48, cc = e - rr * 48;
+      const int col = cc < 16 * Q ? cc : cc + 16;
+      Wl[(16 * Q + rr) * LDS_LD + col] = 0.0;
+    }
+  }
+  __syncthreads();
+  if (q < 2) {
+    const int I = 2 * q + 1, J = 2 * q;
+    double* T = tmp + q * 16 * 17;
+    d4 t = {0.0, 0.0, 0.0, 0.0};
+    mma16x16(t, S + 16 * I * LDS_LD + 16 * J, LDS_LD, Wl + 16 * J * LDS_LD + 16 * J, LDS_LD, true, 1.0, r);
+    blk_store(t, T, 17, r);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    d4 o = {0.0, 0.0, 0.0, 0.0};
+    mma16x16(o, Wl + 16 * I * LDS_LD + 16 * I, LDS_LD, T, 17, true, -1.0, r);
+    blk_store(o, Wl + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
+  }
+  __syncthreads();
+  {
+    const int I = 2 + (q >> 1), J = q & 1;
+    double* U = tmp + q * 16 * 17;
+    d4 u = {0.0, 0.0, 0.0, 0.0};
+    for (int K = J; K < 2; ++K)
+      mma16x16(u, S + 16 * I * LDS_LD + 16 * K, LDS_LD, Wl + 16 * K * LDS_LD + 16 * J, LDS_LD, true, 1.0, r);
+    blk_store(u, U, 17, r);
+  }
+  __syncthreads();
+  {
+    const int I = 2 + (q >> 1), J = q & 1;
+    d4 o = {0.0, 0.0, 0.0, 0.0};
+    for (int K = 2; K <= I; ++K)
+      mma16x16(o, Wl + 16 * I * LDS_LD + 16 * K, LDS_LD, tmp + (2 * (K - 2) + J) * 16 * 17, 17, true, -1.0, r);
+    blk_store(o, Wl + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
+  }
+  __syncthreads();
+  const int f = *fail_sh;
+  return f == 0x7fffffff ? 0 : f;
 }
 
 // Blocked variant of chol_inv_tile (same contract).  The tile is processed in

@@ -56,7 +56,8 @@ struct FactorParams {
   long long ntasks;
   long long step_full, step_last;  // tasks per step (with / without SUB)
   long long spin_limit;
-  unsigned long long* trace;  // optional: 4 words per ticket (start, k loop done, end, type | workgroup << 8)
+  unsigned long long* trace;  // optional: 8 words per ticket (start, k loop done, end, type | workgroup << 8,
+                              // DIAG only: W(g-1) ready, L(g,g-1) published, tile factored)
 };
 
 struct Task {
@@ -147,10 +148,11 @@ __host__ __device__ Task decode(const FactorParams& p, long long t) {
 // Tile views of the block arrays.
 __host__ __device__ inline int ext(int total, int t) { int e = total - 64 * t; return e < 64 ? e : 64; }
 
-struct Shared {
+struct alignas(16) Shared {
   double As[TS * LDS_LD];
   double Bs[TS * LDS_LD];
   double pan[64 * 17];  // diagonal tile factorization workspace
+  double rinv[64];
   long long ticket;
   int fail;
   int ok;    // result of wait_ready
@@ -266,15 +268,20 @@ __device__ __forceinline__ bool wait_ready(const FactorParams& p, const int* f1,
   return uni(sh.ok) != 0;
 }
 
-// Thread 0: extend the run of consecutive final k tiles starting at `from`
-// without blocking; one acquire fence covers every tile it adds.
-__device__ __forceinline__ int extend_ready(const FactorParams& p, const Task& t, int from, int nk) {
-  int upto = from;
-  while (upto < nk) {
+// Wave 0: extend the run of consecutive final k tiles starting at `from`
+// without blocking.  Lane l polls the flags of k tile from + l, so one round
+// trip covers up to 64 tiles; one acquire fence covers every tile added.
+__device__ __forceinline__ int extend_ready(const FactorParams& p, const Task& t, int from, int nk, int lane) {
+  const int kk = from + lane;
+  bool ready = false;
+  if (kk < nk) {
     KSrc s2;
-    ksources(p, t, upto, &s2);
-    if (flag_set(s2.fa) && flag_set(s2.fb)) ++upto; else break;
+    ksources(p, t, kk, &s2);
+    ready = flag_set(s2.fa) && flag_set(s2.fb);
   }
+  const unsigned long long m = __builtin_amdgcn_ballot_w64(ready);
+  const int run = (~m == 0ULL) ? 64 : __builtin_ctzll(~m);
+  const int upto = from + run;
   if (upto > from) acquire_fence();
   return upto;
 }
@@ -293,7 +300,7 @@ __device__ __forceinline__ void publish(int* flag, int tid) {
 // then L(g,g-1) = -acc2 W(g-1)^T is stored and published, acc1 += L(g,g-1) L(g,g-1)^T,
 // and the diagonal tile is factored and inverted (L and W stored, flag published).
 __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, Shared& sh, int tid,
-                                         unsigned long long& tr1) {
+                                         unsigned long long& tr1, unsigned long long* rec) {
   const int T = p.T, b = p.b;
   const int64_t bb = (int64_t)b * b;
   const int rows = ext(b, t.c);
@@ -359,9 +366,12 @@ __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, S
     stage_load_dev(rb, s0.b, tid);
     for (int kk = 0; kk < nk && !aborted; ++kk) {
       __syncthreads();
-      stage_store(ra, sh.As, false, tid);
-      stage_store(rb, sh.Bs, false, tid);
-      if (tid == 0) sh.upto = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, pt, kk + 1, nk) : upto;
+      stage_store(ra, sh.As, tid);
+      stage_store(rb, sh.Bs, tid);
+      if (tid < 64) {
+        const int u = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, pt, kk + 1, nk, tid) : upto;
+        if (tid == 0) sh.upto = u;
+      }
       __syncthreads();
       const int u = uni(sh.upto);
       upto = u > upto ? u : upto;
@@ -379,15 +389,19 @@ __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, S
     }
   }
   __syncthreads();
-  if (p.trace && tid == 0) tr1 = __builtin_amdgcn_s_memrealtime();
+  if (rec && tid == 0) tr1 = __builtin_amdgcn_s_memrealtime();
+  // the rest of this task is the critical path of the factorization: let its
+  // waves win the issue arbitration against another workgroup on this CU
+  __builtin_amdgcn_s_setprio(3);
 
   if (has_pre) {
     // L(g,g-1) = -acc2 W(g-1)^T
     wait_ready(p, fWp, fWp, sh, tid);
+    if (rec && tid == 0) rec[4] = __builtin_amdgcn_s_memrealtime();
     Stage rw;
     stage_load_dev(rw, OpTile{Wp, 64, 64, 64, false}, tid);
     acc_to_lds(acc2, sh.As, tid);
-    stage_store(rw, sh.Bs, false, tid);
+    stage_store(rw, sh.Bs, tid);
     __syncthreads();
     Acc x;  // -L(g,g-1)
     acc_zero(x);
@@ -405,6 +419,7 @@ __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, S
     __syncthreads();
     mma_tile(acc1, sh.As, sh.As, tid);  // + L(g,g-1) L(g,g-1)^T = x x^T
     publish(pflag, tid);
+    if (rec && tid == 0) rec[5] = __builtin_amdgcn_s_memrealtime();
   }
 
   // factor and invert A(g,g) - sum over all k < g (acc1 holds its negative)
@@ -415,19 +430,18 @@ __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, S
 #pragma unroll
       for (int j = 0; j < 4; ++j) sh.As[tile_row(tid, bi, j) * LDS_LD + tile_col(tid, bj)] = -acc1.v[bi][bj][j];
   __syncthreads();
-  const int f = uni(chol_inv_tile_blocked(sh.As, sh.Bs, sh.pan, &sh.fail, tid));
+  const int f = uni(chol_inv_tile_mfma<2>(sh.As, sh.Bs, sh.rinv, sh.pan, &sh.fail, tid));
+  if (rec && tid == 0) rec[6] = __builtin_amdgcn_s_memrealtime();
   if (f != 0 && f <= rows && tid == 0) {
     const long long row0 = (long long)t.i * b + (long long)t.c * 64;
     atomicMin((unsigned long long*)p.info, (unsigned long long)(row0 + f));
   }
   double* Wout = p.Wd + ((int64_t)t.i * T + t.c) * 4096;
-  for (int e = tid; e < 64 * 64; e += NT) {
-    const int rr = e >> 6, cc = e & 63;
-    if (rr < rows && cc < rows) st_dev(out + (int64_t)rr * b + cc, sh.As[rr * LDS_LD + cc]);
-    st_dev(Wout + e, sh.Bs[rr * LDS_LD + cc]);
-  }
+  tile_store_dev(sh.Bs, Wout, 64, 64, 64, tid);
+  tile_store_dev(sh.As, out, b, rows, rows, tid);
   (void)aborted;
   publish(p.flags + fl_D(p, t.i, t.c, t.c), tid);
+  __builtin_amdgcn_s_setprio(0);
 }
 
 // One task of one matrix: accumulate, finish, publish.
@@ -438,9 +452,9 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
     unsigned long long tr0 = 0, tr1 = 0;
     if (p.trace && tid == 0) tr0 = __builtin_amdgcn_s_memrealtime();
     if (t.type == T_DIAG) {
-      run_diag(p, t, sh, tid, tr1);
-      if (p.trace && tid == 0) {
-        unsigned long long* rec = p.trace + 4 * tk;
+      unsigned long long* rec = p.trace ? p.trace + 8 * tk : nullptr;
+      run_diag(p, t, sh, tid, tr1, rec);
+      if (rec && tid == 0) {
         rec[0] = tr0;
         rec[1] = tr1;
         rec[2] = __builtin_amdgcn_s_memrealtime();
@@ -541,9 +555,12 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
       stage_load_dev(rb, s0.b, tid);
       for (int kk = 0; kk < nk && !aborted; ++kk) {
         __syncthreads();  // previous MFMAs are done with the LDS operands
-        stage_store(ra, sh.As, false, tid);
-        stage_store(rb, sh.Bs, false, tid);
-        if (tid == 0) sh.upto = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, t, kk + 1, nk) : upto;
+        stage_store(ra, sh.As, tid);
+        stage_store(rb, sh.Bs, tid);
+        if (tid < 64) {
+          const int u = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, t, kk + 1, nk, tid) : upto;
+          if (tid == 0) sh.upto = u;
+        }
         __syncthreads();
         const int u = uni(sh.upto);
         upto = u > upto ? u : upto;
@@ -575,17 +592,14 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
 #pragma unroll
           for (int j = 0; j < 4; ++j) sh.As[tile_row(tid, bi, j) * LDS_LD + tile_col(tid, bj)] = -acc.v[bi][bj][j];
       __syncthreads();
-      const int f = uni(chol_inv_tile_blocked(sh.As, sh.Bs, sh.pan, &sh.fail, tid));
+      const int f = uni(chol_inv_tile_mfma<2>(sh.As, sh.Bs, sh.rinv, sh.pan, &sh.fail, tid));
       if (f != 0 && f <= rows && tid == 0) {
         const long long row0 = (long long)p.n * b + (long long)t.c * 64;
         atomicMin((unsigned long long*)p.info, (unsigned long long)(row0 + f));
       }
       double* Wout = p.Wt + (int64_t)t.c * 4096;
-      for (int e = tid; e < 64 * 64; e += NT) {
-        const int rr = e >> 6, cc = e & 63;
-        if (rr < rows && cc < cols) st_dev(out + (int64_t)rr * ld + cc, sh.As[rr * LDS_LD + cc]);
-        st_dev(Wout + e, sh.Bs[rr * LDS_LD + cc]);
-      }
+      tile_store_dev(sh.Bs, Wout, 64, 64, 64, tid);
+      tile_store_dev(sh.As, out, ld, rows, cols, tid);
     } else {
       // X = (A - sum) W(c,c)^T
       const double* Wc = (t.type == T_TIPO) ? p.Wt + (int64_t)t.c * 4096
@@ -595,7 +609,7 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
       Stage rw;
       stage_load_dev(rw, OpTile{Wc, 64, 64, 64, false}, tid);
       acc_to_lds(acc, sh.As, tid);
-      stage_store(rw, sh.Bs, false, tid);
+      stage_store(rw, sh.Bs, tid);
       __syncthreads();
       Acc x;
       acc_zero(x);
@@ -614,7 +628,7 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
     }
     publish(my_flag, tid);
     if (p.trace && tid == 0) {
-      unsigned long long* rec = p.trace + 4 * tk;
+      unsigned long long* rec = p.trace + 8 * tk;
       rec[0] = tr0;
       rec[1] = tr1;
       rec[2] = __builtin_amdgcn_s_memrealtime();
@@ -623,8 +637,8 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
   }
 }
 
-__global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
-  __shared__ Shared sh;
+// Persistent workers: take tickets until the task list is exhausted.
+__device__ __forceinline__ void factor_worker(const FactorParams& p, Shared& sh) {
   const int tid = threadIdx.x;
   for (;;) {
     if (tid == 0) sh.ticket = (long long)atomicAdd((unsigned long long*)p.ctl, 1ULL);
@@ -633,6 +647,20 @@ __global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
     if (tk >= p.ntasks) break;
     run_task(p, tk, sh, tid);
   }
+}
+
+__global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
+  __shared__ Shared sh;
+  factor_worker(p, sh);
+}
+
+// One workgroup per CU: launched with extra dynamic LDS (SOLO_LDS_PAD bytes)
+// so that no second workgroup fits on the CU, and the diagonal tiles (the
+// critical path) do not share their SIMDs with the MFMA work of another task.
+constexpr size_t SOLO_LDS_PAD = 8192;
+__global__ __launch_bounds__(NT, 1) void factor_kernel_solo(FactorParams p) {
+  __shared__ Shared sh;
+  factor_worker(p, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -708,6 +736,9 @@ __global__ void factor_finish_kernel(const int* ctl, int64_t* info) {
   }
 }
 
+// workgroups per CU of the single-matrix factor kernel (1 or 2)
+static int g_factor_occ = 2;
+
 // ---------------------------------------------------------------------------
 FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   FactorPlan fp{};
@@ -755,9 +786,12 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
   hipLaunchKernelGGL(factor_reset_kernel, dim3(rgrid), dim3(256), 0, stream, p.flags, fp.nflags, p.ctl, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const long long grid = std::min<long long>(fp.ntasks, 2LL * num_cus);
+  const long long grid = std::min<long long>(fp.ntasks, (long long)g_factor_occ * num_cus);
   timing_mark(KT_FACTOR, true, stream);
-  hipLaunchKernelGGL(factor_kernel, dim3((unsigned)grid), dim3(NT), 0, stream, p);
+  if (g_factor_occ == 1)
+    hipLaunchKernelGGL(factor_kernel_solo, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, p);
+  else
+    hipLaunchKernelGGL(factor_kernel, dim3((unsigned)grid), dim3(NT), 0, stream, p);
   timing_mark(KT_FACTOR, false, stream);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -981,7 +1015,7 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
 
 }  // namespace bta
 
-// bta_factor with a per-task trace buffer of 4 * ntasks words (device memory);
+// bta_factor with a per-task trace buffer of 8 * ntasks words (device memory);
 // the number of tasks is returned through *ntasks when the pointer is set.
 extern "C" __attribute__((visibility("default"))) int bta_internal_factor_traced(
     int64_t n, int64_t b, int64_t a, const double* D, const double* B, const double* R, const double* T, double* LD,
@@ -1020,6 +1054,13 @@ extern "C" __attribute__((visibility("default"))) int bta_internal_factor_batch_
   for (int m = 0; m < count; ++m)
     if (next[m] != bp.plans[m].ntasks) return 3;
   return 0;
+}
+
+// Internal: workgroups per CU of the factor kernel (1 or 2); returns the previous value.
+extern "C" __attribute__((visibility("default"))) int bta_internal_factor_occupancy(int occ) {
+  const int prev = bta::g_factor_occ;
+  if (occ == 1 || occ == 2) bta::g_factor_occ = occ;
+  return prev;
 }
 
 extern "C" __attribute__((visibility("default"))) int bta_internal_factor_schedule_check(int64_t n, int64_t b, int64_t a,
