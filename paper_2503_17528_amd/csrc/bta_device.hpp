@@ -120,50 +120,18 @@ __device__ __forceinline__ void st_dev(double* p, double v) {
 }
 
 // stage_load for tiles produced by other workgroups of the same kernel
-// 16-byte device-coherent accesses through a buffer resource whose base is
-// the (wave-uniform) tile origin; sc1 makes them bypass the caches that are
-// not coherent across XCDs.
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-constexpr int CP_DEV = 16;  // cache policy bit sc1
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t dev_rsrc(const void* p) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7fffffff, 0x00020000);
-}
-__device__ __forceinline__ d2v ld_dev2(__amdgpu_buffer_rsrc_t rs, int byte_off) {
-  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, byte_off, 0, CP_DEV);
-  return __builtin_bit_cast(d2v, v);
-}
-__device__ __forceinline__ void st_dev2(__amdgpu_buffer_rsrc_t rs, int byte_off, d2v x) {
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x), rs, byte_off, 0, CP_DEV);
-}
-
 // Staging layout: thread tid holds rows 8 j + tid / 32 (j = 0..7), columns
-// 2 (tid % 32) and 2 (tid % 32) + 1, so that the lanes of a wave read two
-// whole rows (1 KB) per instruction.  The buffer's range is the tile's
-// extent, so pieces past it read as zero without touching memory; the
-// register masks zero the columns past a ragged edge.  Byte offsets within a
-// tile are 32-bit (leading dimensions below 2^22 doubles).
+// 2 (tid % 32) and 2 (tid % 32) + 1, so that the 64 lanes of a wave cover two
+// whole rows (eight 128-byte lines) per load instruction.  Device-coherent
+// 8-byte accesses; elements past a ragged edge read as zero.
 __device__ __forceinline__ void stage_load_dev(Stage& s, const OpTile& t, int tid) {
   const int c2 = (tid & 31) * 2, r0 = tid >> 5;
-  if (((t.ld & 1) == 0) && ((reinterpret_cast<uintptr_t>(t.p) & 15) == 0)) {
-    const int ldb = (int)t.ld * 8;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(t.p), (short)0,
-                                                                        (t.rows - 1) * ldb + t.cols * 8, 0x00020000);
-    const int off0 = r0 * ldb + c2 * 8;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const d2v x = ld_dev2(rs, off0 + 8 * j * ldb);
-      const bool rok = 8 * j + r0 < t.rows;
-      s.v[2 * j] = (rok && c2 < t.cols) ? x[0] : 0.0;
-      s.v[2 * j + 1] = (rok && c2 + 1 < t.cols) ? x[1] : 0.0;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int row = 8 * j + r0;
-      const double* src = t.p + (int64_t)row * t.ld + c2;
-      s.v[2 * j] = (row < t.rows && c2 < t.cols) ? ld_dev(src) : 0.0;
-      s.v[2 * j + 1] = (row < t.rows && c2 + 1 < t.cols) ? ld_dev(src + 1) : 0.0;
-    }
+  for (int j = 0; j < 8; ++j) {
+    const int row = 8 * j + r0;
+    const double* src = t.p + (int64_t)row * t.ld + c2;
+    s.v[2 * j] = (row < t.rows && c2 < t.cols) ? ld_dev(src) : 0.0;
+    s.v[2 * j + 1] = (row < t.rows && c2 + 1 < t.cols) ? ld_dev(src + 1) : 0.0;
   }
 }
 __device__ __forceinline__ void stage_store(const Stage& s, double* lds, int tid) {
@@ -174,21 +142,11 @@ __device__ __forceinline__ void stage_store(const Stage& s, double* lds, int tid
 // Device-coherent store of the rows x cols corner of a 64 x 64 LDS tile.
 __device__ __forceinline__ void tile_store_dev(const double* lds, double* out, int64_t ld, int rows, int cols, int tid) {
   const int c2 = (tid & 31) * 2, r0 = tid >> 5;
-  if (((cols & 1) == 0) && ((ld & 1) == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0)) {
-    const int ldb = (int)ld * 8;
-    const __amdgpu_buffer_rsrc_t rs = dev_rsrc(out);
-    const int off0 = r0 * ldb + c2 * 8;
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (8 * j + r0 < rows && c2 < cols)
-        st_dev2(rs, off0 + 8 * j * ldb, *reinterpret_cast<const d2v*>(lds + (8 * j + r0) * LDS_LD + c2));
-  } else {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int row = 8 * j + r0;
-      if (row < rows && c2 < cols) st_dev(out + (int64_t)row * ld + c2, lds[row * LDS_LD + c2]);
-      if (row < rows && c2 + 1 < cols) st_dev(out + (int64_t)row * ld + c2 + 1, lds[row * LDS_LD + c2 + 1]);
-    }
+  for (int j = 0; j < 8; ++j) {
+    const int row = 8 * j + r0;
+    if (row < rows && c2 < cols) st_dev(out + (int64_t)row * ld + c2, lds[row * LDS_LD + c2]);
+    if (row < rows && c2 + 1 < cols) st_dev(out + (int64_t)row * ld + c2 + 1, lds[row * LDS_LD + c2 + 1]);
   }
 }
 

@@ -649,16 +649,12 @@ __device__ __forceinline__ void factor_worker(const FactorParams& p, Shared& sh)
   }
 }
 
-__global__ __launch_bounds__(NT, 2) void factor_kernel(FactorParams p) {
-  __shared__ Shared sh;
-  factor_worker(p, sh);
-}
-
-// One workgroup per CU: launched with extra dynamic LDS (SOLO_LDS_PAD bytes)
-// so that no second workgroup fits on the CU, and the diagonal tiles (the
-// critical path) do not share their SIMDs with the MFMA work of another task.
+// One workgroup per CU: the kernel is launched with extra dynamic LDS
+// (SOLO_LDS_PAD bytes) so that no second workgroup fits on a CU.  The diagonal
+// tiles (the critical path) then do not share their SIMDs with the MFMA work
+// of another task, and every task has the CU's full register file.
 constexpr size_t SOLO_LDS_PAD = 8192;
-__global__ __launch_bounds__(NT, 1) void factor_kernel_solo(FactorParams p) {
+__global__ __launch_bounds__(NT, 1) void factor_kernel(FactorParams p) {
   __shared__ Shared sh;
   factor_worker(p, sh);
 }
@@ -684,7 +680,7 @@ struct FactorBatchArgs {
   int* ctl;
 };
 
-__global__ __launch_bounds__(NT, 2) void factor_batched_kernel(FactorBatchArgs args) {
+__global__ __launch_bounds__(NT, 1) void factor_batched_kernel(FactorBatchArgs args) {
   __shared__ Shared sh;
   const int tid = threadIdx.x;
   for (;;) {
@@ -736,9 +732,6 @@ __global__ void factor_finish_kernel(const int* ctl, int64_t* info) {
   }
 }
 
-// workgroups per CU of the single-matrix factor kernel (1 or 2)
-static int g_factor_occ = 2;
-
 // ---------------------------------------------------------------------------
 FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   FactorPlan fp{};
@@ -786,12 +779,9 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
   hipLaunchKernelGGL(factor_reset_kernel, dim3(rgrid), dim3(256), 0, stream, p.flags, fp.nflags, p.ctl, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const long long grid = std::min<long long>(fp.ntasks, (long long)g_factor_occ * num_cus);
+  const long long grid = std::min<long long>(fp.ntasks, (long long)num_cus);
   timing_mark(KT_FACTOR, true, stream);
-  if (g_factor_occ == 1)
-    hipLaunchKernelGGL(factor_kernel_solo, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, p);
-  else
-    hipLaunchKernelGGL(factor_kernel, dim3((unsigned)grid), dim3(NT), 0, stream, p);
+  hipLaunchKernelGGL(factor_kernel, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, p);
   timing_mark(KT_FACTOR, false, stream);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -904,9 +894,9 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
   args.nseg = (int)segs.size();
   args.ntasks = t;
   args.ctl = ctl;
-  const long long grid = std::min<long long>(t, 2LL * num_cus);
+  const long long grid = std::min<long long>(t, (long long)num_cus);
   timing_mark(KT_FACTOR, true, stream);
-  hipLaunchKernelGGL(factor_batched_kernel, dim3((unsigned)grid), dim3(NT), 0, stream, args);
+  hipLaunchKernelGGL(factor_batched_kernel, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, args);
   timing_mark(KT_FACTOR, false, stream);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1054,13 +1044,6 @@ extern "C" __attribute__((visibility("default"))) int bta_internal_factor_batch_
   for (int m = 0; m < count; ++m)
     if (next[m] != bp.plans[m].ntasks) return 3;
   return 0;
-}
-
-// Internal: workgroups per CU of the factor kernel (1 or 2); returns the previous value.
-extern "C" __attribute__((visibility("default"))) int bta_internal_factor_occupancy(int occ) {
-  const int prev = bta::g_factor_occ;
-  if (occ == 1 || occ == 2) bta::g_factor_occ = occ;
-  return prev;
 }
 
 extern "C" __attribute__((visibility("default"))) int bta_internal_factor_schedule_check(int64_t n, int64_t b, int64_t a,
