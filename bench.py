@@ -37,7 +37,36 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-target-s", type=float, default=15.0, help="CPU oracle sample budget (seconds)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="before the warmup, one device-to-device copy of this many MiB (a dispatch of known "
+                         "traffic that calibrates hardware byte counters in a profile of this command)")
     return ap.parse_args()
+
+
+def profiled_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    this workload, if the kernel's sources are still the profiled ones (their
+    hash is recorded in the summary); None otherwise."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel}_bytes_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", " ")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for f in fields["sources"].split():
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest()[:16] != fields["source_sha256_16"]:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
 
 
 def cpu_baseline(b, a, seed, target_s):
@@ -106,6 +135,14 @@ def main():
     ws, nsel = bta.workspace(bta.BTA_OP_SELINV, n, b, a, dev)
     torch.cuda.synchronize()
 
+    if args.copy_probe_mb > 0:
+        src = torch.ones(args.copy_probe_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     def step():
         LD, LB, LR, LT, info = bta.factor(D, B, R, T, out=outL, work=wf, check=False)
         bta.selinv(LD, LB, LR, LT, out=outX, work=ws)
@@ -164,7 +201,8 @@ def main():
     if dom:
         ach = kern[dom]["tflops"]
         roofline = {"bound": "mfma", "kernel": dom, "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                    "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
+                    "traffic": profiled_traffic(dom, wl.name),
                     "flops_per_launch": kern[dom]["flops_per_launch"], "avg_launch_ms": round(kern[dom]["avg_ms"], 4)}
 
     cpu = None
