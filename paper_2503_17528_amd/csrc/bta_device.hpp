@@ -9,6 +9,7 @@
 namespace bta {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+
 typedef double d2v __attribute__((ext_vector_type(2)));
 
 constexpr int TS = 64;        // output tile edge
@@ -19,6 +20,9 @@ constexpr int LDS_LD = 66;    // LDS row stride in doubles: rows shift by 4 bank
 // v_mfma_f64_16x16x4_f64.  Operand layout (lane l): A supplies (row l%16, k l/16),
 // B supplies (k l/16, col l%16).  The 4 accumulator values of lane l hold
 // rows 4*j + l/16 (j = 0..3) of column l%16.
+// A 16-byte aligned pair of zeros: the source of loads whose element lies outside a tile.
+__device__ __align__(16) static const double k_zero_pair[2] = {0.0, 0.0};
+
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -139,6 +143,105 @@ __device__ __forceinline__ void stage_store(const Stage& s, double* lds, int tid
 #pragma unroll
   for (int j = 0; j < 8; ++j) *reinterpret_cast<d2v*>(lds + (8 * j + r0) * LDS_LD + c2) = d2v{s.v[2 * j], s.v[2 * j + 1]};
 }
+// ---------------------------------------------------------------- pieced LDS tiles (direct loads)
+// A 64 x 64 operand tile moved from global memory straight into LDS in 16-byte
+// pieces (global_load_lds_dwordx4, device coherent).  Row m's piece p (columns
+// 2p, 2p+1) sits at slot m*32 + (p ^ (m & 15)): a wave instruction fills two
+// whole rows, and the xor spreads the 16 rows that one MFMA operand read
+// touches over all LDS banks.
+constexpr int PT = 4096;  // doubles per pieced tile
+__device__ __forceinline__ int pslot(int m, int p) { return m * 32 + (p ^ (m & 15)); }
+
+
+__device__ __forceinline__ void lds_dma16_dev(const double* src, double* lds_wave_base) {
+  __builtin_amdgcn_global_load_lds(static_cast<const void*>(src),
+                                   (__attribute__((address_space(3))) void*)(lds_wave_base), 16, 0, 16 /* sc1 */);
+}
+
+// Issue the loads of tile t into the pieced LDS image dst (elements outside
+// t.rows x t.cols read as zero).  Wave w, instruction j fills rows 16w + 2j and
+// 16w + 2j + 1.  The caller waits (vmcnt) and synchronizes before reading dst.
+__device__ __forceinline__ void tile_load_lds_dev(double* dst, const OpTile& t, int tid) {
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const bool fast = ((t.ld & 1) == 0) && ((t.cols & 1) == 0) && ((reinterpret_cast<uintptr_t>(t.p) & 15) == 0);
+  if (fast) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int slot = (w * 8 + j) * 64 + lane;
+      const int m = slot >> 5, pc = (slot & 31) ^ (m & 15);
+      const double* src = (m < t.rows && 2 * pc < t.cols) ? t.p + (int64_t)m * t.ld + 2 * pc : k_zero_pair;
+      lds_dma16_dev(src, dst + (w * 8 + j) * 128);
+    }
+  } else {
+    // odd extents or leading dimension: element loads through registers
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int slot = (w * 8 + j) * 64 + lane;
+      const int m = slot >> 5, pc = (slot & 31) ^ (m & 15);
+      const double* src = t.p + (int64_t)m * t.ld + 2 * pc;
+      const double x0 = (m < t.rows && 2 * pc < t.cols) ? ld_dev(src) : 0.0;
+      const double x1 = (m < t.rows && 2 * pc + 1 < t.cols) ? ld_dev(src + 1) : 0.0;
+      *reinterpret_cast<d2v*>(dst + 2 * slot) = d2v{x0, x1};
+    }
+  }
+}
+
+// The four consecutive k values 16*kg + 4*g .. +3 of row m of a pieced tile.
+__device__ __forceinline__ d4 ptile_row4(const double* T, int m, int kg, int g) {
+  const int p0 = 8 * kg + 2 * g;
+  const d2v x0 = *reinterpret_cast<const d2v*>(T + 2 * pslot(m, p0));
+  const d2v x1 = *reinterpret_cast<const d2v*>(T + 2 * pslot(m, p0 + 1));
+  return d4{x0[0], x0[1], x1[0], x1[1]};
+}
+
+// c += A B^T (64 x 64 x 64) from pieced tiles; wave w owns the 32 x 32 block
+// (32 (w >> 1), 32 (w & 1)) as 2 x 2 MFMA blocks (same layout as mma_tile).
+__device__ __forceinline__ void mma_ptile(Acc& c, const double* A, const double* B, int tid) {
+  const int w = tid >> 6, lane = tid & 63;
+  const int r0 = 32 * (w >> 1) + (lane & 15), c0 = 32 * (w & 1) + (lane & 15), g = lane >> 4;
+#pragma unroll
+  for (int kg = 0; kg < 4; ++kg) {
+    d4 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      a[i] = ptile_row4(A, r0 + 16 * i, kg, g);
+      b[i] = ptile_row4(B, c0 + 16 * i, kg, g);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) c.v[i][j] = mfma16(a[i][s], b[j][s], c.v[i][j]);
+  }
+}
+
+// c1 += A A^T and c2 += A B^T from pieced tiles (the two share their left operand).
+__device__ __forceinline__ void mma_ptile2(Acc& c1, Acc& c2, const double* A, const double* B, int tid) {
+  const int w = tid >> 6, lane = tid & 63;
+  const int r0 = 32 * (w >> 1) + (lane & 15), c0 = 32 * (w & 1) + (lane & 15), g = lane >> 4;
+#pragma unroll
+  for (int kg = 0; kg < 4; ++kg) {
+    d4 ar[2], ac[2], bc[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      ar[i] = ptile_row4(A, r0 + 16 * i, kg, g);
+      ac[i] = ptile_row4(A, c0 + 16 * i, kg, g);
+      bc[i] = ptile_row4(B, c0 + 16 * i, kg, g);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          c1.v[i][j] = mfma16(ar[i][s], ac[j][s], c1.v[i][j]);
+          c2.v[i][j] = mfma16(ar[i][s], bc[j][s], c2.v[i][j]);
+        }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // Device-coherent store of the rows x cols corner of a 64 x 64 LDS tile.
 __device__ __forceinline__ void tile_store_dev(const double* lds, double* out, int64_t ld, int rows, int cols, int tid) {
   const int c2 = (tid & 31) * 2, r0 = tid >> 5;
@@ -238,7 +341,10 @@ __device__ __forceinline__ void acc_load(Acc& c, const double* p, int64_t ld, in
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int r = tile_row(tid, bi, j), q = tile_col(tid, bj);
-        c.v[bi][bj][j] = (r < rows && q < cols) ? scale * p[(int64_t)r * ld + q] : 0.0;
+        const bool ok = r < rows && q < cols;
+        // unconditional load from a valid address: all sixteen loads are in flight together
+        const double v = *(ok ? p + (int64_t)r * ld + q : &k_zero_pair[0]);
+        c.v[bi][bj][j] = ok ? scale * v : 0.0;
       }
 }
 

@@ -11,8 +11,13 @@
 namespace bta {
 
 // ---------------------------------------------------------------- factor
+// Columns by which a diagonal task is dispatched ahead of its column (at most
+// this many tasks wait on tasks with larger tickets; the factor kernel keeps
+// more resident workgroups than that).
+constexpr int FACTOR_LOOKAHEAD = 8;
+
 struct FactorPlan {
-  int T, TA;
+  int T, TA, look;
   long long nflags, step_full, step_last, ntasks;
   size_t off_ctl, off_flags, off_Wd, off_Wt, off_P, bytes;
 };

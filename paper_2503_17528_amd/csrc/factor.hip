@@ -55,9 +55,11 @@ struct FactorParams {
   int64_t* info;   // caller's info
   long long ntasks;
   long long step_full, step_last;  // tasks per step (with / without SUB)
+  int look;                        // DIAG lookahead: DIAG(i,c) is dispatched with column c - look of its step
   long long spin_limit;
   unsigned long long* trace;  // optional: 8 words per ticket (start, k loop done, end, type | workgroup << 8,
-                              // DIAG only: W(g-1) ready, L(g,g-1) published, tile factored)
+                              // W ready (DIAG: of g-1), L(g,g-1) published (DIAG), tile factored (DIAG),
+                              // end of the last blocking wait in the k loop)
 };
 
 struct Task {
@@ -80,7 +82,7 @@ __host__ __device__ inline int64_t fl_tip(const FactorParams& p, int r, int c) {
   return fl_D(p, p.n, 0, 0) + (int64_t)r * p.TA + c;
 }
 
-__host__ __device__ Task decode(const FactorParams& p, long long t) {
+__host__ __device__ __forceinline__ Task decode(const FactorParams& p, long long t) {
   Task k{-1, 0, 0, 0};
   const int T = p.T, TA = p.TA;
   long long rem;
@@ -108,24 +110,34 @@ __host__ __device__ Task decode(const FactorParams& p, long long t) {
     }
     return k;
   }
-  // column c: DIAG, OFFD rows c+2 .. T-1 (row c+1 is fused into the next DIAG),
-  // SUB rows 0 .. T-1 (not row 0 of the last column: fused into the next
-  // step's first DIAG), ARW rows 0 .. TA-1
+  // column c: DIAG tasks (DIAG(0 .. L) at c = 0, DIAG(c + L) after, L = look:
+  // a diagonal task starts its long k loop L columns ahead of the chain), OFFD
+  // rows c+2 .. T-1 (row c+1 is fused into the next DIAG), SUB rows 0 .. T-1
+  // (not row 0 of the last column: fused into the next step's first DIAG),
+  // ARW rows 0 .. TA-1
+  const int L = p.look;
   for (int c = 0; c < T; ++c) {
-    const int nd = (c < T - 1) ? T - c - 1 : 1;
+    const int ndg = (c == 0) ? L + 1 : ((c + L <= T - 1) ? 1 : 0);
+    const int no = (c <= T - 2) ? T - c - 2 : 0;
     const int ns = has_sub ? (c == T - 1 ? T - 1 : T) : 0;
-    const int g = nd + ns + TA;
+    const int g = ndg + no + ns + TA;
     if (rem < g) {
-      k.c = c;
-      if (rem < nd) {
-        k.type = rem == 0 ? T_DIAG : T_OFFD;
-        k.r = rem == 0 ? c : c + 1 + (int)rem;
-      } else if (rem - nd < ns) {
+      if (rem < ndg) {
+        k.type = T_DIAG;
+        k.c = (c == 0) ? (int)rem : c + L;
+        k.r = k.c;
+      } else if (rem - ndg < no) {
+        k.type = T_OFFD;
+        k.c = c;
+        k.r = c + 2 + (int)(rem - ndg);
+      } else if (rem - ndg - no < ns) {
         k.type = T_SUB;
-        k.r = (int)(rem - nd) + (c == T - 1 ? 1 : 0);
+        k.c = c;
+        k.r = (int)(rem - ndg - no) + (c == T - 1 ? 1 : 0);
       } else {
         k.type = T_ARW;
-        k.r = (int)(rem - nd - ns);
+        k.c = c;
+        k.r = (int)(rem - ndg - no - ns);
       }
       return k;
     }
@@ -149,8 +161,13 @@ __host__ __device__ Task decode(const FactorParams& p, long long t) {
 __host__ __device__ inline int ext(int total, int t) { int e = total - 64 * t; return e < 64 ? e : 64; }
 
 struct alignas(16) Shared {
-  double As[TS * LDS_LD];
-  double Bs[TS * LDS_LD];
+  union {
+    double stage[2][2][PT];  // k loop: pieced operand tiles, double buffered (direct loads)
+    struct {
+      double As[TS * LDS_LD];
+      double Bs[TS * LDS_LD];
+    } f;  // finishing a tile: row-major padded tiles
+  } u;
   double pan[64 * 17];  // diagonal tile factorization workspace
   double rinv[64];
   long long ticket;
@@ -168,7 +185,7 @@ struct KSrc {
 
 // Enumerate the k sources of a task.  Returns the number of k tiles and fills
 // src for index kk when kk >= 0.
-__host__ __device__ int ksources(const FactorParams& p, const Task& t, int kk, KSrc* src) {
+__host__ __device__ __forceinline__ int ksources(const FactorParams& p, const Task& t, int kk, KSrc* src) {
   const int T = p.T, b = p.b, a = p.a;
   const int64_t bb = (int64_t)b * b, ab = (int64_t)a * b;
   const int nprev = (t.i > 0) ? T : 0;  // previous block column (cross-step update)
@@ -361,18 +378,15 @@ __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, S
     ksources(p, pt, 0, &s0);
     if (!wait_ready(p, s0.fa, s0.fb, sh, tid)) aborted = true;
     upto = 1;
-    Stage ra, rb;
-    stage_load_dev(ra, s0.a, tid);
-    stage_load_dev(rb, s0.b, tid);
+    tile_load_lds_dev(sh.u.stage[0][0], s0.a, tid);
+    tile_load_lds_dev(sh.u.stage[0][1], s0.b, tid);
     for (int kk = 0; kk < nk && !aborted; ++kk) {
-      __syncthreads();
-      stage_store(ra, sh.As, tid);
-      stage_store(rb, sh.Bs, tid);
       if (tid < 64) {
         const int u = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, pt, kk + 1, nk, tid) : upto;
         if (tid == 0) sh.upto = u;
       }
-      __syncthreads();
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of k tile kk have landed
+      __syncthreads();                // everyone's; and stage (kk+1)&1 is no longer read
       const int u = uni(sh.upto);
       upto = u > upto ? u : upto;
       if (kk + 1 < nk) {
@@ -380,14 +394,16 @@ __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, S
         ksources(p, pt, kk + 1, &sn);
         if (kk + 1 >= upto) {
           if (!wait_ready(p, sn.fa, sn.fb, sh, tid)) aborted = true;
+          if (rec && tid == 0) rec[7] = __builtin_amdgcn_s_memrealtime();
           upto = kk + 2;
         }
-        stage_load_dev(ra, sn.a, tid);
-        stage_load_dev(rb, sn.b, tid);
+        tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][0], sn.a, tid);
+        tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][1], sn.b, tid);
       }
-      mma_tile2(acc1, acc2, sh.As, sh.Bs, tid);
+      mma_ptile2(acc1, acc2, sh.u.stage[kk & 1][0], sh.u.stage[kk & 1][1], tid);
     }
   }
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (rec && tid == 0) tr1 = __builtin_amdgcn_s_memrealtime();
   // the rest of this task is the critical path of the factorization: let its
@@ -400,12 +416,12 @@ __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, S
     if (rec && tid == 0) rec[4] = __builtin_amdgcn_s_memrealtime();
     Stage rw;
     stage_load_dev(rw, OpTile{Wp, 64, 64, 64, false}, tid);
-    acc_to_lds(acc2, sh.As, tid);
-    stage_store(rw, sh.Bs, tid);
+    acc_to_lds(acc2, sh.u.f.As, tid);
+    stage_store(rw, sh.u.f.Bs, tid);
     __syncthreads();
     Acc x;  // -L(g,g-1)
     acc_zero(x);
-    mma_tile(x, sh.As, sh.Bs, tid);
+    mma_tile(x, sh.u.f.As, sh.u.f.Bs, tid);
     acc_store_dev(x, pout, b, prows, pcols, -1.0, tid);
     if (t.c > 0) {  // exact zeros in the mirrored upper tile of the diagonal block
       double* up = p.LD + t.i * bb + (int64_t)(t.c - 1) * 64 * b + t.c * 64;
@@ -415,9 +431,9 @@ __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, S
       }
     }
     __syncthreads();
-    acc_to_lds(x, sh.As, tid);
+    acc_to_lds(x, sh.u.f.As, tid);
     __syncthreads();
-    mma_tile(acc1, sh.As, sh.As, tid);  // + L(g,g-1) L(g,g-1)^T = x x^T
+    mma_tile(acc1, sh.u.f.As, sh.u.f.As, tid);  // + L(g,g-1) L(g,g-1)^T = x x^T
     publish(pflag, tid);
     if (rec && tid == 0) rec[5] = __builtin_amdgcn_s_memrealtime();
   }
@@ -428,17 +444,17 @@ __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, S
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) sh.As[tile_row(tid, bi, j) * LDS_LD + tile_col(tid, bj)] = -acc1.v[bi][bj][j];
+      for (int j = 0; j < 4; ++j) sh.u.f.As[tile_row(tid, bi, j) * LDS_LD + tile_col(tid, bj)] = -acc1.v[bi][bj][j];
   __syncthreads();
-  const int f = uni(chol_inv_tile_mfma<2>(sh.As, sh.Bs, sh.rinv, sh.pan, &sh.fail, tid));
+  const int f = uni(chol_inv_tile_mfma<2>(sh.u.f.As, sh.u.f.Bs, sh.rinv, sh.pan, &sh.fail, tid));
   if (rec && tid == 0) rec[6] = __builtin_amdgcn_s_memrealtime();
   if (f != 0 && f <= rows && tid == 0) {
     const long long row0 = (long long)t.i * b + (long long)t.c * 64;
     atomicMin((unsigned long long*)p.info, (unsigned long long)(row0 + f));
   }
   double* Wout = p.Wd + ((int64_t)t.i * T + t.c) * 4096;
-  tile_store_dev(sh.Bs, Wout, 64, 64, 64, tid);
-  tile_store_dev(sh.As, out, b, rows, rows, tid);
+  tile_store_dev(sh.u.f.Bs, Wout, 64, 64, 64, tid);
+  tile_store_dev(sh.u.f.As, out, b, rows, rows, tid);
   (void)aborted;
   publish(p.flags + fl_D(p, t.i, t.c, t.c), tid);
   __builtin_amdgcn_s_setprio(0);
@@ -458,7 +474,9 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
         rec[0] = tr0;
         rec[1] = tr1;
         rec[2] = __builtin_amdgcn_s_memrealtime();
-        rec[3] = (unsigned long long)t.type | ((unsigned long long)blockIdx.x << 8);
+        rec[3] = (unsigned long long)t.type | ((unsigned long long)(blockIdx.x & 0xffff) << 8) |
+               ((unsigned long long)(t.r & 0xffff) << 24) | ((unsigned long long)(t.c & 0xfff) << 40) |
+               ((unsigned long long)(t.i & 0xfff) << 52);
       }
       return;
     }
@@ -540,8 +558,8 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
       }
     }
 
-    // ---- left-looking accumulation, software pipelined: the next k tile is
-    // loaded into registers while the MFMAs of the current one run.
+    // ---- left-looking accumulation, software pipelined: the next k tiles are
+    // moved into the other LDS stage while the MFMAs of the current ones run.
     const int nk = uni(ksources(p, t, -1, nullptr));
     bool aborted = false;
     if (nk > 0) {
@@ -550,18 +568,15 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
       ksources(p, t, 0, &s0);
       if (!wait_ready(p, s0.fa, s0.fb, sh, tid)) aborted = true;
       upto = 1;
-      Stage ra, rb;
-      stage_load_dev(ra, s0.a, tid);
-      stage_load_dev(rb, s0.b, tid);
+      tile_load_lds_dev(sh.u.stage[0][0], s0.a, tid);
+      tile_load_lds_dev(sh.u.stage[0][1], s0.b, tid);
       for (int kk = 0; kk < nk && !aborted; ++kk) {
-        __syncthreads();  // previous MFMAs are done with the LDS operands
-        stage_store(ra, sh.As, tid);
-        stage_store(rb, sh.Bs, tid);
         if (tid < 64) {
           const int u = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, t, kk + 1, nk, tid) : upto;
           if (tid == 0) sh.upto = u;
         }
-        __syncthreads();
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of k tile kk have landed
+        __syncthreads();                // everyone's; and stage (kk+1)&1 is no longer read
         const int u = uni(sh.upto);
         upto = u > upto ? u : upto;
         if (kk + 1 < nk) {
@@ -569,14 +584,16 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
           ksources(p, t, kk + 1, &sn);
           if (kk + 1 >= upto) {  // not final yet: block (rare once the pipeline is primed)
             if (!wait_ready(p, sn.fa, sn.fb, sh, tid)) { aborted = true; }
+            if (p.trace && tid == 0) p.trace[8 * tk + 7] = __builtin_amdgcn_s_memrealtime();
             upto = kk + 2;
           }
-          stage_load_dev(ra, sn.a, tid);
-          stage_load_dev(rb, sn.b, tid);
+          tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][0], sn.a, tid);
+          tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][1], sn.b, tid);
         }
-        mma_tile(acc, sh.As, sh.Bs, tid);
+        mma_ptile(acc, sh.u.stage[kk & 1][0], sh.u.stage[kk & 1][1], tid);
       }
     }
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (p.trace && tid == 0) tr1 = __builtin_amdgcn_s_memrealtime();
 
@@ -590,30 +607,31 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) sh.As[tile_row(tid, bi, j) * LDS_LD + tile_col(tid, bj)] = -acc.v[bi][bj][j];
+          for (int j = 0; j < 4; ++j) sh.u.f.As[tile_row(tid, bi, j) * LDS_LD + tile_col(tid, bj)] = -acc.v[bi][bj][j];
       __syncthreads();
-      const int f = uni(chol_inv_tile_mfma<2>(sh.As, sh.Bs, sh.rinv, sh.pan, &sh.fail, tid));
+      const int f = uni(chol_inv_tile_mfma<2>(sh.u.f.As, sh.u.f.Bs, sh.rinv, sh.pan, &sh.fail, tid));
       if (f != 0 && f <= rows && tid == 0) {
         const long long row0 = (long long)p.n * b + (long long)t.c * 64;
         atomicMin((unsigned long long*)p.info, (unsigned long long)(row0 + f));
       }
       double* Wout = p.Wt + (int64_t)t.c * 4096;
-      tile_store_dev(sh.Bs, Wout, 64, 64, 64, tid);
-      tile_store_dev(sh.As, out, ld, rows, cols, tid);
+      tile_store_dev(sh.u.f.Bs, Wout, 64, 64, 64, tid);
+      tile_store_dev(sh.u.f.As, out, ld, rows, cols, tid);
     } else {
       // X = (A - sum) W(c,c)^T
       const double* Wc = (t.type == T_TIPO) ? p.Wt + (int64_t)t.c * 4096
                                             : p.Wd + ((int64_t)t.i * T + t.c) * 4096;
       const int* fdiag = (t.type == T_TIPO) ? p.flags + fl_tip(p, t.c, t.c) : p.flags + fl_D(p, t.i, t.c, t.c);
       wait_ready(p, fdiag, fdiag, sh, tid);
+      if (p.trace && tid == 0) p.trace[8 * tk + 4] = __builtin_amdgcn_s_memrealtime();
       Stage rw;
       stage_load_dev(rw, OpTile{Wc, 64, 64, 64, false}, tid);
-      acc_to_lds(acc, sh.As, tid);
-      stage_store(rw, sh.Bs, tid);
+      acc_to_lds(acc, sh.u.f.As, tid);
+      stage_store(rw, sh.u.f.Bs, tid);
       __syncthreads();
       Acc x;
       acc_zero(x);
-      mma_tile(x, sh.As, sh.Bs, tid);
+      mma_tile(x, sh.u.f.As, sh.u.f.Bs, tid);
       acc_store_dev(x, out, ld, rows, cols, -1.0, tid);
       // exact zeros in the mirrored (upper) tile of a diagonal block / the tip
       if (t.type == T_OFFD || t.type == T_TIPO) {
@@ -632,7 +650,9 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
       rec[0] = tr0;
       rec[1] = tr1;
       rec[2] = __builtin_amdgcn_s_memrealtime();
-      rec[3] = (unsigned long long)t.type | ((unsigned long long)blockIdx.x << 8);
+      rec[3] = (unsigned long long)t.type | ((unsigned long long)(blockIdx.x & 0xffff) << 8) |
+               ((unsigned long long)(t.r & 0xffff) << 24) | ((unsigned long long)(t.c & 0xfff) << 40) |
+               ((unsigned long long)(t.i & 0xfff) << 52);
     }
   }
 }
@@ -649,11 +669,12 @@ __device__ __forceinline__ void factor_worker(const FactorParams& p, Shared& sh)
   }
 }
 
-// One workgroup per CU: the kernel is launched with extra dynamic LDS
-// (SOLO_LDS_PAD bytes) so that no second workgroup fits on a CU.  The diagonal
+// One workgroup per CU (the static LDS is more than half of a CU's): the
+// kernel is launched with no extra dynamic LDS (SOLO_LDS_PAD = 0).  The diagonal
 // tiles (the critical path) then do not share their SIMDs with the MFMA work
 // of another task, and every task has the CU's full register file.
-constexpr size_t SOLO_LDS_PAD = 8192;
+constexpr size_t SOLO_LDS_PAD = 0;
+static_assert(sizeof(Shared) > 80 * 1024, "one workgroup per CU relies on the LDS footprint");
 __global__ __launch_bounds__(NT, 1) void factor_kernel(FactorParams p) {
   __shared__ Shared sh;
   factor_worker(p, sh);
@@ -744,6 +765,7 @@ FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   fp.step_full = T * (T - 1) / 2 + 1 + T * T - 1 + T * TA + TA * (TA + 1) / 2;
   fp.step_last = T * (T - 1) / 2 + 1 + T * TA + TA * (TA + 1) / 2;
   fp.ntasks = (n - 1) * fp.step_full + fp.step_last + TA * (TA + 1) / 2;
+  fp.look = (int)std::min<int64_t>(FACTOR_LOOKAHEAD, T - 1);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
   fp.off_ctl = take(64);
@@ -773,6 +795,7 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
   p.ntasks = fp.ntasks;
   p.step_full = fp.step_full;
   p.step_last = fp.step_last;
+  p.look = fp.look;
   p.trace = trace;
   p.spin_limit = 1LL << 22;  // a few seconds of polling without progress before the watchdog fires
   const int rgrid = (int)std::min<long long>(1024, (fp.nflags + 255) / 256 + 1);
@@ -780,6 +803,7 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long grid = std::min<long long>(fp.ntasks, (long long)num_cus);
+  if (grid < fp.ntasks && grid <= fp.look + 1) return hipErrorInvalidConfiguration;  // lookahead needs more workers
   timing_mark(KT_FACTOR, true, stream);
   hipLaunchKernelGGL(factor_kernel, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, p);
   timing_mark(KT_FACTOR, false, stream);
@@ -872,6 +896,7 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
     p.ntasks = fp.ntasks;
     p.step_full = fp.step_full;
     p.step_last = fp.step_last;
+    p.look = fp.look;
     p.spin_limit = 1LL << 22;
     p.trace = nullptr;
   }
@@ -895,6 +920,7 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
   args.ntasks = t;
   args.ctl = ctl;
   const long long grid = std::min<long long>(t, (long long)num_cus);
+  if (grid < t && grid <= FACTOR_LOOKAHEAD + 1) return hipErrorInvalidConfiguration;  // lookahead needs more workers
   timing_mark(KT_FACTOR, true, stream);
   hipLaunchKernelGGL(factor_batched_kernel, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, args);
   timing_mark(KT_FACTOR, false, stream);
@@ -921,7 +947,7 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
   p.LR = reinterpret_cast<double*>(3 * G);
   p.LT = reinterpret_cast<double*>(4 * G);
   p.flags = reinterpret_cast<int*>(5 * G);
-  p.ntasks = fp.ntasks; p.step_full = fp.step_full; p.step_last = fp.step_last;
+  p.ntasks = fp.ntasks; p.step_full = fp.step_full; p.step_last = fp.step_last; p.look = fp.look;
   const size_t lim[4] = {(size_t)(n * b * b), (size_t)((n - 1) * b * b), (size_t)(n * a * b), (size_t)(a * a)};
   auto inside = [&](const OpTile& o) -> bool {
     if (o.rows <= 0 || o.cols <= 0) return false;
@@ -932,12 +958,23 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
     const size_t last = off + (size_t)(o.rows - 1) * o.ld + (o.cols - 1);
     return last < lim[arr] && (size_t)o.cols <= (size_t)o.ld;
   };
+  // rank of a task: the global band column it belongs to (tip tasks after all columns)
+  auto rank_of = [&](const Task& t) -> long long {
+    switch (t.type) {
+      case T_TUPD: return (long long)t.i * p.T + p.T - 1;
+      case T_TIPD: case T_TIPO: return (long long)p.n * p.T;
+      default: return (long long)t.i * p.T + t.c;
+    }
+  };
+  // pass 1: every ticket decodes to a task, every flag has exactly one owner
   std::vector<long long> owner((size_t)fp.nflags, -1);
+  std::vector<long long> rank((size_t)fp.ntasks);
   long long cnt[7] = {0, 0, 0, 0, 0, 0, 0};
   for (long long tk = 0; tk < fp.ntasks; ++tk) {
     const Task t = decode(p, tk);
     if (t.type < 0 || t.type > 6) return 1;
     cnt[t.type]++;
+    rank[(size_t)tk] = rank_of(t);
     int64_t f;
     switch (t.type) {
       case T_DIAG: case T_OFFD: f = fl_D(p, t.i, t.r, t.c); if (t.r < t.c || t.r >= p.T) return 2; break;
@@ -947,12 +984,35 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
       default: f = fl_tip(p, t.r, t.c); break;
     }
     if (f < 0 || f >= fp.nflags || owner[(size_t)f] != -1) return 3;
+    owner[(size_t)f] = tk;
     if (t.type == T_DIAG && (t.c > 0 || t.i > 0)) {
-      // the fused tile L(g, g-1): its k sources, W(g-1), and its own flag
+      const int64_t pf = t.c > 0 ? fl_D(p, t.i, t.c, t.c - 1) : fl_B(p, t.i - 1, 0, p.T - 1);
+      if (pf < 0 || pf >= fp.nflags || owner[(size_t)pf] != -1) return 3;
+      owner[(size_t)pf] = tk;
+      cnt[t.c > 0 ? T_OFFD : T_SUB]++;
+    }
+  }
+  // pass 2: dependencies.  A task other than DIAG waits only on tasks with
+  // smaller tickets; a DIAG task (dispatched up to `look` columns early) waits
+  // only on tasks of smaller rank.  Together with the bound on the number of
+  // DIAG tasks ahead of the in-order frontier (checked below) this keeps the
+  // schedule deadlock free whenever more workgroups than that bound are resident.
+  std::vector<long long> maxdep((size_t)fp.ntasks, -1);  // largest ticket a task waits on
+  auto dep_ok = [&](int64_t flag, long long tk, bool diag) -> int {
+    if (flag < 0 || flag >= fp.nflags) return 4;
+    const long long o = owner[(size_t)flag];
+    if (o < 0) return 5;
+    if (diag ? !(rank[(size_t)o] < rank[(size_t)tk]) : !(o < tk)) return 5;
+    maxdep[(size_t)tk] = std::max(maxdep[(size_t)tk], o);
+    return 0;
+  };
+  for (long long tk = 0; tk < fp.ntasks; ++tk) {
+    const Task t = decode(p, tk);
+    int e;
+    if (t.type == T_DIAG && (t.c > 0 || t.i > 0)) {
       const Task pt = t.c > 0 ? Task{T_OFFD, t.i, t.c, t.c - 1} : Task{T_SUB, t.i - 1, 0, p.T - 1};
       const int64_t pf = t.c > 0 ? fl_D(p, t.i, t.c, t.c - 1) : fl_B(p, t.i - 1, 0, p.T - 1);
       const int64_t wf = t.c > 0 ? fl_D(p, t.i, t.c - 1, t.c - 1) : fl_D(p, t.i - 1, p.T - 1, p.T - 1);
-      if (pf < 0 || pf >= fp.nflags || owner[(size_t)pf] != -1) return 3;
       const int pnk = ksources(p, pt, -1, nullptr);
       if (pnk != ksources(p, t, -1, nullptr) - 1) return 10;
       for (int kk = 0; kk < pnk; ++kk) {
@@ -960,39 +1020,42 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
         ksources(p, pt, kk, &s);
         ksources(p, t, kk, &sd);
         if (s.a.p != sd.a.p || s.fa != sd.fa) return 10;  // shared left operand
-        const int64_t fa = s.fa - p.flags, fb = s.fb - p.flags;
-        if (fa < 0 || fa >= fp.nflags || fb < 0 || fb >= fp.nflags) return 4;
-        if (owner[(size_t)fa] < 0 || owner[(size_t)fb] < 0) return 5;
+        if ((e = dep_ok(s.fa - p.flags, tk, true)) || (e = dep_ok(s.fb - p.flags, tk, true))) return e;
         if (!inside(s.a) || !inside(s.b)) return 6;
       }
       KSrc last;
       ksources(p, t, pnk, &last);  // the diagonal tile's last k source is the fused tile
       if (last.fa - p.flags != pf || last.fb - p.flags != pf) return 10;
-      if (owner[(size_t)wf] < 0) return 7;
-      owner[(size_t)pf] = tk;
-      cnt[pt.type]++;
-      owner[(size_t)f] = tk;
+      if (dep_ok(wf, tk, true)) return 7;
       continue;
     }
+    const bool diag = t.type == T_DIAG;
     const int nk = ksources(p, t, -1, nullptr);
     for (int kk = 0; kk < nk; ++kk) {
       KSrc s;
       ksources(p, t, kk, &s);
-      const int64_t fa = s.fa - p.flags, fb = s.fb - p.flags;
-      if (fa < 0 || fa >= fp.nflags || fb < 0 || fb >= fp.nflags) return 4;
-      if (owner[(size_t)fa] < 0 || owner[(size_t)fb] < 0) return 5;
+      if ((e = dep_ok(s.fa - p.flags, tk, diag)) || (e = dep_ok(s.fb - p.flags, tk, diag))) return e;
       if (!inside(s.a) || !inside(s.b)) return 6;
     }
     if (t.type == T_OFFD || t.type == T_SUB || t.type == T_ARW) {
-      if (owner[(size_t)fl_D(p, t.i, t.c, t.c)] < 0) return 7;
+      if (dep_ok(fl_D(p, t.i, t.c, t.c), tk, false)) return 7;
     }
-    if (t.type == T_TIPO && owner[(size_t)fl_tip(p, t.c, t.c)] < 0) return 7;
+    if (t.type == T_TIPO && dep_ok(fl_tip(p, t.c, t.c), tk, false)) return 7;
     if (t.type == T_TIPD || t.type == T_TIPO) {
       for (int i = 0; i < p.n; ++i)
-        if (owner[(size_t)fl_U(p, i, t.r, t.c)] < 0) return 8;
+        if (dep_ok(fl_U(p, i, t.r, t.c), tk, false)) return 8;
     }
-    owner[(size_t)f] = tk;
   }
+  // at any point of the dispatch order, at most look + 1 dispatched tasks still
+  // wait on a task with a larger ticket
+  long long ahead_max = 0;
+  std::vector<long long> open;  // max dependency tickets of dispatched tasks that wait ahead
+  for (long long tk = 0; tk < fp.ntasks; ++tk) {
+    if (maxdep[(size_t)tk] > tk) open.push_back(maxdep[(size_t)tk]);
+    open.erase(std::remove_if(open.begin(), open.end(), [&](long long m) { return m <= tk; }), open.end());
+    ahead_max = std::max<long long>(ahead_max, (long long)open.size());
+  }
+  if (ahead_max > fp.look + 1) return 11;
   const long long T = fp.T, TA = fp.TA;
   const long long expect[7] = {n * T, n * T * (T - 1) / 2, (n - 1) * T * T, n * T * TA, n * TA * (TA + 1) / 2, TA,
                                TA * (TA - 1) / 2};
