@@ -396,6 +396,15 @@ __device__ __forceinline__ void gemm_tile_dl(const GProb& P, long long local, in
 #pragma unroll
     for (int jj = 0; jj < WN; ++jj) acc.v[i][jj] = d4{0.0, 0.0, 0.0, 0.0};
   const int rw = 16 * WM * (wave >> 1), cw = 16 * WN * (wave & 1);
+  // MFMA blocks with no element inside the tile's extent, or (lower stores)
+  // entirely above the diagonal, are not computed
+  bool live[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int jj = 0; jj < WN; ++jj)
+      live[i][jj] = (rw + 16 * i < mext) && (cw + 16 * jj < next) &&
+                    (P.store == ST_FULL || n0 + cw + 16 * jj <= m0 + rw + 16 * i + 15);
   if (total > 0) issue(0);
   for (int kk = 0; kk < total; ++kk) {
     // stage kk has landed for every wave, and every wave is done with stage kk-1
@@ -411,7 +420,8 @@ __device__ __forceinline__ void gemm_tile_dl(const GProb& P, long long local, in
 #pragma unroll
       for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int jj = 0; jj < WN; ++jj) acc.v[i][jj] = mfma16(a[i][q], b[jj][q], acc.v[i][jj]);
+        for (int jj = 0; jj < WN; ++jj)
+          if (live[i][jj]) acc.v[i][jj] = mfma16(a[i][q], b[jj][q], acc.v[i][jj]);
   }
 
   const int64_t coff = b0 * P.sC0 + b1 * P.sC1;
@@ -622,8 +632,31 @@ static bool dl_ok(const GProb& p) {
 }
 
 // 0: choose per launch; 1: register-staged kernels only; 2: direct-to-LDS
-// kernels wherever the operands allow (tests run both paths through this).
+// kernels wherever the operands allow; 3 / 4: direct-to-LDS with 64 / 128
+// tiles only (tests run every path through this).
 static int g_gemm_mode = 0;
+
+// Sum over the tiles of a planned launch of the fraction of MFMA blocks a
+// tile computes (ragged edges and lower-store tiles compute fewer).
+static double tile_weight(const GemmArgs& a, int TM, int TN) {
+  double w = 0.0;
+  for (int pi = 0; pi < a.nprob; ++pi) {
+    const GProb& p = a.p[pi];
+    double per = 0.0;
+    for (int tm = 0; tm < p.ntm; ++tm) {
+      const int rows = std::min(TM, p.M - tm * TM);
+      const int tn_end = p.lower_tiles ? std::min(p.ntn, (tm * TM + TM - 1) / TN + 1) : p.ntn;
+      for (int tn = 0; tn < tn_end; ++tn) {
+        const int cols = std::min(TN, p.N - tn * TN);
+        double f = (double)((rows + 15) / 16 * 16) * ((cols + 15) / 16 * 16) / ((double)TM * TN);
+        if (p.store != ST_FULL && tn * TN + TN > tm * TM) f *= 0.6;  // diagonal tile of a lower store
+        per += f;
+      }
+    }
+    w += per * p.nb0 * p.nb1;
+  }
+  return w;
+}
 
 hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream) {
   if (g_rec) {
@@ -643,11 +676,17 @@ hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream) {
   const long long t64 = plan_tiles(small, probs, nprob, 64, 64);
   if (t64 == 0) return hipSuccess;
   if (dl) {
-    // makespan model: tiles are dealt evenly to the CUs, a 128-tile costs four 64-tiles
-    const long long cus = std::max(1, device_cu_count());
-    const long long c128 = 4 * ((t128 + cus - 1) / cus), c64 = (t64 + cus - 1) / cus;
+    // makespan model in units of one 64 x 64 tile: the work of a launch (tiles
+    // weighted by the MFMA blocks they compute) spread over the CUs, and at
+    // least one whole tile; a 128-tile is four 64-tiles
+    const double cus = std::max(1, device_cu_count());
+    const double c128 = 4.0 * std::max(tile_weight(big, 128, 128) / cus, 1.0);
+    const double c64 = std::max(tile_weight(small, 64, 64) / cus, 1.0);
     timing_mark(KT_GEMM, true, stream);
-    if (c128 <= c64)
+    // measured: the 128-tile kernel runs ~1.4x slower per flop than the
+    // 64-tile one, so it only pays when 64-tiles leave most CUs idle
+    const bool use128 = g_gemm_mode == 4 || (g_gemm_mode != 3 && 1.4 * c128 < c64);
+    if (use128)
       hipLaunchKernelGGL(gemm_dl128_kernel, dim3((unsigned)t128), dim3(NT), 0, stream, big);
     else
       hipLaunchKernelGGL(gemm_dl64_kernel, dim3((unsigned)t64), dim3(NT), 0, stream, small);
@@ -798,11 +837,28 @@ extern "C" __attribute__((visibility("default"))) int bta_internal_timing(int on
 }
 
 // Internal GEMM kernel selection (0 automatic, 1 register-staged only,
-// 2 direct-to-LDS where possible); returns the previous mode.
+// 2 direct-to-LDS where possible, 3 / 4 direct-to-LDS with 64 / 128 tiles);
+// returns the previous mode.
 extern "C" __attribute__((visibility("default"))) int bta_internal_gemm_mode(int mode) {
   const int prev = bta::g_gemm_mode;
-  if (mode >= 0 && mode <= 2) bta::g_gemm_mode = mode;
+  if (mode >= 0 && mode <= 4) bta::g_gemm_mode = mode;
   return prev;
+}
+
+// Internal: one product through the grouped GEMM (tests and measurements):
+// C = beta * Cin + alpha * sum_k A(m,k) B(c,k), operand layouts and k range as
+// in the selected inversion's problems.  Returns a HIP error code.
+extern "C" __attribute__((visibility("default"))) int bta_internal_gemm(
+    int M, int N, int K, const double* A, int64_t lda, int at, const double* B, int64_t ldb, int bt, int tri,
+    const double* Cin, double* C, int64_t ldc, double alpha, double beta, int store, int lower_tiles, hipStream_t s) {
+  bta::GProb p{};
+  p.seg[0].A = A; p.seg[0].B = B; p.seg[0].lda = lda; p.seg[0].ldb = ldb; p.seg[0].K = K;
+  p.seg[0].at = at; p.seg[0].bt = bt; p.seg[0].tri = tri;
+  p.nseg = 1;
+  p.Cin = Cin; p.Cout = C; p.ldc = ldc;
+  p.M = M; p.N = N; p.nb0 = 1; p.nb1 = 1;
+  p.alpha = alpha; p.beta = beta; p.store = store; p.lower_tiles = lower_tiles;
+  return (int)bta::gemm_launch(&p, 1, s);
 }
 
 extern "C" __attribute__((visibility("default"))) int bta_internal_timing_read(double* ms, long long* launches) {
