@@ -92,8 +92,9 @@ def lib() -> ctypes.CDLL:
 
 def gemm_mode(mode: int = -1) -> int:
     """Select the GEMM kernels of the selected inversion (0 automatic,
-    1 register-staged, 2 direct-to-LDS where the operands allow); -1 only
-    queries.  Returns the previous mode."""
+    1 register-staged, 2 direct-to-LDS where the operands allow, 3 .. 7 one
+    direct-to-LDS kernel: 64 / 128 tiles, lean 64 x 64 / 128 x 64 / 128 x 128);
+    -1 only queries.  Returns the previous mode."""
     return int(lib().bta_internal_gemm_mode(int(mode)))
 
 def bta_workspace_bytes(op: int, n: int, b: int, a: int, nrhs: int = 0) -> int:

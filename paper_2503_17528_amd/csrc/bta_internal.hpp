@@ -94,7 +94,7 @@ hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream);
 // ---------------------------------------------------------------- selinv
 struct SelinvPlan {
   int64_t chunk;  // blocks per preprocessing chunk
-  size_t off_W, off_T1, off_P, off_Xp, off_WT, bytes;
+  size_t off_W, off_T1, off_PR, off_Xp, off_WT, bytes;
 };
 SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a);
 hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
@@ -146,9 +146,14 @@ struct Window {
   const void* base;
   int64_t rows, cols, ld;  // row-major window: element (r, c) at base + r*ld + c (doubles)
   bool write;
+  int op;  // launch that touches it
 };
 struct DryRecorder {
   std::vector<Window> windows;
+  int op = 0;
+  void add(const void* base, int64_t rows, int64_t cols, int64_t ld, bool write) {
+    windows.push_back(Window{base, rows, cols, ld, write, op});
+  }
 };
 extern thread_local DryRecorder* g_dry;
 

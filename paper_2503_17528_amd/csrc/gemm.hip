@@ -6,6 +6,8 @@
 // inversion for its products with the inverses of the diagonal factor blocks
 // (TRMM/LAUUM/TRTRI steps) and the two GEMMs of each backward step.
 #include <algorithm>
+#include <cmath>
+#include <type_traits>
 
 #include "bta_device.hpp"
 #include "bta_internal.hpp"
@@ -405,24 +407,34 @@ __device__ __forceinline__ void gemm_tile_dl(const GProb& P, long long local, in
     for (int jj = 0; jj < WN; ++jj)
       live[i][jj] = (rw + 16 * i < mext) && (cw + 16 * jj < next) &&
                     (P.store == ST_FULL || n0 + cw + 16 * jj <= m0 + rw + 16 * i + 15);
+  bool all_live = true;
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int jj = 0; jj < WN; ++jj) all_live = all_live && live[i][jj];
   if (total > 0) issue(0);
-  for (int kk = 0; kk < total; ++kk) {
-    // stage kk has landed for every wave, and every wave is done with stage kk-1
-    __syncthreads();
-    const bool first = kk < nk0;
-    const double* st = lds + (kk & 1) * C::STAGE;
-    double a[WM][4], b[WN][4];
-    stage_read<TM, WM>(a, st, first ? P.seg[0].at : P.seg[1].at, rw, lane);
-    stage_read<TN, WN>(b, st + C::SA, first ? P.seg[0].bt : P.seg[1].bt, cw, lane);
-    if (kk + 1 < total) issue(kk + 1);
+  auto kloop = [&](auto checked) {
+    constexpr bool CK = decltype(checked)::value;
+    for (int kk = 0; kk < total; ++kk) {
+      // stage kk has landed for every wave, and every wave is done with stage kk-1
+      __syncthreads();
+      const bool first = kk < nk0;
+      const double* st = lds + (kk & 1) * C::STAGE;
+      double a[WM][4], b[WN][4];
+      stage_read<TM, WM>(a, st, first ? P.seg[0].at : P.seg[1].at, rw, lane);
+      stage_read<TN, WN>(b, st + C::SA, first ? P.seg[0].bt : P.seg[1].bt, cw, lane);
+      if (kk + 1 < total) issue(kk + 1);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int i = 0; i < WM; ++i)
+        for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int jj = 0; jj < WN; ++jj)
-          if (live[i][jj]) acc.v[i][jj] = mfma16(a[i][q], b[jj][q], acc.v[i][jj]);
-  }
+          for (int jj = 0; jj < WN; ++jj)
+            if (!CK || live[i][jj]) acc.v[i][jj] = mfma16(a[i][q], b[jj][q], acc.v[i][jj]);
+    }
+  };
+  if (__builtin_amdgcn_readfirstlane((int)all_live)) kloop(std::false_type{});
+  else kloop(std::true_type{});
 
   const int64_t coff = b0 * P.sC0 + b1 * P.sC1;
   double* Cb = P.Cout + coff;
@@ -444,6 +456,179 @@ __device__ __forceinline__ void gemm_tile_dl(const GProb& P, long long local, in
   for (int bi = 0; bi < WM; ++bi)
 #pragma unroll
     for (int bj = 0; bj < WN; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = rw + 16 * bi + acc_row(lane, e), c = cw + 16 * bj + acc_col(lane);
+        const int gr = m0 + r, gc = n0 + c;
+        if (r >= mext || c >= next) continue;
+        if (P.store != ST_FULL && gc > gr) continue;
+        Cb[(int64_t)gr * P.ldc + gc] = acc.v[bi][bj][e];
+        if (P.store == ST_LOWER_MIRROR && gc < gr) Cb[(int64_t)gc * P.ldc + gr] = acc.v[bi][bj][e];
+      }
+}
+
+// ---------------------------------------------------------------- lean direct-to-LDS tile body
+// Waves WR x WC, each (16 BI) x (16 BJ) of the (16 BI WR) x (16 BJ WC) tile;
+// stages of BK = 16 as in gemm_tile_dl (same piece layouts).  The source of
+// each of a thread's pieces is resolved once per segment (pointer, validity,
+// k position); a stage only advances the pointers.
+template <int WR, int WC, int BI, int BJ>
+struct DL2 {
+  static constexpr int NW = WR * WC, NTH = NW * 64, TM = 16 * BI * WR, TN = 16 * BJ * WC, BK = 16;
+  static constexpr int SA = TM * BK, SB = TN * BK, STAGE = SA + SB;
+  static constexpr int PA = TM * BK / 2, PB = TN * BK / 2, PER_T = (PA + PB) / NTH;
+  static_assert((PA + PB) % NTH == 0 && PA % 64 == 0, "stage pieces per thread");
+};
+
+template <int WR, int WC, int BI, int BJ>
+__device__ __forceinline__ void gemm_tile_dl2(const GProb& P, long long local, int tid, double* lds) {
+  using C = DL2<WR, WC, BI, BJ>;
+  constexpr int TM = C::TM, TN = C::TN, BK = C::BK, PER = C::PER_T;
+  const int batch = (int)(local / P.tiles_per_batch);
+  const int tile = (int)(local - (long long)batch * P.tiles_per_batch);
+  const int b0 = batch / P.nb1, b1 = batch - b0 * P.nb1;
+  int tm, tn;
+  tile_coords<TM, TN>(P, tile, tm, tn);
+  const int m0 = tm * TM, n0 = tn * TN;
+  const int mext = min(TM, P.M - m0), next = min(TN, P.N - n0);
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+
+  auto krange = [&](const GSeg& g, int& k0, int& k1) {
+    k0 = 0;
+    k1 = g.K;
+    switch (g.tri) {
+      case TRI_K_GE_COL: k0 = n0; break;
+      case TRI_K_GE_ROW: k0 = m0; break;
+      case TRI_K_LE_ROW: k1 = min(g.K, m0 + TM); break;
+      case TRI_K_LE_COL: k1 = min(g.K, n0 + TN); break;
+      default: break;
+    }
+    k0 = (k0 / BK) * BK;
+    if (k0 > k1) k0 = k1;
+  };
+  int kb0, ke0, kb1 = 0, ke1 = 0;
+  krange(P.seg[0], kb0, ke0);
+  if (P.nseg > 1) krange(P.seg[1], kb1, ke1);
+  const int nk0 = (ke0 - kb0 + BK - 1) / BK;
+  const int total = nk0 + (ke1 - kb1 + BK - 1) / BK;
+
+  // per piece: source pointer at the segment's first stage, its advance per
+  // stage, the piece's k offset within a stage, and whether it is inside M / N
+  const double* src[PER];
+  int64_t inc[PER];
+  int kpos[PER];
+  bool inb[PER];
+  int seg_klen = 0;
+  auto setup = [&](int sidx) {
+    const GSeg& g = P.seg[sidx];
+    const int kb = sidx == 0 ? kb0 : kb1;
+    seg_klen = (sidx == 0 ? ke0 : ke1) - kb;
+    const double* Ab = g.A + b0 * g.sA0 + b1 * g.sA1;
+    const double* Bb = g.B + b0 * g.sB0 + b1 * g.sB1;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int slot = (wave * PER + j) * 64 + lane;
+      const bool isA = slot < C::PA;
+      const int sl = isA ? slot : slot - C::PA;
+      const int R = isA ? TM : TN;
+      const int r0 = isA ? m0 : n0, rext = isA ? mext : next;
+      const double* base = isA ? Ab : Bb;
+      const int64_t ld = isA ? g.lda : g.ldb;
+      const int tr = isA ? g.at : g.bt;
+      if (!tr) {
+        const int m = sl >> 3, pc = (sl & 7) ^ swzN(m);
+        src[j] = base + (int64_t)(r0 + m) * ld + kb + 2 * pc;
+        inc[j] = BK;
+        kpos[j] = 2 * pc;
+        inb[j] = m < rext;
+      } else {
+        const int PRT = R / 2;
+        const int kr = sl / PRT, qc = (sl - kr * PRT) ^ swzT(kr);
+        src[j] = base + (int64_t)(kb + kr) * ld + r0 + 2 * qc;
+        inc[j] = (int64_t)BK * ld;
+        kpos[j] = kr;
+        inb[j] = 2 * qc < rext;
+      }
+    }
+  };
+  int stage_in_seg = 0;
+  auto issue = [&](int kk) {
+    if (kk == 0) { setup(0); stage_in_seg = 0; }
+    if (kk == nk0) { setup(1); stage_in_seg = 0; }
+    double* st = lds + (kk & 1) * C::STAGE;
+    const int krel = stage_in_seg * BK;
+    const bool full = krel + BK <= seg_klen;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const bool ok = inb[j] && (full || krel + kpos[j] < seg_klen);
+      load_piece_lds(ok ? src[j] : g_zero_piece, st + (wave * PER + j) * 128);
+      src[j] += inc[j];
+    }
+    ++stage_in_seg;
+  };
+
+  AccT<BI, BJ> acc;
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int jj = 0; jj < BJ; ++jj) acc.v[i][jj] = d4{0.0, 0.0, 0.0, 0.0};
+  const int rw = 16 * BI * (wave / WC), cw = 16 * BJ * (wave % WC);
+  bool live[BI][BJ];
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int jj = 0; jj < BJ; ++jj)
+      live[i][jj] = (rw + 16 * i < mext) && (cw + 16 * jj < next) &&
+                    (P.store == ST_FULL || n0 + cw + 16 * jj <= m0 + rw + 16 * i + 15);
+  bool all_live = true;
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int jj = 0; jj < BJ; ++jj) all_live = all_live && live[i][jj];
+  if (total > 0) issue(0);
+  // the k loop, with the per-block checks only where a block can be dead
+  auto kloop = [&](auto checked) {
+    constexpr bool CK = decltype(checked)::value;
+    for (int kk = 0; kk < total; ++kk) {
+      __syncthreads();
+      const bool first = kk < nk0;
+      const double* st = lds + (kk & 1) * C::STAGE;
+      double a[BI][4], b[BJ][4];
+      stage_read<TM, BI>(a, st, first ? P.seg[0].at : P.seg[1].at, rw, lane);
+      stage_read<TN, BJ>(b, st + C::SA, first ? P.seg[0].bt : P.seg[1].bt, cw, lane);
+      if (kk + 1 < total) issue(kk + 1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int i = 0; i < BI; ++i)
+#pragma unroll
+          for (int jj = 0; jj < BJ; ++jj)
+            if (!CK || live[i][jj]) acc.v[i][jj] = mfma16(a[i][q], b[jj][q], acc.v[i][jj]);
+    }
+  };
+  if (__builtin_amdgcn_readfirstlane((int)all_live)) kloop(std::false_type{});
+  else kloop(std::true_type{});
+
+  const int64_t coff = b0 * P.sC0 + b1 * P.sC1;
+  double* Cb = P.Cout + coff;
+  const double* Cib = P.Cin ? P.Cin + coff : nullptr;
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = rw + 16 * bi + acc_row(lane, e), c = cw + 16 * bj + acc_col(lane);
+        const int gr = m0 + r, gc = n0 + c;
+        double v = P.alpha * acc.v[bi][bj][e];
+        const bool lv = r < mext && c < next && !(P.store != ST_FULL && gc > gr);
+        if (lv && P.beta != 0.0) v += P.beta * Cib[(int64_t)gr * P.ldc + gc];
+        acc.v[bi][bj][e] = v;
+      }
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int r = rw + 16 * bi + acc_row(lane, e), c = cw + 16 * bj + acc_col(lane);
@@ -496,6 +681,27 @@ __global__ __launch_bounds__(NT, 4) void gemm_dl64_kernel(GemmArgs args) {
   const long long t = xcd_tile(blockIdx.x, gridDim.x);
   const int j = find_prob(args, t);
   gemm_tile_dl<2, 2>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
+}
+
+__global__ __launch_bounds__(256, 2) void gemm_l64_kernel(GemmArgs args) {
+  __shared__ __align__(16) double lds[2 * DL2<2, 2, 2, 2>::STAGE];
+  const long long t = xcd_tile(blockIdx.x, gridDim.x);
+  const int j = find_prob(args, t);
+  gemm_tile_dl2<2, 2, 2, 2>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
+}
+
+__global__ __launch_bounds__(512, 3) void gemm_l128x64_kernel(GemmArgs args) {
+  __shared__ __align__(16) double lds[2 * DL2<4, 2, 2, 2>::STAGE];
+  const long long t = xcd_tile(blockIdx.x, gridDim.x);
+  const int j = find_prob(args, t);
+  gemm_tile_dl2<4, 2, 2, 2>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
+}
+
+__global__ __launch_bounds__(512, 2) void gemm_l128_kernel(GemmArgs args) {
+  __shared__ __align__(16) double lds[2 * DL2<4, 2, 2, 4>::STAGE];
+  const long long t = xcd_tile(blockIdx.x, gridDim.x);
+  const int j = find_prob(args, t);
+  gemm_tile_dl2<4, 2, 2, 4>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
 }
 
 // The same tile bodies over a problem list in device memory (batched launches):
@@ -583,13 +789,13 @@ static void record_gemm(const GProb& p) {
         if (g.K <= 0) continue;
         const double* A = g.A + b0 * g.sA0 + b1 * g.sA1;
         const double* B = g.B + b0 * g.sB0 + b1 * g.sB1;
-        g_dry->windows.push_back(g.at ? Window{A, g.K, p.M, g.lda, false} : Window{A, p.M, g.K, g.lda, false});
-        g_dry->windows.push_back(g.bt ? Window{B, g.K, p.N, g.ldb, false} : Window{B, p.N, g.K, g.ldb, false});
+        if (g.at) g_dry->add(A, g.K, p.M, g.lda, false); else g_dry->add(A, p.M, g.K, g.lda, false);
+        if (g.bt) g_dry->add(B, g.K, p.N, g.ldb, false); else g_dry->add(B, p.N, g.K, g.ldb, false);
       }
       const int64_t off = b0 * p.sC0 + b1 * p.sC1;
-      if (p.beta != 0.0) g_dry->windows.push_back(Window{p.Cin + off, p.M, p.N, p.ldc, false});
-      g_dry->windows.push_back(Window{p.Cout + off, p.M, p.N, p.ldc, true});
-      if (p.store == ST_LOWER_MIRROR) g_dry->windows.push_back(Window{p.Cout + off, p.N, p.M, p.ldc, true});
+      if (p.beta != 0.0) g_dry->add(p.Cin + off, p.M, p.N, p.ldc, false);
+      g_dry->add(p.Cout + off, p.M, p.N, p.ldc, true);
+      if (p.store == ST_LOWER_MIRROR) g_dry->add(p.Cout + off, p.N, p.M, p.ldc, true);
     }
 }
 
@@ -632,8 +838,9 @@ static bool dl_ok(const GProb& p) {
 }
 
 // 0: choose per launch; 1: register-staged kernels only; 2: direct-to-LDS
-// kernels wherever the operands allow; 3 / 4: direct-to-LDS with 64 / 128
-// tiles only (tests run every path through this).
+// kernels wherever the operands allow; 3 / 4: first direct-to-LDS body with 64
+// / 128 tiles; 5 / 6 / 7: lean body with 64 x 64 / 128 x 64 / 128 x 128 tiles
+// (tests run every path through this).
 static int g_gemm_mode = 0;
 
 // Sum over the tiles of a planned launch of the fraction of MFMA blocks a
@@ -665,31 +872,42 @@ hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream) {
     return hipSuccess;
   }
   if (g_dry) {
+    ++g_dry->op;
     for (int i = 0; i < nprob; ++i)
       if (probs[i].M > 0 && probs[i].N > 0) record_gemm(probs[i]);
     return hipSuccess;
   }
   bool dl = g_gemm_mode != 1;
   for (int i = 0; i < nprob; ++i) dl = dl && dl_ok(probs[i]);
-  GemmArgs big{}, small{};
+  GemmArgs big{}, small{}, mid{};
   const long long t128 = plan_tiles(big, probs, nprob, 128, 128);
   const long long t64 = plan_tiles(small, probs, nprob, 64, 64);
+  const long long t12864 = plan_tiles(mid, probs, nprob, 128, 64);
   if (t64 == 0) return hipSuccess;
   if (dl) {
-    // makespan model in units of one 64 x 64 tile: the work of a launch (tiles
-    // weighted by the MFMA blocks they compute) spread over the CUs, and at
-    // least one whole tile; a 128-tile is four 64-tiles
-    const double cus = std::max(1, device_cu_count());
-    const double c128 = 4.0 * std::max(tile_weight(big, 128, 128) / cus, 1.0);
-    const double c64 = std::max(tile_weight(small, 64, 64) / cus, 1.0);
+    int kind = g_gemm_mode >= 3 ? g_gemm_mode : 0;
+    if (kind == 0) {
+      // 128 x 128 tiles (the most efficient per flop) when they fill the CUs
+      // in whole rounds (at least 3/4 of the last round) and are mostly full
+      // (ragged tiles cost nearly a whole tile of loads); otherwise 64 x 64
+      // tiles, with the first direct-to-LDS body for lower-triangle stores
+      // (fewer, unevenly sized tiles).
+      const double cus = std::max(1, device_cu_count());
+      const double rounds = std::ceil((double)t128 / cus);
+      const bool fill = (double)t128 >= 0.75 * rounds * cus;
+      const bool full = tile_weight(big, 128, 128) >= 0.85 * (double)t128;
+      bool lower_only = true;
+      for (int i = 0; i < nprob; ++i) lower_only = lower_only && probs[i].lower_tiles;
+      kind = (fill && full) ? 7 : (lower_only ? 3 : 5);
+    }
     timing_mark(KT_GEMM, true, stream);
-    // measured: the 128-tile kernel runs ~1.4x slower per flop than the
-    // 64-tile one, so it only pays when 64-tiles leave most CUs idle
-    const bool use128 = g_gemm_mode == 4 || (g_gemm_mode != 3 && 1.4 * c128 < c64);
-    if (use128)
-      hipLaunchKernelGGL(gemm_dl128_kernel, dim3((unsigned)t128), dim3(NT), 0, stream, big);
-    else
-      hipLaunchKernelGGL(gemm_dl64_kernel, dim3((unsigned)t64), dim3(NT), 0, stream, small);
+    switch (kind) {
+      case 3: hipLaunchKernelGGL(gemm_dl64_kernel, dim3((unsigned)t64), dim3(NT), 0, stream, small); break;
+      case 4: hipLaunchKernelGGL(gemm_dl128_kernel, dim3((unsigned)t128), dim3(NT), 0, stream, big); break;
+      case 5: hipLaunchKernelGGL(gemm_l64_kernel, dim3((unsigned)t64), dim3(256), 0, stream, small); break;
+      case 7: hipLaunchKernelGGL(gemm_l128_kernel, dim3((unsigned)t128), dim3(512), 0, stream, big); break;
+      default: hipLaunchKernelGGL(gemm_l128x64_kernel, dim3((unsigned)t12864), dim3(512), 0, stream, mid); break;
+    }
     timing_mark(KT_GEMM, false, stream);
     return hipGetLastError();
   }
@@ -746,9 +964,10 @@ hipError_t trinv_diag_tiles_launch(const double* L, int64_t ldL, int64_t sL, dou
     return hipSuccess;
   }
   if (g_dry) {
+    ++g_dry->op;
     for (int blk = 0; blk < nblk; ++blk) {
-      g_dry->windows.push_back(Window{L + blk * sL, m, m, ldL, false});
-      g_dry->windows.push_back(Window{W + blk * sW, m, m, ldW, true});
+      g_dry->add(L + blk * sL, m, m, ldL, false);
+      g_dry->add(W + blk * sW, m, m, ldW, true);
     }
     return hipSuccess;
   }
@@ -769,7 +988,8 @@ hipError_t fill_zero_launch(double* p, size_t count, hipStream_t stream) {
     return hipSuccess;
   }
   if (g_dry) {
-    g_dry->windows.push_back(Window{p, 1, (int64_t)count, (int64_t)count, true});
+    ++g_dry->op;
+    g_dry->add(p, 1, (int64_t)count, (int64_t)count, true);
     return hipSuccess;
   }
   const unsigned grid = (unsigned)std::min<size_t>(4096, (count + 255) / 256);
@@ -782,8 +1002,19 @@ __global__ void copy2d_kernel(const double* src, int64_t lds, int64_t ss, double
   const int blk = blockIdx.y;
   const double* s = src + blk * ss;
   double* d = dst + blk * sd;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const bool pairs = ((cols | lds | ldd) & 1) == 0 && ((reinterpret_cast<uintptr_t>(s) | reinterpret_cast<uintptr_t>(d)) & 15) == 0;
+  if (pairs) {  // 16-byte moves
+    const int hc = cols >> 1;
+    const long long total = (long long)rows * hc;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+      const int r = (int)(e / hc), c = 2 * (int)(e - (long long)r * hc);
+      *reinterpret_cast<double2*>(d + (int64_t)r * ldd + c) = *reinterpret_cast<const double2*>(s + (int64_t)r * lds + c);
+    }
+    return;
+  }
   const long long total = (long long)rows * cols;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int r = (int)(e / cols), c = (int)(e - (long long)r * cols);
     d[(int64_t)r * ldd + c] = s[(int64_t)r * lds + c];
   }
@@ -797,9 +1028,10 @@ hipError_t copy2d_launch(const double* src, int64_t lds, int64_t ss, double* dst
     return hipSuccess;
   }
   if (g_dry) {
+    ++g_dry->op;
     for (int b = 0; b < nb; ++b) {
-      g_dry->windows.push_back(Window{src + b * ss, rows, cols, lds, false});
-      g_dry->windows.push_back(Window{dst + b * sd, rows, cols, ldd, true});
+      g_dry->add(src + b * ss, rows, cols, lds, false);
+      g_dry->add(dst + b * sd, rows, cols, ldd, true);
     }
     return hipSuccess;
   }
@@ -836,12 +1068,10 @@ extern "C" __attribute__((visibility("default"))) int bta_internal_timing(int on
   return 0;
 }
 
-// Internal GEMM kernel selection (0 automatic, 1 register-staged only,
-// 2 direct-to-LDS where possible, 3 / 4 direct-to-LDS with 64 / 128 tiles);
-// returns the previous mode.
+// Internal GEMM kernel selection (see g_gemm_mode); returns the previous mode.
 extern "C" __attribute__((visibility("default"))) int bta_internal_gemm_mode(int mode) {
   const int prev = bta::g_gemm_mode;
-  if (mode >= 0 && mode <= 4) bta::g_gemm_mode = mode;
+  if (mode >= 0 && mode <= 7) bta::g_gemm_mode = mode;
   return prev;
 }
 

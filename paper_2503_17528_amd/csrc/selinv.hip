@@ -14,6 +14,11 @@
 // blocks up front in large batched launches (chunks of blocks); the
 // sequential backward sweep is then two MFMA GEMM launches per step.
 //   X_{n,n} = L_nn^{-T} L_nn^{-1} comes from the same inverse + product.
+//
+// The arrow rows form a recursion of their own, X_{n,i} = -(X_{n,i+1} P_B +
+// X_nn P_R), which does not involve the diagonal blocks; it runs on the
+// preprocessing stream right after each chunk's products, so that the sweep
+// proper is one b x b product and one lower-triangular b x b product per step.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -163,23 +168,37 @@ SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a) {
   SelinvPlan sp{};
   const int64_t T = (b + 63) / 64;
   // enough blocks per chunk to give the 64-tile inverses ~512 workgroups,
-  // within ~4 GB of workspace (W, T1 and P per block of the chunk)
+  // within ~4 GB of workspace (W and T1 per block of the chunk)
   int64_t chunk = (512 + T - 1) / T;
-  const int64_t per_block = 8 * (2 * b * b + (b + a) * b);
+  const int64_t per_block = 8 * (2 * b * b);
   chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, (int64_t(4) << 30) / per_block));
   chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, 64));
   chunk = std::min<int64_t>(chunk, n);
   sp.chunk = chunk;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
-  const size_t bb = (size_t)b * b, pb = (size_t)(b + a) * b;
+  const size_t bb = (size_t)b * b;
   sp.off_W = take(8 * bb * chunk);
   sp.off_T1 = take(8 * bb * chunk);
-  sp.off_P = take(8 * pb * chunk);
-  sp.off_Xp = take(8 * pb);
+  sp.off_PR = take(8 * (size_t)std::max<int64_t>(1, a * b * n));
+  sp.off_Xp = take(8 * bb);
   sp.off_WT = take(8 * (size_t)std::max<int64_t>(1, 2 * a * a));
   sp.bytes = off;
   return sp;
+}
+
+// Preprocessing chunks [i0, i1), from the last block down: the first ones
+// small, so that the sweep starts early, then doubling up to sp.chunk.
+static std::vector<std::pair<int64_t, int64_t>> selinv_chunks(const SelinvPlan& sp, int64_t n) {
+  std::vector<std::pair<int64_t, int64_t>> c;
+  int64_t size = std::min<int64_t>(sp.chunk, 2), i1 = n;
+  while (i1 > 0) {
+    const int64_t i0 = std::max<int64_t>(0, i1 - size);
+    c.emplace_back(i0, i1);
+    i1 = i0;
+    size = std::min<int64_t>(sp.chunk, 2 * size);
+  }
+  return c;
 }
 
 hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
@@ -189,11 +208,14 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
   char* w = static_cast<char*>(work);
   double* Ws = reinterpret_cast<double*>(w + sp.off_W);
   double* T1 = reinterpret_cast<double*>(w + sp.off_T1);
-  double* Pw = reinterpret_cast<double*>(w + sp.off_P);
   double* Xp = reinterpret_cast<double*>(w + sp.off_Xp);
+  double* PR = reinterpret_cast<double*>(w + sp.off_PR);  // P_R of every block (a x b each)
   double* WT = reinterpret_cast<double*>(w + sp.off_WT);
-  const int64_t bb = b * b, ab = a * b, pb = (b + a) * b;
+  const int64_t bb = b * b, ab = a * b;
   const int ib = (int)b, ia = (int)a;
+  // outputs may alias the inputs exactly: P_B = L_{i+1,i} W_i then goes to
+  // staging (T1, free once the inverses are done) and is copied afterwards
+  const bool inplace = n > 1 && XB == LB;
 
   // ---- tip: X_nn = W_T^T W_T
   if (a > 0) {
@@ -212,9 +234,10 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
     BTA_TRY(gemm_launch(&p, 1, s));
   }
 
-  // ---- per-block preprocessing on a side stream, chunk by chunk from the
-  // last block down, so that the backward sweep (on `s`) can start on the
-  // first finished chunk while later chunks fill the CUs the sweep leaves idle.
+  // ---- per-block preprocessing and the arrow-row recursion on a side
+  // stream, chunk by chunk from the last block down, so that the backward
+  // sweep (on `s`) can start on the first finished chunk while later chunks
+  // fill the CUs the sweep leaves idle.
   const bool dry = recording();
   hipStream_t sa = dry ? s : side_stream();
   if (!dry) {
@@ -222,9 +245,9 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
     BTA_TRY(hipEventRecord(event_at(0), s));
     BTA_TRY(hipStreamWaitEvent(sa, event_at(0), 0));
   }
-  const int64_t nchunks = (n + sp.chunk - 1) / sp.chunk;
-  for (int64_t k = 0; k < nchunks; ++k) {
-    const int64_t i1 = n - k * sp.chunk, i0 = std::max<int64_t>(0, i1 - sp.chunk);
+  const auto chunks = selinv_chunks(sp, n);
+  for (size_t k = 0; k < chunks.size(); ++k) {
+    const int64_t i0 = chunks[k].first, i1 = chunks[k].second;
     const int nblk = (int)(i1 - i0);
     const int nsub = (int)std::min<int64_t>(nblk, (n - 1) - i0);  // blocks of the chunk with an L_{i+1,i}
     set_stage(1, (int)k, 0);
@@ -233,11 +256,11 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
     set_stage(1, (int)k, 100);
     GProb pr[3];
     int np = 0;
-    if (nsub > 0) {  // P_B = L_{i+1,i} W_i
+    if (nsub > 0) {  // P_B = L_{i+1,i} W_i into the X_{i+1,i} slot
       GProb p = prob_init();
       p.seg[0] = seg(LB + i0 * bb, b, 0, Ws, b, 1, ib, TRI_K_GE_COL, bb, bb);
       p.nseg = 1;
-      p.Cout = Pw; p.ldc = b; p.sC0 = pb;
+      p.Cout = inplace ? T1 : XB + i0 * bb; p.ldc = b; p.sC0 = bb;
       p.M = ib; p.N = ib; p.nb0 = nsub;
       pr[np++] = p;
     }
@@ -245,7 +268,7 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       GProb p = prob_init();
       p.seg[0] = seg(LR + i0 * ab, b, 0, Ws, b, 1, ib, TRI_K_GE_COL, ab, bb);
       p.nseg = 1;
-      p.Cout = Pw + bb; p.ldc = b; p.sC0 = pb;
+      p.Cout = PR + i0 * ab; p.ldc = b; p.sC0 = ab;
       p.M = ia; p.N = ib; p.nb0 = nblk;
       pr[np++] = p;
     }
@@ -260,56 +283,60 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       pr[np++] = p;
     }
     BTA_TRY(gemm_launch(pr, np, sa));
-    set_stage(1, (int)k, 101);
-    BTA_TRY(copy2d_launch(Pw, b, pb, XB + i0 * bb, b, bb, ib, ib, nsub, sa));
-    set_stage(1, (int)k, 102);
-    if (a > 0) BTA_TRY(copy2d_launch(Pw + bb, b, pb, XR + i0 * ab, b, ab, ia, ib, nblk, sa));
+    if (inplace) {  // every L_{i+1,i} of the chunk has been read
+      set_stage(1, (int)k, 101);
+      BTA_TRY(copy2d_launch(T1, b, bb, XB + i0 * bb, b, bb, ib, ib, nsub, sa));
+    }
+    // arrow rows of the chunk: X_{n,i} = -(X_{n,i+1} P_B + X_nn P_R)
+    for (int64_t i = i1 - 1; a > 0 && i >= i0; --i) {
+      set_stage(1, (int)k, 200 + (int)(i1 - 1 - i));
+      GProb p = prob_init();
+      if (i < n - 1) {
+        p.seg[0] = seg(XR + (i + 1) * ab, b, 0, XB + i * bb, b, 1, ib, TRI_NONE);
+        p.seg[1] = seg(XT, a, 0, PR + i * ab, b, 1, ia, TRI_NONE);
+        p.nseg = 2;
+      } else {
+        p.seg[0] = seg(XT, a, 0, PR + i * ab, b, 1, ia, TRI_NONE);
+        p.nseg = 1;
+      }
+      p.Cout = XR + i * ab; p.ldc = b;
+      p.M = ia; p.N = ib;
+      p.alpha = -1.0;
+      BTA_TRY(gemm_launch(&p, 1, sa));
+    }
     if (!dry) BTA_TRY(hipEventRecord(event_at(1 + (int)k), sa));
   }
 
   // ---- backward sweep
+  size_t next_chunk = 0;
   for (int64_t i = n - 1; i >= 0; --i) {
     // first step of a preprocessing chunk: wait for that chunk
-    if (!dry && (n - 1 - i) % sp.chunk == 0) BTA_TRY(hipStreamWaitEvent(s, event_at(1 + (int)((n - 1 - i) / sp.chunk)), 0));
+    if (next_chunk < chunks.size() && i == chunks[next_chunk].second - 1) {
+      if (!dry) BTA_TRY(hipStreamWaitEvent(s, event_at(1 + (int)next_chunk), 0));
+      ++next_chunk;
+    }
     const bool has_sub = i < n - 1;
     const int step = (int)(n - 1 - i);
     set_stage(2, step, 0);
-    const double* PB = has_sub ? XB + i * bb : nullptr;
-    const double* PR = a > 0 ? XR + i * ab : nullptr;
-    GProb pr[2];
-    int np = 0;
+    const double* PB = XB + i * bb;
+    const double* PRi = PR + i * ab;
     if (has_sub) {  // X_{i+1,i} = -(X_{i+1,i+1} P_B + X_{n,i+1}^T P_R)
       GProb p = prob_init();
       p.seg[0] = seg(XD + (i + 1) * bb, b, 0, PB, b, 1, ib, TRI_NONE);
       p.nseg = 1;
-      if (a > 0) { p.seg[1] = seg(XR + (i + 1) * ab, b, 1, PR, b, 1, ia, TRI_NONE); p.nseg = 2; }
+      if (a > 0) { p.seg[1] = seg(XR + (i + 1) * ab, b, 1, PRi, b, 1, ia, TRI_NONE); p.nseg = 2; }
       p.Cout = Xp; p.ldc = b;
       p.M = ib; p.N = ib;
       p.alpha = -1.0;
-      pr[np++] = p;
+      BTA_TRY(gemm_launch(&p, 1, s));
     }
-    if (a > 0) {  // X_{n,i} = -(X_{n,i+1} P_B + X_nn P_R)
-      GProb p = prob_init();
-      if (has_sub) {
-        p.seg[0] = seg(XR + (i + 1) * ab, b, 0, PB, b, 1, ib, TRI_NONE);
-        p.seg[1] = seg(XT, a, 0, PR, b, 1, ia, TRI_NONE);
-        p.nseg = 2;
-      } else {
-        p.seg[0] = seg(XT, a, 0, PR, b, 1, ia, TRI_NONE);
-        p.nseg = 1;
-      }
-      p.Cout = Xp + bb; p.ldc = b;
-      p.M = ia; p.N = ib;
-      p.alpha = -1.0;
-      pr[np++] = p;
-    }
-    BTA_TRY(gemm_launch(pr, np, s));
     set_stage(2, step, 1);
-    {  // X_ii = V_i - [X_{i+1,i}; X_{n,i}]^T P_i  (lower, mirrored)
+    {  // X_ii = V_i - X_{i+1,i}^T P_B - X_{n,i}^T P_R  (lower, mirrored; no
+       // segments when n == 1 and a == 0: the mirror of V_0)
       GProb p = prob_init();
       p.nseg = 0;
       if (has_sub) p.seg[p.nseg++] = seg(Xp, b, 1, PB, b, 1, ib, TRI_NONE);
-      if (a > 0) p.seg[p.nseg++] = seg(Xp + bb, b, 1, PR, b, 1, ia, TRI_NONE);
+      if (a > 0) p.seg[p.nseg++] = seg(XR + i * ab, b, 1, PRi, b, 1, ia, TRI_NONE);
       p.Cin = XD + i * bb; p.Cout = XD + i * bb; p.ldc = b;
       p.M = ib; p.N = ib;
       p.alpha = -1.0; p.beta = 1.0;
@@ -317,28 +344,43 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       p.store = ST_LOWER_MIRROR;
       BTA_TRY(gemm_launch(&p, 1, s));
     }
-    set_stage(2, step, 2);
-    if (has_sub) BTA_TRY(copy2d_launch(Xp, b, 0, XB + i * bb, b, 0, ib, ib, 1, s));
     set_stage(2, step, 3);
-    if (a > 0) BTA_TRY(copy2d_launch(Xp + bb, b, 0, XR + i * ab, b, 0, ia, ib, 1, s));
+    if (has_sub) BTA_TRY(copy2d_launch(Xp, b, 0, XB + i * bb, b, 0, ib, ib, 1, s));
   }
   return hipSuccess;
 }
 
+// Whether two windows of one launch share an element (exact rectangle test
+// when both have the same leading dimension, byte spans otherwise).
+static bool windows_meet(const Window& x, const Window& y) {
+  const intptr_t bx = reinterpret_cast<intptr_t>(x.base), by = reinterpret_cast<intptr_t>(y.base);
+  const intptr_t ex = bx + 8 * ((x.rows - 1) * x.ld + x.cols), ey = by + 8 * ((y.rows - 1) * y.ld + y.cols);
+  if (ex <= by || ey <= bx) return false;
+  if (x.ld != y.ld || (bx - by) % 8 != 0) return true;
+  const int64_t ox = (bx - std::min(bx, by)) / 8, oy = (by - std::min(bx, by)) / 8;
+  const int64_t rx = ox / x.ld, cx = ox % x.ld, ry = oy / y.ld, cy = oy % y.ld;
+  if (cx + x.cols > x.ld || cy + y.cols > y.ld) return true;
+  return rx < ry + y.rows && ry < rx + x.rows && cx < cy + y.cols && cy < cx + x.cols;
+}
+
 // Host dry run of selinv_launch with fake, widely separated array bases:
 // every window any launch would touch must lie inside one array (inputs are
-// never written).  Returns 0 when all windows are in bounds.
-int selinv_dry_check(int64_t n, int64_t b, int64_t a) {
+// never written out of place), and no launch may write an element that it
+// also reads through another window (identical windows are the epilogue's
+// read-then-write of its own C tile).  In place (outputs = inputs) the same
+// checks run with the bounds of the shared arrays.  Returns 0 when all hold.
+static int selinv_dry_run(int64_t n, int64_t b, int64_t a, bool inplace) {
   const SelinvPlan sp = selinv_plan(n, b, a);
   const uintptr_t G = uintptr_t(1) << 40;
   const size_t sz[9] = {(size_t)(n * b * b) * 8, (size_t)((n - 1) * b * b) * 8, (size_t)(n * a * b) * 8, (size_t)(a * a) * 8,
                         (size_t)(n * b * b) * 8, (size_t)((n - 1) * b * b) * 8, (size_t)(n * a * b) * 8, (size_t)(a * a) * 8,
                         sp.bytes};
   auto base = [&](int k) { return reinterpret_cast<double*>((uintptr_t)(k + 1) * G); };
+  const int xo = inplace ? 0 : 4;
   DryRecorder rec;
   g_dry = &rec;
-  hipError_t e = selinv_launch(sp, n, b, a, base(0), base(1), base(2), base(3), base(4), base(5), base(6), base(7),
-                               reinterpret_cast<void*>(base(8)), nullptr);
+  hipError_t e = selinv_launch(sp, n, b, a, base(0), base(1), base(2), base(3), base(xo), base(xo + 1), base(xo + 2),
+                               base(xo + 3), reinterpret_cast<void*>(base(8)), nullptr);
   g_dry = nullptr;
   if (e != hipSuccess) return 1;
   for (const Window& w : rec.windows) {
@@ -350,9 +392,26 @@ int selinv_dry_check(int64_t n, int64_t b, int64_t a) {
     const size_t first = addr - (uintptr_t)(arr + 1) * G;
     const size_t last = first + 8 * ((size_t)(w.rows - 1) * w.ld + (w.cols - 1));
     if (last + 8 > sz[arr]) return 4;
-    if (w.write && arr < 4) return 5;  // inputs are read only (out of place)
+    if (!inplace && w.write && arr < 4) return 5;
+  }
+  for (size_t i = 0; i < rec.windows.size(); ++i) {
+    const Window& x = rec.windows[i];
+    if (!x.write || x.rows <= 0 || x.cols <= 0) continue;
+    for (size_t j = 0; j < rec.windows.size(); ++j) {
+      const Window& y = rec.windows[j];
+      if (j == i || y.op != x.op || y.rows <= 0 || y.cols <= 0) continue;
+      const bool same = y.base == x.base && y.rows == x.rows && y.cols == x.cols && y.ld == x.ld;
+      if (!same && windows_meet(x, y)) return 6;
+    }
   }
   return 0;
+}
+
+int selinv_dry_check(int64_t n, int64_t b, int64_t a) {
+  const int r = selinv_dry_run(n, b, a, false);
+  if (r) return r;
+  const int q = selinv_dry_run(n, b, a, true);
+  return q ? 10 + q : 0;
 }
 
 }  // namespace bta

@@ -64,7 +64,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("mode", [1, 3, 4])
+@pytest.mark.parametrize("mode", [1, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(str(v) for v in c))
 def test_gemm_kernels_match_reference(lib, case, mode):
     import torch
