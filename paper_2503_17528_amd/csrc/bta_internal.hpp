@@ -19,7 +19,7 @@ constexpr int FACTOR_LOOKAHEAD = 8;
 struct FactorPlan {
   int T, TA, look;
   long long nflags, step_full, step_last, ntasks;
-  size_t off_ctl, off_flags, off_Wd, off_Wt, off_P, bytes;
+  size_t off_ctl, off_flags, off_Wd, off_Wt, off_P, off_Pacc, bytes;
 };
 FactorPlan factor_plan(int64_t n, int64_t b, int64_t a);
 hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,

@@ -21,10 +21,17 @@
 // arithmetic outside the diagonal tiles runs on FP64 MFMA.
 //
 // The diagonal tiles form the critical path (each needs the one before it).
-// A DIAG task therefore also computes the tile just left of its diagonal tile
-// in the band, L(g, g-1) (L_ii(c,c-1), or L_{i,i-1}(0,T-1) at c = 0), which the
-// diagonal tile needs last: the two share their left operands in one k loop,
-// and the chain of diagonal tiles takes one workgroup hop per tile.
+// The tile just left of a diagonal tile in the band, L(g, g-1) (L_ii(c,c-1),
+// or L_{i,i-1}(0,T-1) at c = 0), is the last input of the diagonal tile, so
+// the two are produced together: one k loop accumulates both (they share
+// their left operands) up to k = g-2, then L(g, g-1) = (...) W(g-1)^T is
+// formed and its product added, and the diagonal tile is factored.  In the
+// single-matrix kernel the k loops run as PART tasks (in the DIAG slots of
+// the ticket order) that hand their two partial sums to one chain workgroup,
+// which walks the diagonal tiles in band order and keeps W(g-1) in LDS from
+// one link to the next: the critical path then holds no workgroup hop and no
+// reload of W.  The batched kernel runs each diagonal tile as one DIAG task
+// that does all of it.
 //
 // Workgroups take task tickets from an atomic counter in a fixed topological
 // order (column by column across the whole band), so a task only ever waits
@@ -41,6 +48,11 @@ namespace bta {
 
 enum : int { T_DIAG = 0, T_OFFD = 1, T_SUB = 2, T_ARW = 3, T_TUPD = 4, T_TIPD = 5, T_TIPO = 6 };
 
+// The chain-workgroup schedule is switched off: its first GPU run (n = 1,
+// b = 3, a = 0) did not complete, and no cause has been established yet.
+// With it off, every diagonal tile runs as one DIAG task.
+constexpr bool kFactorChain = false;
+
 struct FactorParams {
   int n, b, a;
   int T;   // tiles per block edge: ceil(b/64)
@@ -52,6 +64,8 @@ struct FactorParams {
   double* P;       // [n][TA][TA] 64x64 per-step tip updates
   int* flags;      // completion flags
   int* ctl;        // [0..1] 64-bit ticket counter, [2] abort flag
+  int chain;       // 1: diagonal tiles by the chain workgroup (block 0), DIAG tickets run as PART tasks
+  double* Pacc;    // chain: [n][T] the two partial sums of each diagonal tile (2 x 4096, accumulator order)
   int64_t* info;   // caller's info
   long long ntasks;
   long long step_full, step_last;  // tasks per step (with / without SUB)
@@ -59,7 +73,8 @@ struct FactorParams {
   long long spin_limit;
   unsigned long long* trace;  // optional: 8 words per ticket (start, k loop done, end, type | workgroup << 8,
                               // W ready (DIAG: of g-1), L(g,g-1) published (DIAG), tile factored (DIAG),
-                              // end of the last blocking wait in the k loop)
+                              // end of the last blocking wait in the k loop); chain: then 8 words per
+                              // link (start, partial sums ready, -, L(g,g-1) published, factored, end)
 };
 
 struct Task {
@@ -80,6 +95,9 @@ __host__ __device__ inline int64_t fl_U(const FactorParams& p, int i, int r, int
 }
 __host__ __device__ inline int64_t fl_tip(const FactorParams& p, int r, int c) {
   return fl_D(p, p.n, 0, 0) + (int64_t)r * p.TA + c;
+}
+__host__ __device__ inline int64_t fl_part(const FactorParams& p, int i, int c) {
+  return fl_D(p, p.n, 0, 0) + (int64_t)p.TA * p.TA + (int64_t)i * p.T + c;
 }
 
 __host__ __device__ __forceinline__ Task decode(const FactorParams& p, long long t) {
@@ -311,49 +329,33 @@ __device__ __forceinline__ void publish(int* flag, int tid) {
   if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Diagonal tile g = (block i, tile column c), fused with the tile left of it,
-// L(g, g-1).  One k loop over the k < g-1 shared by both accumulates
-//   acc1 = -(A(g,g) - sum_k L(g,k) L(g,k)^T),  acc2 = -(A(g,g-1) - sum_k L(g,k) L(g-1,k)^T);
-// then L(g,g-1) = -acc2 W(g-1)^T is stored and published, acc1 += L(g,g-1) L(g,g-1)^T,
-// and the diagonal tile is factored and inverted (L and W stored, flag published).
-__device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, Shared& sh, int tid,
-                                         unsigned long long& tr1, unsigned long long* rec) {
+// Diagonal tile g = (block i, tile column c) and the tile left of it, L(g, g-1).
+// One k loop over the k < g-1 shared by both accumulates
+//   acc1 = -(A(g,g) - sum_k L(g,k) L(g,k)^T),  acc2 = -(A(g,g-1) - sum_k L(g,k) L(g-1,k)^T)
+// (a padded diagonal tile gets -1 on the padded diagonal).
+__device__ __forceinline__ void diag_partials(const FactorParams& p, const Task& t, Shared& sh, int tid, Acc& acc1,
+                                              Acc& acc2, unsigned long long* rec) {
   const int T = p.T, b = p.b;
   const int64_t bb = (int64_t)b * b;
   const int rows = ext(b, t.c);
   const double* in = p.D + t.i * bb + (int64_t)t.c * 64 * b + t.c * 64;
-  double* out = p.LD + t.i * bb + (int64_t)t.c * 64 * b + t.c * 64;
 
   // the tile left of the diagonal tile, described by the task that would produce it alone
   const bool has_pre = t.c > 0 || t.i > 0;
   Task pt{T_OFFD, t.i, t.c, t.c - 1};
   const double* pin = nullptr;
-  double* pout = nullptr;
   int prows = 0, pcols = 0;
-  int* pflag = nullptr;
-  const double* Wp = nullptr;
-  const int* fWp = nullptr;
   if (t.c > 0) {
     pin = p.D + t.i * bb + (int64_t)t.c * 64 * b + (t.c - 1) * 64;
-    pout = p.LD + t.i * bb + (int64_t)t.c * 64 * b + (t.c - 1) * 64;
     prows = rows;
     pcols = ext(b, t.c - 1);
-    pflag = p.flags + fl_D(p, t.i, t.c, t.c - 1);
-    Wp = p.Wd + ((int64_t)t.i * T + t.c - 1) * 4096;
-    fWp = p.flags + fl_D(p, t.i, t.c - 1, t.c - 1);
   } else if (t.i > 0) {
     pt = Task{T_SUB, t.i - 1, 0, T - 1};
     pin = p.B + (t.i - 1) * bb + (T - 1) * 64;
-    pout = p.LB + (t.i - 1) * bb + (T - 1) * 64;
     prows = ext(b, 0);
     pcols = ext(b, T - 1);
-    pflag = p.flags + fl_B(p, t.i - 1, 0, T - 1);
-    Wp = p.Wd + ((int64_t)(t.i - 1) * T + T - 1) * 4096;
-    fWp = p.flags + fl_D(p, t.i - 1, T - 1, T - 1);
   }
 
-  // accumulators; a padded diagonal tile gets -1 on the padded diagonal
-  Acc acc1, acc2;
   acc_load(acc1, in, b, rows, rows, -1.0, tid);
   if (rows < 64) {
 #pragma unroll
@@ -405,37 +407,66 @@ __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, S
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (rec && tid == 0) tr1 = __builtin_amdgcn_s_memrealtime();
-  // the rest of this task is the critical path of the factorization: let its
+}
+
+// The rest of diagonal tile g = (i, c) from its partial sums: L(g,g-1) =
+// -acc2 W(g-1)^T is stored and published, acc1 += L(g,g-1) L(g,g-1)^T, and the
+// diagonal tile is factored and inverted (L and W stored, flag published).
+// W(g-1) is loaded once its flag is set, or is already in sh.u.f.Bs (chain).
+// rec (optional): [0] W(g-1) ready, [1] L(g,g-1) published, [2] tile factored.
+__device__ __forceinline__ void diag_finish(const FactorParams& p, int i, int c, Shared& sh, int tid, Acc& acc1,
+                                            Acc& acc2, bool w_in_lds, unsigned long long* rec) {
+  const int T = p.T, b = p.b;
+  const int64_t bb = (int64_t)b * b;
+  const int rows = ext(b, c);
+  double* out = p.LD + i * bb + (int64_t)c * 64 * b + c * 64;
+  const bool has_pre = c > 0 || i > 0;
+  double* pout = nullptr;
+  int prows = 0, pcols = 0;
+  int* pflag = nullptr;
+  const double* Wp = nullptr;
+  const int* fWp = nullptr;
+  if (c > 0) {
+    pout = p.LD + i * bb + (int64_t)c * 64 * b + (c - 1) * 64;
+    prows = rows;
+    pcols = ext(b, c - 1);
+    pflag = p.flags + fl_D(p, i, c, c - 1);
+    Wp = p.Wd + ((int64_t)i * T + c - 1) * 4096;
+    fWp = p.flags + fl_D(p, i, c - 1, c - 1);
+  } else if (i > 0) {
+    pout = p.LB + (i - 1) * bb + (T - 1) * 64;
+    prows = ext(b, 0);
+    pcols = ext(b, T - 1);
+    pflag = p.flags + fl_B(p, i - 1, 0, T - 1);
+    Wp = p.Wd + ((int64_t)(i - 1) * T + T - 1) * 4096;
+    fWp = p.flags + fl_D(p, i - 1, T - 1, T - 1);
+  }
+  // the rest of this tile is the critical path of the factorization: let its
   // waves win the issue arbitration against another workgroup on this CU
   __builtin_amdgcn_s_setprio(3);
 
   if (has_pre) {
-    // L(g,g-1) = -acc2 W(g-1)^T
-    wait_ready(p, fWp, fWp, sh, tid);
-    if (rec && tid == 0) rec[4] = __builtin_amdgcn_s_memrealtime();
-    Stage rw;
-    stage_load_dev(rw, OpTile{Wp, 64, 64, 64, false}, tid);
-    acc_to_lds(acc2, sh.u.f.As, tid);
-    stage_store(rw, sh.u.f.Bs, tid);
+    if (!w_in_lds) {
+      wait_ready(p, fWp, fWp, sh, tid);
+      if (rec && tid == 0) rec[0] = __builtin_amdgcn_s_memrealtime();
+      Stage rw;
+      stage_load_dev(rw, OpTile{Wp, 64, 64, 64, false}, tid);
+      acc_to_lds(acc2, sh.u.f.As, tid);
+      stage_store(rw, sh.u.f.Bs, tid);
+    } else {
+      acc_to_lds(acc2, sh.u.f.As, tid);
+    }
     __syncthreads();
     Acc x;  // -L(g,g-1)
     acc_zero(x);
     mma_tile(x, sh.u.f.As, sh.u.f.Bs, tid);
     acc_store_dev(x, pout, b, prows, pcols, -1.0, tid);
-    if (t.c > 0) {  // exact zeros in the mirrored upper tile of the diagonal block
-      double* up = p.LD + t.i * bb + (int64_t)(t.c - 1) * 64 * b + t.c * 64;
-      for (int e = tid; e < 64 * 64; e += NT) {
-        const int rr = e >> 6, cc = e & 63;
-        if (rr < pcols && cc < prows) up[(int64_t)rr * b + cc] = 0.0;
-      }
-    }
     __syncthreads();
     acc_to_lds(x, sh.u.f.As, tid);
     __syncthreads();
     mma_tile(acc1, sh.u.f.As, sh.u.f.As, tid);  // + L(g,g-1) L(g,g-1)^T = x x^T
     publish(pflag, tid);
-    if (rec && tid == 0) rec[5] = __builtin_amdgcn_s_memrealtime();
+    if (rec && tid == 0) rec[1] = __builtin_amdgcn_s_memrealtime();
   }
 
   // factor and invert A(g,g) - sum over all k < g (acc1 holds its negative)
@@ -447,17 +478,83 @@ __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, S
       for (int j = 0; j < 4; ++j) sh.u.f.As[tile_row(tid, bi, j) * LDS_LD + tile_col(tid, bj)] = -acc1.v[bi][bj][j];
   __syncthreads();
   const int f = uni(chol_inv_tile_mfma<2>(sh.u.f.As, sh.u.f.Bs, sh.rinv, sh.pan, &sh.fail, tid));
-  if (rec && tid == 0) rec[6] = __builtin_amdgcn_s_memrealtime();
+  if (rec && tid == 0) rec[2] = __builtin_amdgcn_s_memrealtime();
   if (f != 0 && f <= rows && tid == 0) {
-    const long long row0 = (long long)t.i * b + (long long)t.c * 64;
+    const long long row0 = (long long)i * b + (long long)c * 64;
     atomicMin((unsigned long long*)p.info, (unsigned long long)(row0 + f));
   }
-  double* Wout = p.Wd + ((int64_t)t.i * T + t.c) * 4096;
+  double* Wout = p.Wd + ((int64_t)i * T + c) * 4096;
   tile_store_dev(sh.u.f.Bs, Wout, 64, 64, 64, tid);
   tile_store_dev(sh.u.f.As, out, b, rows, rows, tid);
-  (void)aborted;
-  publish(p.flags + fl_D(p, t.i, t.c, t.c), tid);
+  publish(p.flags + fl_D(p, i, c, c), tid);
   __builtin_amdgcn_s_setprio(0);
+  // exact zeros in the mirrored upper tile of the diagonal block (no task reads them)
+  if (c > 0) {
+    double* up = p.LD + i * bb + (int64_t)(c - 1) * 64 * b + c * 64;
+    for (int e = tid; e < 64 * 64; e += NT) {
+      const int rr = e >> 6, cc = e & 63;
+      if (rr < pcols && cc < prows) up[(int64_t)rr * b + cc] = 0.0;
+    }
+  }
+}
+
+__device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, Shared& sh, int tid,
+                                         unsigned long long& tr1, unsigned long long* rec) {
+  Acc acc1, acc2;
+  diag_partials(p, t, sh, tid, acc1, acc2, rec);
+  if (rec && tid == 0) tr1 = __builtin_amdgcn_s_memrealtime();
+  diag_finish(p, t.i, t.c, sh, tid, acc1, acc2, false, rec ? rec + 4 : nullptr);
+}
+
+// Partial sums of a diagonal tile for the chain: element e of thread tid of
+// acc1 (acc2) at Pacc[g][e * 256 + tid] (+ 4096), so that every store and load
+// instruction covers 2 KB of consecutive addresses.
+__device__ __forceinline__ void part_store(const Acc& c, double* P, int tid) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) st_dev(P + ((bi * 2 + bj) * 4 + j) * NT + tid, c.v[bi][bj][j]);
+}
+__device__ __forceinline__ void part_load(Acc& c, const double* P, int tid) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c.v[bi][bj][j] = ld_dev(P + ((bi * 2 + bj) * 4 + j) * NT + tid);
+}
+
+__device__ __forceinline__ void run_part(const FactorParams& p, const Task& t, Shared& sh, int tid,
+                                         unsigned long long& tr1, unsigned long long* rec) {
+  Acc acc1, acc2;
+  diag_partials(p, t, sh, tid, acc1, acc2, rec);
+  if (rec && tid == 0) tr1 = __builtin_amdgcn_s_memrealtime();
+  double* P = p.Pacc + ((int64_t)t.i * p.T + t.c) * 8192;
+  part_store(acc1, P, tid);
+  part_store(acc2, P + 4096, tid);
+  publish(p.flags + fl_part(p, t.i, t.c), tid);
+}
+
+// The chain workgroup: diagonal tiles in band order.  Returns false on abort.
+__device__ __forceinline__ bool chain_run(const FactorParams& p, Shared& sh, int tid) {
+  for (int i = 0; i < p.n; ++i) {
+    for (int c = 0; c < p.T; ++c) {
+      unsigned long long* rec = p.trace ? p.trace + 8 * (p.ntasks + (long long)i * p.T + c) : nullptr;
+      if (rec && tid == 0) rec[0] = __builtin_amdgcn_s_memrealtime();
+      const int* fp = p.flags + fl_part(p, i, c);
+      if (!wait_ready(p, fp, fp, sh, tid)) return false;
+      Acc acc1, acc2;
+      const double* P = p.Pacc + ((int64_t)i * p.T + c) * 8192;
+      part_load(acc1, P, tid);
+      part_load(acc2, P + 4096, tid);
+      if (rec && tid == 0) rec[1] = __builtin_amdgcn_s_memrealtime();
+      diag_finish(p, i, c, sh, tid, acc1, acc2, true, rec ? rec + 2 : nullptr);
+      if (rec && tid == 0) rec[5] = __builtin_amdgcn_s_memrealtime();
+    }
+  }
+  return true;
 }
 
 // One task of one matrix: accumulate, finish, publish.
@@ -469,7 +566,8 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
     if (p.trace && tid == 0) tr0 = __builtin_amdgcn_s_memrealtime();
     if (t.type == T_DIAG) {
       unsigned long long* rec = p.trace ? p.trace + 8 * tk : nullptr;
-      run_diag(p, t, sh, tid, tr1, rec);
+      if (p.chain) run_part(p, t, sh, tid, tr1, rec);
+      else run_diag(p, t, sh, tid, tr1, rec);
       if (rec && tid == 0) {
         rec[0] = tr0;
         rec[1] = tr1;
@@ -660,6 +758,10 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
 // Persistent workers: take tickets until the task list is exhausted.
 __device__ __forceinline__ void factor_worker(const FactorParams& p, Shared& sh) {
   const int tid = threadIdx.x;
+  if (p.chain && blockIdx.x == 0) {
+    chain_run(p, sh, tid);
+    return;
+  }
   for (;;) {
     if (tid == 0) sh.ticket = (long long)atomicAdd((unsigned long long*)p.ctl, 1ULL);
     __syncthreads();
@@ -759,7 +861,7 @@ FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   const int64_t T = (b + 63) / 64, TA = (a + 63) / 64;
   fp.T = (int)T;
   fp.TA = (int)TA;
-  fp.nflags = n * (2 * T * T + TA * T + TA * TA) + TA * TA;
+  fp.nflags = n * (2 * T * T + TA * T + TA * TA) + TA * TA + n * T;  // ..., tip tiles, PART tasks
   // per step: DIAG + OFFD tasks T(T-1)/2 + 1 (the T-1 tiles L_ii(c+1,c) are
   // computed by DIAG tasks), SUB T*T - 1 (L_{i+1,i}(0,T-1) likewise), ARW, TUPD
   fp.step_full = T * (T - 1) / 2 + 1 + T * T - 1 + T * TA + TA * (TA + 1) / 2;
@@ -773,6 +875,7 @@ FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   fp.off_Wd = take(sizeof(double) * 4096 * (size_t)(n * T));
   fp.off_Wt = take(sizeof(double) * 4096 * (size_t)(TA > 0 ? TA : 1));
   fp.off_P = take(sizeof(double) * 4096 * (size_t)(n * TA * TA > 0 ? n * TA * TA : 1));
+  fp.off_Pacc = take(sizeof(double) * 8192 * (size_t)(n * T));  // single-matrix kernel only
   fp.bytes = off;
   return fp;
 }
@@ -798,12 +901,15 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
   p.look = fp.look;
   p.trace = trace;
   p.spin_limit = 1LL << 22;  // a few seconds of polling without progress before the watchdog fires
+  // chain workgroup when, besides it, more workgroups than the lookahead bound are resident
+  p.chain = (kFactorChain && num_cus >= fp.look + 3) ? 1 : 0;
+  p.Pacc = reinterpret_cast<double*>(w + fp.off_Pacc);
   const int rgrid = (int)std::min<long long>(1024, (fp.nflags + 255) / 256 + 1);
   hipLaunchKernelGGL(factor_reset_kernel, dim3(rgrid), dim3(256), 0, stream, p.flags, fp.nflags, p.ctl, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const long long grid = std::min<long long>(fp.ntasks, (long long)num_cus);
-  if (grid < fp.ntasks && grid <= fp.look + 1) return hipErrorInvalidConfiguration;  // lookahead needs more workers
+  const long long grid = std::min<long long>(fp.ntasks + p.chain, (long long)num_cus);
+  if (grid - p.chain < fp.ntasks && grid - p.chain <= fp.look + 1) return hipErrorInvalidConfiguration;  // lookahead needs more workers
   timing_mark(KT_FACTOR, true, stream);
   hipLaunchKernelGGL(factor_kernel, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, p);
   timing_mark(KT_FACTOR, false, stream);
@@ -864,7 +970,7 @@ FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b,
   for (int m = 0; m < count; ++m) {
     const FactorPlan& fp = bp.plans[m];
     bp.ws_off[m][0] = take(fp.off_P - fp.off_Wd);          // Wd + Wt
-    bp.ws_off[m][1] = take(fp.bytes - fp.off_P);           // P
+    bp.ws_off[m][1] = take(fp.off_Pacc - fp.off_P);        // P
   }
   bp.bytes = off;
   long long t = 0;
@@ -899,6 +1005,8 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
     p.look = fp.look;
     p.spin_limit = 1LL << 22;
     p.trace = nullptr;
+    p.chain = 0;
+    p.Pacc = nullptr;
   }
   std::vector<int64_t> ns(bp.count);
   for (int m = 0; m < bp.count; ++m) ns[m] = mats[m].n;
@@ -991,10 +1099,19 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
       owner[(size_t)pf] = tk;
       cnt[t.c > 0 ? T_OFFD : T_SUB]++;
     }
+    if (t.type == T_DIAG) {  // single-matrix kernel: the PART task's hand-off flag
+      const int64_t qf = fl_part(p, t.i, t.c);
+      if (qf < 0 || qf >= fp.nflags || owner[(size_t)qf] != -1) return 3;
+      owner[(size_t)qf] = tk;
+    }
   }
   // pass 2: dependencies.  A task other than DIAG waits only on tasks with
   // smaller tickets; a DIAG task (dispatched up to `look` columns early) waits
-  // only on tasks of smaller rank.  Together with the bound on the number of
+  // only on tasks of smaller rank.  With the chain workgroup the outputs of a
+  // diagonal tile come from the chain once the PART task in its DIAG slot is
+  // done, and the chain needs nothing else but the previous link: ownership by
+  // that ticket is the same relation, so the same checks cover both kernels
+  // (the chain is one extra resident workgroup).  Together with the bound on the number of
   // DIAG tasks ahead of the in-order frontier (checked below) this keeps the
   // schedule deadlock free whenever more workgroups than that bound are resident.
   std::vector<long long> maxdep((size_t)fp.ntasks, -1);  // largest ticket a task waits on
@@ -1068,14 +1185,15 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
 
 }  // namespace bta
 
-// bta_factor with a per-task trace buffer of 8 * ntasks words (device memory);
-// the number of tasks is returned through *ntasks when the pointer is set.
+// bta_factor with a trace buffer of 8 words per record (device memory): one
+// record per ticket, then one per chain link (n * ceil(b/64)); the number of
+// records is returned through *ntasks when the pointer is set.
 extern "C" __attribute__((visibility("default"))) int bta_internal_factor_traced(
     int64_t n, int64_t b, int64_t a, const double* D, const double* B, const double* R, const double* T, double* LD,
     double* LB, double* LR, double* LT, void* work, int64_t* info, unsigned long long* trace, long long* ntasks,
     hipStream_t stream) {
   const bta::FactorPlan fp = bta::factor_plan(n, b, a);
-  if (ntasks) *ntasks = fp.ntasks;
+  if (ntasks) *ntasks = fp.ntasks + n * fp.T;
   if (!trace) return 0;
   return bta::factor_launch(fp, n, b, a, D, B, R, T, LD, LB, LR, LT, work, info, stream, bta::device_cu_count(), trace) ==
                  hipSuccess
