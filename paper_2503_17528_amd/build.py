@@ -1,11 +1,15 @@
 """Build the HIP shared library ``libbta.so`` for gfx950 with hipcc.
 
 Every call compiles from source (a few tens of seconds); ``python -m
-paper_2503_17528_amd.build`` does the same from the command line.
+paper_2503_17528_amd.build`` does the same from the command line.  The build
+fails if any kernel needs scratch memory (register spills or private arrays):
+the kernels are written to run from registers and LDS alone, and spilling
+builds of them have produced wrong results.
 """
 from __future__ import annotations
 
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -25,6 +29,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fvisibility=hidden",
     "-Wno-unused-result",
+    # per-kernel resource report (parsed below for scratch use)
+    "-Rpass-analysis=kernel-resource-usage",
 ]
 
 
@@ -44,15 +50,34 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
-    out = "\n".join(l for l in res.stdout.splitlines()
-                    if "packed-fp32-ops" not in l and "is not a recognized feature" not in l)
+    lines = res.stdout.splitlines()
+    out = "\n".join(l for l in lines if "packed-fp32-ops" not in l and "is not a recognized feature" not in l
+                    and "kernel-resource-usage" not in l)
     if res.returncode != 0:
         os.unlink(tmp)
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{out}")
+    spills = scratch_kernels(lines)
+    if spills:
+        os.unlink(tmp)
+        raise RuntimeError("kernels using scratch memory: " + ", ".join(f"{k} ({v} B/lane)" for k, v in spills))
     if verbose and out.strip():
         print(out)
     os.replace(tmp, LIB)
     return LIB
+
+
+def scratch_kernels(lines):
+    """(kernel, bytes per lane) for every kernel of the resource report with scratch."""
+    found, name = [], None
+    for l in lines:
+        m = re.search(r"remark: Function Name: (\S+)", l)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"remark:\s+ScratchSize \[bytes/lane\]: (\d+)", l)
+        if m and name is not None and int(m.group(1)) > 0:
+            found.append((name, int(m.group(1))))
+    return found
 
 
 if __name__ == "__main__":

@@ -719,7 +719,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_list_kernel(const GProb* probs, co
   __shared__ double As[64 * 66];
   __shared__ double Bs[64 * 66];
   const int j = find_prob_list(tile_begin, nprob, blockIdx.x);
-  const GProb P = probs[j];
+  const GProb& P = probs[j];  // read in place: a private copy would live in scratch
   gemm_tile_body<2, 2, 64>(P, blockIdx.x - tile_begin[j], threadIdx.x, As, Bs);
 }
 
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(NT, 1) void gemm128_list_kernel(const GProb* probs,
   __shared__ double As[128 * 34];
   __shared__ double Bs[128 * 34];
   const int j = find_prob_list(tile_begin, nprob, blockIdx.x);
-  const GProb P = probs[j];
+  const GProb& P = probs[j];  // read in place: a private copy would live in scratch
   gemm_tile_body<4, 4, 32>(P, blockIdx.x - tile_begin[j], threadIdx.x, As, Bs);
 }
 

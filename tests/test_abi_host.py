@@ -130,3 +130,19 @@ def test_selinv_solve_logdet_validate(bta):
     assert bta.bta_solve(2, 8, 2, *p[:4], p[0], 1, FAKE, 1 << 30, None) == bta.BTA_EINVAL  # rhs overlaps LD
     assert bta.bta_logdet(2, 8, 2, p[0], p[3], None, FAKE, 1 << 30, None) == bta.BTA_EINVAL
     assert bta.bta_logdet(2, 8, 2, p[0], p[3], p[1], FAKE, 1, None) == bta.BTA_EINVAL
+
+
+def test_build_rejects_scratch_kernels():
+    """The build's parser of the compiler's per-kernel resource report flags
+    every kernel with scratch and only those."""
+    from paper_2503_17528_amd import build
+
+    lines = [
+        "gemm.hip:1:1: remark: Function Name: _Zk1 [-Rpass-analysis=kernel-resource-usage]",
+        "gemm.hip:1:1: remark:     VGPRs: 104 [-Rpass-analysis=kernel-resource-usage]",
+        "gemm.hip:1:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "gemm.hip:9:1: remark: Function Name: _Zk2 [-Rpass-analysis=kernel-resource-usage]",
+        "gemm.hip:9:1: remark:     ScratchSize [bytes/lane]: 352 [-Rpass-analysis=kernel-resource-usage]",
+    ]
+    assert build.scratch_kernels(lines) == [("_Zk2", 352)]
+    assert build.scratch_kernels(lines[:3]) == []
