@@ -483,10 +483,12 @@ __device__ __forceinline__ void diag_finish(const FactorParams& p, int i, int c,
     const long long row0 = (long long)i * b + (long long)c * 64;
     atomicMin((unsigned long long*)p.info, (unsigned long long)(row0 + f));
   }
+  // the flag covers W only: no task reads a diagonal tile of L (every solve
+  // uses W), so L(g,g) is stored after the publication, off the chain
   double* Wout = p.Wd + ((int64_t)i * T + c) * 4096;
   tile_store_dev(sh.u.f.Bs, Wout, 64, 64, 64, tid);
-  tile_store_dev(sh.u.f.As, out, b, rows, rows, tid);
   publish(p.flags + fl_D(p, i, c, c), tid);
+  tile_store_dev(sh.u.f.As, out, b, rows, rows, tid);
   __builtin_amdgcn_s_setprio(0);
   // exact zeros in the mirrored upper tile of the diagonal block (no task reads them)
   if (c > 0) {
@@ -856,6 +858,9 @@ __global__ void factor_finish_kernel(const int* ctl, int64_t* info) {
 }
 
 // ---------------------------------------------------------------------------
+// DIAG lookahead in columns (internal override for measurements).
+static int g_factor_look = FACTOR_LOOKAHEAD;
+
 FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   FactorPlan fp{};
   const int64_t T = (b + 63) / 64, TA = (a + 63) / 64;
@@ -867,7 +872,7 @@ FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   fp.step_full = T * (T - 1) / 2 + 1 + T * T - 1 + T * TA + TA * (TA + 1) / 2;
   fp.step_last = T * (T - 1) / 2 + 1 + T * TA + TA * (TA + 1) / 2;
   fp.ntasks = (n - 1) * fp.step_full + fp.step_last + TA * (TA + 1) / 2;
-  fp.look = (int)std::min<int64_t>(FACTOR_LOOKAHEAD, T - 1);
+  fp.look = (int)std::min<int64_t>(g_factor_look, T - 1);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
   fp.off_ctl = take(64);
@@ -1028,7 +1033,9 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
   args.ntasks = t;
   args.ctl = ctl;
   const long long grid = std::min<long long>(t, (long long)num_cus);
-  if (grid < t && grid <= FACTOR_LOOKAHEAD + 1) return hipErrorInvalidConfiguration;  // lookahead needs more workers
+  int look = 0;
+  for (int m = 0; m < bp.count; ++m) look = std::max(look, bp.plans[m].look);
+  if (grid < t && grid <= look + 1) return hipErrorInvalidConfiguration;  // lookahead needs more workers
   timing_mark(KT_FACTOR, true, stream);
   hipLaunchKernelGGL(factor_batched_kernel, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, args);
   timing_mark(KT_FACTOR, false, stream);
@@ -1184,6 +1191,14 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
 }
 
 }  // namespace bta
+
+// Internal: DIAG lookahead in columns for later factorizations (1..64);
+// returns the previous value (any other argument only queries).
+extern "C" __attribute__((visibility("default"))) int bta_internal_factor_lookahead(int look) {
+  const int prev = bta::g_factor_look;
+  if (look >= 1 && look <= 64) bta::g_factor_look = look;
+  return prev;
+}
 
 // bta_factor with a trace buffer of 8 words per record (device memory): one
 // record per ticket, then one per chain link (n * ceil(b/64)); the number of

@@ -71,3 +71,17 @@ def test_batched_selinv_merge_is_independent(L):
                                                                              (5, 40, 1), (4, 200, 0)]]):
         n, b, a = arr([w.n for w in wls]), arr([w.b for w in wls]), arr([w.a for w in wls])
         assert L.bta_internal_selinv_batch_check(len(wls), n, b, a) == 0
+
+
+@pytest.mark.parametrize("look", [1, 4, 12, 16, 32])
+def test_factor_schedule_other_lookaheads(L, look):
+    """The schedule invariants hold for every DIAG lookahead the internal
+    override can set (the ahead bound scales with it)."""
+    L.bta_internal_factor_lookahead.argtypes = [ctypes.c_int]
+    L.bta_internal_factor_lookahead.restype = ctypes.c_int
+    prev = L.bta_internal_factor_lookahead(look)
+    try:
+        for n, b, a in [(3, 64 * 20 + 5, 3), (2, 64 * 40, 70), (4, 200, 0), (1, 64 * 33, 8)]:
+            assert L.bta_internal_factor_schedule_check(n, b, a, None) == 0, (look, n, b, a)
+    finally:
+        L.bta_internal_factor_lookahead(prev)
