@@ -35,6 +35,9 @@ def parse():
     ap.add_argument("--b", type=int, default=2048)
     ap.add_argument("--a", type=int, default=8)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workload", choices=["custom", "large"], default="custom",
+                    help="large: the n=256, b=4096, a=16 workload (diagonal of L_ii in [1,3]); "
+                         "custom: --n/--b/--a with the default generator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-target-s", type=float, default=15.0, help="CPU oracle sample budget (seconds)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -123,9 +126,13 @@ def main():
     L.bta_internal_timing.argtypes = [ctypes.c_int, ctypes.c_int]
     L.bta_internal_timing_read.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
 
-    n, b, a = args.n, args.b, args.a
-    reading = "scaled" if b >= 2048 else "literal"
-    wl = synth.workload(n, b, a, reading, name=f"bta_n{n}_b{b}_a{a}")
+    if args.workload == "large":
+        wl = synth.LARGE
+        n, b, a, reading = wl.n, wl.b, wl.a, wl.reading
+    else:
+        n, b, a = args.n, args.b, args.a
+        reading = "scaled" if b >= 2048 else "literal"
+        wl = synth.workload(n, b, a, reading, name=f"bta_n{n}_b{b}_a{a}")
     print(f"[bench] drawing {wl.name} ({wl.block_bytes() / 1e9:.2f} GB of blocks) on {dev}", file=sys.stderr, flush=True)
     Q = synth.make_torch(wl, args.seed, dev)
     D, B, R, T = Q["D"], Q["B"], Q["R"], Q["T"]
