@@ -136,6 +136,7 @@ hipError_t copy2d_launch(const double* src, int64_t lds, int64_t ss, double* dst
 int device_cu_count();
 // Library-owned side stream and reusable events of the current device.
 hipStream_t side_stream();
+hipStream_t copy_stream();
 hipStream_t capture_stream();
 hipEvent_t event_at(int k);
 

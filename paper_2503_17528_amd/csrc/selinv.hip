@@ -126,6 +126,7 @@ static hipError_t trtri_batched(const double* L, int64_t ldL, int64_t sL, double
 namespace {
 struct DevSync {
   hipStream_t side = nullptr;
+  hipStream_t copy = nullptr;
   hipStream_t capture = nullptr;
   std::vector<hipEvent_t> ev;
 };
@@ -142,6 +143,14 @@ hipStream_t side_stream() {
   return d.side;
 }
 
+hipStream_t copy_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_sync_mu);
+  DevSync& d = g_sync[dev];
+  if (!d.copy && hipStreamCreateWithFlags(&d.copy, hipStreamNonBlocking) != hipSuccess) d.copy = nullptr;
+  return d.copy;
+}
 hipStream_t capture_stream() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
@@ -181,7 +190,7 @@ SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a) {
   sp.off_W = take(8 * bb * chunk);
   sp.off_T1 = take(8 * bb * chunk);
   sp.off_PR = take(8 * (size_t)std::max<int64_t>(1, a * b * n));
-  sp.off_Xp = take(8 * bb);
+  sp.off_Xp = take(8 * 2 * bb);  // X_{i+1,i} of two consecutive steps
   sp.off_WT = take(8 * (size_t)std::max<int64_t>(1, 2 * a * a));
   sp.bytes = off;
   return sp;
@@ -307,7 +316,13 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
     if (!dry) BTA_TRY(hipEventRecord(event_at(1 + (int)k), sa));
   }
 
-  // ---- backward sweep
+  // ---- backward sweep.  X_{i+1,i} goes to one of two buffers; its copy over
+  // P_B (the X_{i+1,i} slot) runs on a copy stream after the step's second
+  // product, off the sweep's critical path, and the buffer is reused two steps
+  // later.
+  hipStream_t sc = dry ? s : copy_stream();
+  if (!dry && !sc) return hipErrorInvalidResourceHandle;
+  const int E0 = 1 + (int)chunks.size();
   size_t next_chunk = 0;
   for (int64_t i = n - 1; i >= 0; --i) {
     // first step of a preprocessing chunk: wait for that chunk
@@ -320,12 +335,14 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
     set_stage(2, step, 0);
     const double* PB = XB + i * bb;
     const double* PRi = PR + i * ab;
+    double* Xb = Xp + (step & 1) * bb;
     if (has_sub) {  // X_{i+1,i} = -(X_{i+1,i+1} P_B + X_{n,i+1}^T P_R)
+      if (!dry && step >= 2) BTA_TRY(hipStreamWaitEvent(s, event_at(E0 + 2 * (step - 2) + 1), 0));  // buffer copied out
       GProb p = prob_init();
       p.seg[0] = seg(XD + (i + 1) * bb, b, 0, PB, b, 1, ib, TRI_NONE);
       p.nseg = 1;
       if (a > 0) { p.seg[1] = seg(XR + (i + 1) * ab, b, 1, PRi, b, 1, ia, TRI_NONE); p.nseg = 2; }
-      p.Cout = Xp; p.ldc = b;
+      p.Cout = Xb; p.ldc = b;
       p.M = ib; p.N = ib;
       p.alpha = -1.0;
       BTA_TRY(gemm_launch(&p, 1, s));
@@ -335,7 +352,7 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
        // segments when n == 1 and a == 0: the mirror of V_0)
       GProb p = prob_init();
       p.nseg = 0;
-      if (has_sub) p.seg[p.nseg++] = seg(Xp, b, 1, PB, b, 1, ib, TRI_NONE);
+      if (has_sub) p.seg[p.nseg++] = seg(Xb, b, 1, PB, b, 1, ib, TRI_NONE);
       if (a > 0) p.seg[p.nseg++] = seg(XR + i * ab, b, 1, PRi, b, 1, ia, TRI_NONE);
       p.Cin = XD + i * bb; p.Cout = XD + i * bb; p.ldc = b;
       p.M = ib; p.N = ib;
@@ -345,8 +362,17 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       BTA_TRY(gemm_launch(&p, 1, s));
     }
     set_stage(2, step, 3);
-    if (has_sub) BTA_TRY(copy2d_launch(Xp, b, 0, XB + i * bb, b, 0, ib, ib, 1, s));
+    if (has_sub) {
+      if (!dry) {
+        BTA_TRY(hipEventRecord(event_at(E0 + 2 * step), s));
+        BTA_TRY(hipStreamWaitEvent(sc, event_at(E0 + 2 * step), 0));
+      }
+      BTA_TRY(copy2d_launch(Xb, b, 0, XB + i * bb, b, 0, ib, ib, 1, sc));
+      if (!dry) BTA_TRY(hipEventRecord(event_at(E0 + 2 * step + 1), sc));
+    }
   }
+  // the last copy (step n-1) before the call's work on `s` is complete
+  if (!dry && n > 1) BTA_TRY(hipStreamWaitEvent(s, event_at(E0 + 2 * (int)(n - 1) + 1), 0));
   return hipSuccess;
 }
 
