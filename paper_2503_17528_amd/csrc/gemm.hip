@@ -380,16 +380,20 @@ __device__ __forceinline__ void gemm_tile_dl(const GProb& P, long long local, in
   const double* B0 = P.seg[0].B + b0 * P.seg[0].sB0 + b1 * P.seg[0].sB1;
   const double* A1 = P.seg[1].A + b0 * P.seg[1].sA0 + b1 * P.seg[1].sA1;
   const double* B1 = P.seg[1].B + b0 * P.seg[1].sB0 + b1 * P.seg[1].sB1;
+  // the segments' layouts and strides, read once into scalar registers (a
+  // reload inside the k loop costs a scalar load and a full wait per stage)
+  const int at0 = __builtin_amdgcn_readfirstlane(P.seg[0].at), bt0 = __builtin_amdgcn_readfirstlane(P.seg[0].bt);
+  const int at1 = __builtin_amdgcn_readfirstlane(P.seg[1].at), bt1 = __builtin_amdgcn_readfirstlane(P.seg[1].bt);
+  const int64_t lda0 = P.seg[0].lda, lda1 = P.seg[1].lda, ldb0 = P.seg[0].ldb, ldb1 = P.seg[1].ldb;
 
   auto issue = [&](int kk) {
     const bool first = kk < nk0;
     const int k = first ? kb0 + kk * BK : kb1 + (kk - nk0) * BK;
     const int kext = min(BK, (first ? ke0 : ke1) - k);
     double* st = lds + (kk & 1) * C::STAGE;
-    stage_operand<TM, C::IA>(first ? A0 : A1, first ? P.seg[0].lda : P.seg[1].lda, first ? P.seg[0].at : P.seg[1].at,
-                             m0, mext, k, kext, st, wave, lane);
-    stage_operand<TN, C::IB>(first ? B0 : B1, first ? P.seg[0].ldb : P.seg[1].ldb, first ? P.seg[0].bt : P.seg[1].bt,
-                             n0, next, k, kext, st + C::SA, wave, lane);
+    stage_operand<TM, C::IA>(first ? A0 : A1, first ? lda0 : lda1, first ? at0 : at1, m0, mext, k, kext, st, wave, lane);
+    stage_operand<TN, C::IB>(first ? B0 : B1, first ? ldb0 : ldb1, first ? bt0 : bt1, n0, next, k, kext, st + C::SA,
+                             wave, lane);
   };
 
   AccT<WM, WN> acc;
@@ -421,8 +425,8 @@ __device__ __forceinline__ void gemm_tile_dl(const GProb& P, long long local, in
       const bool first = kk < nk0;
       const double* st = lds + (kk & 1) * C::STAGE;
       double a[WM][4], b[WN][4];
-      stage_read<TM, WM>(a, st, first ? P.seg[0].at : P.seg[1].at, rw, lane);
-      stage_read<TN, WN>(b, st + C::SA, first ? P.seg[0].bt : P.seg[1].bt, cw, lane);
+      stage_read<TM, WM>(a, st, first ? at0 : at1, rw, lane);
+      stage_read<TN, WN>(b, st + C::SA, first ? bt0 : bt1, cw, lane);
       if (kk + 1 < total) issue(kk + 1);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -586,6 +590,10 @@ __device__ __forceinline__ void gemm_tile_dl2(const GProb& P, long long local, i
 #pragma unroll
     for (int jj = 0; jj < BJ; ++jj) all_live = all_live && live[i][jj];
   if (total > 0) issue(0);
+  // the segments' layouts, read once into scalar registers (a reload inside
+  // the k loop costs a scalar load and a full wait per stage)
+  const int at0 = __builtin_amdgcn_readfirstlane(P.seg[0].at), bt0 = __builtin_amdgcn_readfirstlane(P.seg[0].bt);
+  const int at1 = __builtin_amdgcn_readfirstlane(P.seg[1].at), bt1 = __builtin_amdgcn_readfirstlane(P.seg[1].bt);
   // the k loop, with the per-block checks only where a block can be dead
   auto kloop = [&](auto checked) {
     constexpr bool CK = decltype(checked)::value;
@@ -594,8 +602,8 @@ __device__ __forceinline__ void gemm_tile_dl2(const GProb& P, long long local, i
       const bool first = kk < nk0;
       const double* st = lds + (kk & 1) * C::STAGE;
       double a[BI][4], b[BJ][4];
-      stage_read<TM, BI>(a, st, first ? P.seg[0].at : P.seg[1].at, rw, lane);
-      stage_read<TN, BJ>(b, st + C::SA, first ? P.seg[0].bt : P.seg[1].bt, cw, lane);
+      stage_read<TM, BI>(a, st, first ? at0 : at1, rw, lane);
+      stage_read<TN, BJ>(b, st + C::SA, first ? bt0 : bt1, cw, lane);
       if (kk + 1 < total) issue(kk + 1);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
