@@ -343,7 +343,9 @@ __device__ __forceinline__ void tile_coords(const GProb& P, int tile, int& tm, i
   }
 }
 
-template <int WM, int WN>
+// L0: layout of every problem's first segment as at * 2 + bt when the launch
+// shares one (its k loop then has no layout branch), 4 when it does not.
+template <int WM, int WN, int L0>
 __device__ __forceinline__ void gemm_tile_dl(const GProb& P, long long local, int tid, double* lds) {
   using C = DLCfg<WM, WN>;
   constexpr int TM = C::TM, TN = C::TN, BK = C::BK;
@@ -417,16 +419,18 @@ __device__ __forceinline__ void gemm_tile_dl(const GProb& P, long long local, in
 #pragma unroll
     for (int jj = 0; jj < WN; ++jj) all_live = all_live && live[i][jj];
   if (total > 0) issue(0);
-  auto kloop = [&](auto checked) {
+  // stages [k0, k1); layout code LC < 4 fixes both operand layouts at compile time
+  auto kloop = [&](auto checked, auto lc, int k0, int k1) {
     constexpr bool CK = decltype(checked)::value;
-    for (int kk = 0; kk < total; ++kk) {
+    constexpr int LC = decltype(lc)::value;
+    for (int kk = k0; kk < k1; ++kk) {
       // stage kk has landed for every wave, and every wave is done with stage kk-1
       __syncthreads();
       const bool first = kk < nk0;
       const double* st = lds + (kk & 1) * C::STAGE;
       double a[WM][4], b[WN][4];
-      stage_read<TM, WM>(a, st, first ? at0 : at1, rw, lane);
-      stage_read<TN, WN>(b, st + C::SA, first ? bt0 : bt1, cw, lane);
+      stage_read<TM, WM>(a, st, LC < 4 ? (LC >> 1) : (first ? at0 : at1), rw, lane);
+      stage_read<TN, WN>(b, st + C::SA, LC < 4 ? (LC & 1) : (first ? bt0 : bt1), cw, lane);
       if (kk + 1 < total) issue(kk + 1);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -437,8 +441,15 @@ __device__ __forceinline__ void gemm_tile_dl(const GProb& P, long long local, in
             if (!CK || live[i][jj]) acc.v[i][jj] = mfma16(a[i][q], b[jj][q], acc.v[i][jj]);
     }
   };
-  if (__builtin_amdgcn_readfirstlane((int)all_live)) kloop(std::false_type{});
-  else kloop(std::true_type{});
+  using LFix = std::integral_constant<int, L0>;
+  using LRun = std::integral_constant<int, 4>;
+  if (__builtin_amdgcn_readfirstlane((int)all_live)) {
+    kloop(std::false_type{}, LFix{}, 0, L0 < 4 ? nk0 : total);
+    if (L0 < 4) kloop(std::false_type{}, LRun{}, nk0, total);
+  } else {
+    kloop(std::true_type{}, LFix{}, 0, L0 < 4 ? nk0 : total);
+    if (L0 < 4) kloop(std::true_type{}, LRun{}, nk0, total);
+  }
 
   const int64_t coff = b0 * P.sC0 + b1 * P.sC1;
   double* Cb = P.Cout + coff;
@@ -484,7 +495,7 @@ struct DL2 {
   static_assert((PA + PB) % NTH == 0 && PA % 64 == 0, "stage pieces per thread");
 };
 
-template <int WR, int WC, int BI, int BJ>
+template <int WR, int WC, int BI, int BJ, int L0>
 __device__ __forceinline__ void gemm_tile_dl2(const GProb& P, long long local, int tid, double* lds) {
   using C = DL2<WR, WC, BI, BJ>;
   constexpr int TM = C::TM, TN = C::TN, BK = C::BK, PER = C::PER_T;
@@ -595,15 +606,17 @@ __device__ __forceinline__ void gemm_tile_dl2(const GProb& P, long long local, i
   const int at0 = __builtin_amdgcn_readfirstlane(P.seg[0].at), bt0 = __builtin_amdgcn_readfirstlane(P.seg[0].bt);
   const int at1 = __builtin_amdgcn_readfirstlane(P.seg[1].at), bt1 = __builtin_amdgcn_readfirstlane(P.seg[1].bt);
   // the k loop, with the per-block checks only where a block can be dead
-  auto kloop = [&](auto checked) {
+  // stages [k0, k1); layout code LC < 4 fixes both operand layouts at compile time
+  auto kloop = [&](auto checked, auto lc, int k0, int k1) {
     constexpr bool CK = decltype(checked)::value;
-    for (int kk = 0; kk < total; ++kk) {
+    constexpr int LC = decltype(lc)::value;
+    for (int kk = k0; kk < k1; ++kk) {
       __syncthreads();
       const bool first = kk < nk0;
       const double* st = lds + (kk & 1) * C::STAGE;
       double a[BI][4], b[BJ][4];
-      stage_read<TM, BI>(a, st, first ? at0 : at1, rw, lane);
-      stage_read<TN, BJ>(b, st + C::SA, first ? bt0 : bt1, cw, lane);
+      stage_read<TM, BI>(a, st, LC < 4 ? (LC >> 1) : (first ? at0 : at1), rw, lane);
+      stage_read<TN, BJ>(b, st + C::SA, LC < 4 ? (LC & 1) : (first ? bt0 : bt1), cw, lane);
       if (kk + 1 < total) issue(kk + 1);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -614,8 +627,15 @@ __device__ __forceinline__ void gemm_tile_dl2(const GProb& P, long long local, i
             if (!CK || live[i][jj]) acc.v[i][jj] = mfma16(a[i][q], b[jj][q], acc.v[i][jj]);
     }
   };
-  if (__builtin_amdgcn_readfirstlane((int)all_live)) kloop(std::false_type{});
-  else kloop(std::true_type{});
+  using LFix = std::integral_constant<int, L0>;
+  using LRun = std::integral_constant<int, 4>;
+  if (__builtin_amdgcn_readfirstlane((int)all_live)) {
+    kloop(std::false_type{}, LFix{}, 0, L0 < 4 ? nk0 : total);
+    if (L0 < 4) kloop(std::false_type{}, LRun{}, nk0, total);
+  } else {
+    kloop(std::true_type{}, LFix{}, 0, L0 < 4 ? nk0 : total);
+    if (L0 < 4) kloop(std::true_type{}, LRun{}, nk0, total);
+  }
 
   const int64_t coff = b0 * P.sC0 + b1 * P.sC1;
   double* Cb = P.Cout + coff;
@@ -677,39 +697,44 @@ __global__ __launch_bounds__(NT, 1) void gemm128_kernel(GemmArgs args) {
   gemm_tile_body<4, 4, 32>(args.p[j], blockIdx.x - args.p[j].tile_begin, threadIdx.x, As, Bs);
 }
 
+template <int L0>
 __global__ __launch_bounds__(NT, 2) void gemm_dl128_kernel(GemmArgs args) {
   __shared__ __align__(16) double lds[2 * DLCfg<4, 4>::STAGE];
   const long long t = xcd_tile(blockIdx.x, gridDim.x);
   const int j = find_prob(args, t);
-  gemm_tile_dl<4, 4>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
+  gemm_tile_dl<4, 4, L0>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
 }
 
+template <int L0>
 __global__ __launch_bounds__(NT, 4) void gemm_dl64_kernel(GemmArgs args) {
   __shared__ __align__(16) double lds[2 * DLCfg<2, 2>::STAGE];
   const long long t = xcd_tile(blockIdx.x, gridDim.x);
   const int j = find_prob(args, t);
-  gemm_tile_dl<2, 2>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
+  gemm_tile_dl<2, 2, L0>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
 }
 
+template <int L0>
 __global__ __launch_bounds__(256, 2) void gemm_l64_kernel(GemmArgs args) {
   __shared__ __align__(16) double lds[2 * DL2<2, 2, 2, 2>::STAGE];
   const long long t = xcd_tile(blockIdx.x, gridDim.x);
   const int j = find_prob(args, t);
-  gemm_tile_dl2<2, 2, 2, 2>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
+  gemm_tile_dl2<2, 2, 2, 2, L0>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
 }
 
+template <int L0>
 __global__ __launch_bounds__(512, 3) void gemm_l128x64_kernel(GemmArgs args) {
   __shared__ __align__(16) double lds[2 * DL2<4, 2, 2, 2>::STAGE];
   const long long t = xcd_tile(blockIdx.x, gridDim.x);
   const int j = find_prob(args, t);
-  gemm_tile_dl2<4, 2, 2, 2>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
+  gemm_tile_dl2<4, 2, 2, 2, L0>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
 }
 
+template <int L0>
 __global__ __launch_bounds__(512, 2) void gemm_l128_kernel(GemmArgs args) {
   __shared__ __align__(16) double lds[2 * DL2<4, 2, 2, 4>::STAGE];
   const long long t = xcd_tile(blockIdx.x, gridDim.x);
   const int j = find_prob(args, t);
-  gemm_tile_dl2<4, 2, 2, 4>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
+  gemm_tile_dl2<4, 2, 2, 4, L0>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
 }
 
 // The same tile bodies over a problem list in device memory (batched launches):
@@ -908,14 +933,27 @@ hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream) {
       for (int i = 0; i < nprob; ++i) lower_only = lower_only && probs[i].lower_tiles;
       kind = (fill && full) ? 7 : (lower_only ? 3 : 5);
     }
+    // the first segment's layout when every problem of the launch shares it
+    int L0 = small.p[0].seg[0].at * 2 + small.p[0].seg[0].bt;
+    for (int i = 1; i < small.nprob; ++i)
+      if (small.p[i].seg[0].at * 2 + small.p[i].seg[0].bt != L0) L0 = 4;
+#define BTA_LAUNCH_L0(KER, GRID, BLOCK, ARGS)                                                  \
+  switch (L0) {                                                                                \
+    case 0: hipLaunchKernelGGL((KER<0>), dim3((unsigned)(GRID)), dim3(BLOCK), 0, stream, ARGS); break; \
+    case 1: hipLaunchKernelGGL((KER<1>), dim3((unsigned)(GRID)), dim3(BLOCK), 0, stream, ARGS); break; \
+    case 2: hipLaunchKernelGGL((KER<2>), dim3((unsigned)(GRID)), dim3(BLOCK), 0, stream, ARGS); break; \
+    case 3: hipLaunchKernelGGL((KER<3>), dim3((unsigned)(GRID)), dim3(BLOCK), 0, stream, ARGS); break; \
+    default: hipLaunchKernelGGL((KER<4>), dim3((unsigned)(GRID)), dim3(BLOCK), 0, stream, ARGS); break; \
+  }
     timing_mark(KT_GEMM, true, stream);
     switch (kind) {
-      case 3: hipLaunchKernelGGL(gemm_dl64_kernel, dim3((unsigned)t64), dim3(NT), 0, stream, small); break;
-      case 4: hipLaunchKernelGGL(gemm_dl128_kernel, dim3((unsigned)t128), dim3(NT), 0, stream, big); break;
-      case 5: hipLaunchKernelGGL(gemm_l64_kernel, dim3((unsigned)t64), dim3(256), 0, stream, small); break;
-      case 7: hipLaunchKernelGGL(gemm_l128_kernel, dim3((unsigned)t128), dim3(512), 0, stream, big); break;
-      default: hipLaunchKernelGGL(gemm_l128x64_kernel, dim3((unsigned)t12864), dim3(512), 0, stream, mid); break;
+      case 3: BTA_LAUNCH_L0(gemm_dl64_kernel, t64, NT, small); break;
+      case 4: BTA_LAUNCH_L0(gemm_dl128_kernel, t128, NT, big); break;
+      case 5: BTA_LAUNCH_L0(gemm_l64_kernel, t64, 256, small); break;
+      case 7: BTA_LAUNCH_L0(gemm_l128_kernel, t128, 512, big); break;
+      default: BTA_LAUNCH_L0(gemm_l128x64_kernel, t12864, 512, mid); break;
     }
+#undef BTA_LAUNCH_L0
     timing_mark(KT_GEMM, false, stream);
     return hipGetLastError();
   }
