@@ -428,10 +428,12 @@ __device__ __forceinline__ void gemm_tile_dl(const GProb& P, long long local, in
       __syncthreads();
       const bool first = kk < nk0;
       const double* st = lds + (kk & 1) * C::STAGE;
+      // the next stage's loads first (its buffer was last read before the
+      // barrier), then this stage's operands
+      if (kk + 1 < total) issue(kk + 1);
       double a[WM][4], b[WN][4];
       stage_read<TM, WM>(a, st, LC < 4 ? (LC >> 1) : (first ? at0 : at1), rw, lane);
       stage_read<TN, WN>(b, st + C::SA, LC < 4 ? (LC & 1) : (first ? bt0 : bt1), cw, lane);
-      if (kk + 1 < total) issue(kk + 1);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -614,10 +616,12 @@ __device__ __forceinline__ void gemm_tile_dl2(const GProb& P, long long local, i
       __syncthreads();
       const bool first = kk < nk0;
       const double* st = lds + (kk & 1) * C::STAGE;
+      // the next stage's loads first (its buffer was last read before the
+      // barrier), then this stage's operands
+      if (kk + 1 < total) issue(kk + 1);
       double a[BI][4], b[BJ][4];
       stage_read<TM, BI>(a, st, LC < 4 ? (LC >> 1) : (first ? at0 : at1), rw, lane);
       stage_read<TN, BJ>(b, st + C::SA, LC < 4 ? (LC & 1) : (first ? bt0 : bt1), cw, lane);
-      if (kk + 1 < total) issue(kk + 1);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
