@@ -860,6 +860,8 @@ __global__ void factor_finish_kernel(const int* ctl, int64_t* info) {
 // ---------------------------------------------------------------------------
 // DIAG lookahead in columns (internal override for measurements).
 static int g_factor_look = FACTOR_LOOKAHEAD;
+// Upper bound on the factor kernel's workgroups (internal, for measurements; 0: one per CU).
+static int g_factor_max_grid = 0;
 
 FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   FactorPlan fp{};
@@ -913,7 +915,9 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
   hipLaunchKernelGGL(factor_reset_kernel, dim3(rgrid), dim3(256), 0, stream, p.flags, fp.nflags, p.ctl, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const long long grid = std::min<long long>(fp.ntasks + p.chain, (long long)num_cus);
+  long long cap = num_cus;
+  if (g_factor_max_grid > 0) cap = std::min<long long>(cap, g_factor_max_grid);
+  const long long grid = std::min<long long>(fp.ntasks + p.chain, cap);
   if (grid - p.chain < fp.ntasks && grid - p.chain <= fp.look + 1) return hipErrorInvalidConfiguration;  // lookahead needs more workers
   timing_mark(KT_FACTOR, true, stream);
   hipLaunchKernelGGL(factor_kernel, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, p);
@@ -1197,6 +1201,14 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
 extern "C" __attribute__((visibility("default"))) int bta_internal_factor_lookahead(int look) {
   const int prev = bta::g_factor_look;
   if (look >= 1 && look <= 64) bta::g_factor_look = look;
+  return prev;
+}
+
+// Internal: cap on the single-matrix factor kernel's workgroups (0 = one per
+// CU); returns the previous value (a negative argument only queries).
+extern "C" __attribute__((visibility("default"))) int bta_internal_factor_max_grid(int g) {
+  const int prev = bta::g_factor_max_grid;
+  if (g >= 0) bta::g_factor_max_grid = g;
   return prev;
 }
 
