@@ -35,8 +35,11 @@ def parse():
     ap.add_argument("--b", type=int, default=2048)
     ap.add_argument("--a", type=int, default=8)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=["custom", "large"], default="custom",
+    ap.add_argument("--workload", choices=["custom", "large", "batched", "autograd"], default="custom",
                     help="large: the n=256, b=4096, a=16 workload (diagonal of L_ii in [1,3]); "
+                         "batched: 64 matrices, n in [16,96], b in {128,256,384}, a in {2,4,6}, one batched "
+                         "factorization + selected inversion per step (graph-replayed); "
+                         "autograd: f = logdet Q + y^T Q^-1 y at n=256, b=512, a=4, forward + backward per step; "
                          "custom: --n/--b/--a with the default generator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-target-s", type=float, default=15.0, help="CPU oracle sample budget (seconds)")
@@ -108,6 +111,112 @@ def cpu_baseline(b, a, seed, target_s):
             "sample": f"POBTAF+POBTASI oracle on n={ns} blocks of b={b}, a={a} (same block shape), {dt:.1f} s"}
 
 
+def timed_steps(torch, step, steps, warmup):
+    """Warm up, then time `steps` calls of step() between synchronizations
+    (events on the current stream); returns (ms per step, wall seconds)."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, time.perf_counter() - t0
+
+
+def kernel_line(L, steps):
+    """Per-kernel HIP-event totals of the timed region (factor kernels only are
+    timed outside graphs)."""
+    kms = (ctypes.c_double * 4)()
+    kcnt = (ctypes.c_longlong * 4)()
+    L.bta_internal_timing_read(kms, kcnt)
+    L.bta_internal_timing(0, 0)
+    return kms, kcnt
+
+
+def run_batched(args, torch, bta, synth, L):
+    """The batched workload: one bta_factor_batched + bta_selinv_batched per step."""
+    wls = synth.batched_workloads(args.seed)
+    print(f"[bench] drawing {len(wls)} matrices ({sum(w.block_bytes() for w in wls) / 1e9:.2f} GB of blocks)",
+          file=sys.stderr, flush=True)
+    mats = [synth.make_torch(w, 100 + k, "cuda") for k, w in enumerate(wls)]
+    batch = bta.Batch(mats)
+
+    def step():
+        batch.factor(check=False)
+        batch.selinv()
+
+    step()  # first call: autotuning and graph capture
+    torch.cuda.synchronize()
+    L.bta_internal_timing(1, 4096 * max(1, args.steps))
+    ms, wall = timed_steps(torch, step, args.steps, args.warmup)
+    kms, kcnt = kernel_line(L, args.steps)
+    bad = [m for m, i in enumerate(batch.info) if int(i.item()) != 0]
+    if bad:
+        raise RuntimeError(f"factorization failed for matrices {bad}")
+    fl = sum(w.flops()["total"] for w in wls)
+    ffac = sum(w.flops()["factor"] for w in wls)
+    tfl = fl / (ms * 1e-3) / 1e12
+    roof = None
+    if kcnt[0]:
+        avg = kms[0] / kcnt[0]
+        ach = ffac / (kcnt[0] / args.steps) / (avg * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": "factor_batched_kernel", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": ffac / (kcnt[0] / args.steps), "avg_launch_ms": round(avg, 4)}
+    return {"metric": "POBTAF+POBTASI FP64 TFLOP/s and % FP64 MFMA peak on 1 MI355X at err<=1e-10",
+            "value": round(tfl, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "bta_batched64", "matrices": len(wls), "seed": args.seed, "flops_per_step": fl},
+            "pct_fp64_peak": round(100.0 * tfl / PEAK_FP64_TFLOPS, 2), "roofline": roof, "cpu_baseline": None,
+            "wall_s_timed": round(wall, 3)}
+
+
+def run_autograd(args, torch, bta, synth, L):
+    """f = logdet Q + y^T Q^{-1} y: forward and backward per step."""
+    from paper_2503_17528_amd import autograd
+
+    wl = synth.AUTOGRAD
+    Q = synth.make_torch(wl, args.seed, "cuda")
+    n, b, a = wl.n, wl.b, wl.a
+    g = torch.Generator(device="cuda").manual_seed(args.seed)
+    y = torch.randn(n * b + a, dtype=torch.float64, device="cuda", generator=g)
+    leaves = [Q[k].clone().requires_grad_(True) for k in "DBRT"]
+
+    def step():
+        for t in leaves:
+            t.grad = None
+        f = autograd.logdet_quad(*leaves, y)
+        f.backward()
+
+    L.bta_internal_timing(1, 4096 * max(1, args.steps))
+    ms, wall = timed_steps(torch, step, args.steps, args.warmup)
+    kms, kcnt = kernel_line(L, args.steps)
+    fl = wl.flops()
+    # factor + selected inversion (the O(n b^2) solves and gradient assembly are not counted)
+    tfl = fl["total"] / (ms * 1e-3) / 1e12
+    roof = None
+    if kcnt[0]:
+        avg = kms[0] / kcnt[0]
+        ach = fl["factor"] / (kcnt[0] / args.steps) / (avg * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": "factor_kernel", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": fl["factor"] / (kcnt[0] / args.steps), "avg_launch_ms": round(avg, 4)}
+    return {"metric": "POBTAF+POBTASI FP64 TFLOP/s and % FP64 MFMA peak on 1 MI355X at err<=1e-10",
+            "value": round(tfl, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": wl.name + "_logdet_quad_fwd_bwd", "n": n, "b": b, "a": a, "seed": args.seed,
+                       "flops_per_step": fl["total"]},
+            "pct_fp64_peak": round(100.0 * tfl / PEAK_FP64_TFLOPS, 2), "roofline": roof, "cpu_baseline": None,
+            "wall_s_timed": round(wall, 3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -125,6 +234,10 @@ def main():
     L = bta.lib()
     L.bta_internal_timing.argtypes = [ctypes.c_int, ctypes.c_int]
     L.bta_internal_timing_read.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    if args.workload in ("batched", "autograd"):
+        run = run_batched if args.workload == "batched" else run_autograd
+        print(json.dumps(run(args, torch, bta, synth, L)), flush=True)
+        return
 
     if args.workload == "large":
         wl = synth.LARGE

@@ -2,10 +2,13 @@
 // the log-determinant 2 * sum log diag(L).  Neither is in the paper; both are
 // needed for f(A) = log det A + y^T A^{-1} y and its gradient.
 //
-// The solve is memory bound (O(n b^2) reads of L per sweep).  Each right-hand
-// side column is handled by one workgroup that sweeps the block rows in order;
-// inside a diagonal block the substitution goes tile by tile, with the 64 x 64
-// diagonal tiles applied through their precomputed inverses.
+// The solve is memory bound (O(n b^2) reads of L per sweep).  Per block row
+// and right-hand side, the coupling to the block solved before it (L_{i,i-1}
+// z_{i-1} forward; L_{i+1,i}^T x_{i+1} and L_{n,i}^T x_n backward) is a
+// matrix-vector product spread over many workgroups (split along the
+// reduction, partial sums summed in a fixed order), and the substitution with
+// the diagonal block goes tile by tile in one workgroup per right-hand side,
+// with the 64 x 64 diagonal tiles applied through their precomputed inverses.
 #include <algorithm>
 
 #include "bta_device.hpp"
@@ -211,26 +214,47 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// out[r] (r < R <= 64) += sign * sum_{k<K} M[r*ld + k] x[k]   (row access, lanes over k)
+// out[r] (r < R <= 64) += sign * sum_{k<K} M[r*ld + k] x[k]   (row access, lanes over k).
+// Wave w takes rows w, w+4, ..., w+60 together, so the loads of all its rows
+// are in flight at once (one row at a time would pay the memory latency per row).
 __device__ void rowdot_acc(const double* M, int64_t ld, int R, int64_t K, const double* x, double* out, double sign, int tid) {
   const int w = tid >> 6, lane = tid & 63;
-  for (int r = w; r < R; r += 4) {
-    double s = 0.0;
-    const double* row = M + (int64_t)r * ld;
-    for (int64_t k = lane; k < K; k += 64) s += row[k] * x[k];
-    s = wave_sum(s);
-    if (lane == 0) out[r] += sign * s;
+  double s[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) s[j] = 0.0;
+  for (int64_t k = lane; k < K; k += 64) {
+    const double xk = x[k];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int r = w + 4 * j;
+      if (r < R) s[j] += M[(int64_t)r * ld + k] * xk;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int r = w + 4 * j;
+    const double t = wave_sum(s[j]);
+    if (lane == 0 && r < R) out[r] += sign * t;
   }
 }
 
-// out[k] (k < Kc <= 64) += sign * sum_{r<R} M[r*ld + k] x[r]   (column access)
+// out[k] (k < Kc <= 64) += sign * sum_{r<R} M[r*ld + k] x[r]   (column access).
+// Eight independent partial sums per thread keep eight rows' loads in flight.
 __device__ void coldot_acc(const double* M, int64_t ld, int64_t R, int Kc, const double* x, double* out, double* red,
                            double sign, int tid) {
   const int k = tid & 63, ph = tid >> 6;
-  double s = 0.0;
-  if (k < Kc)
-    for (int64_t r = ph; r < R; r += 4) s += M[r * ld + k] * x[r];
-  red[ph * 64 + k] = s;
+  double s[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) s[u] = 0.0;
+  if (k < Kc) {
+    int64_t r = ph;
+    for (; r + 28 < R; r += 32) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[u] += M[(r + 4 * u) * ld + k] * x[r + 4 * u];
+    }
+    for (; r < R; r += 4) s[0] += M[r * ld + k] * x[r];
+  }
+  red[ph * 64 + k] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
   __syncthreads();
   if (tid < 64 && tid < Kc) out[tid] += sign * (red[tid] + red[64 + tid] + red[128 + tid] + red[192 + tid]);
   __syncthreads();
@@ -240,114 +264,218 @@ struct SolveParams {
   int64_t n, b, a, nrhs, N;
   int T, TA;
   const double* LD; const double* LB; const double* LR; const double* LT;
-  double* rhs;
   const double* Wd;  // [n*T] tile inverses
   const double* Wt;  // [TA] tip tile inverses
   double* vec;       // [nrhs][N] contiguous working copies
+  double* part;      // [nrhs][SP][b] partial sums of the coupling products
+  double* ptip;      // [nrhs][n][a] partial sums of the arrow coupling
+  int SF, SB, SR;    // splits: forward (along b), backward L_{i+1,i} and L_{n,i} (64 rows each)
+  int64_t SP;        // split capacity per right-hand side
 };
 
-__global__ __launch_bounds__(NT) void solve_kernel(SolveParams p) {
+__global__ __launch_bounds__(256) void solve_gather_kernel(const double* rhs, int64_t nrhs, int64_t N, double* vec) {
+  const int64_t j = blockIdx.y;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += (int64_t)gridDim.x * 256) vec[j * N + r] = rhs[r * nrhs + j];
+}
+__global__ __launch_bounds__(256) void solve_scatter_kernel(double* rhs, int64_t nrhs, int64_t N, const double* vec) {
+  const int64_t j = blockIdx.y;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += (int64_t)gridDim.x * 256) rhs[r * nrhs + j] = vec[j * N + r];
+}
+
+// part[j][s][r] = sum over k in split s of L_{i,i-1}[r][k] z_{i-1}[k]; a
+// workgroup covers 16 rows (4 per wave, lanes along k), grid (b/16, SF, nrhs).
+__global__ __launch_bounds__(256) void solve_fwd_couple_kernel(SolveParams p, int64_t i) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t j = blockIdx.z, s = blockIdx.y, b = p.b;
+  const int64_t kc = (b + p.SF - 1) / p.SF, k0 = s * kc, k1 = std::min<int64_t>(b, k0 + kc);
+  const double* M = p.LB + (i - 1) * b * b;
+  const double* x = p.vec + j * p.N + (i - 1) * b;
+  const int64_t rbase = (int64_t)blockIdx.x * 16 + 4 * w;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t k = k0 + lane; k < k1; k += 64) {
+    const double xk = x[k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (rbase + u < b) acc[u] += M[(rbase + u) * b + k] * xk;
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const double t = wave_sum(acc[u]);
+    if (lane == 0 && rbase + u < b) p.part[(j * p.SP + s) * b + rbase + u] = t;
+  }
+}
+
+// ptip[j][i][r] = L_{n,i}[r] . z_i for every block i (grid (n, 1, nrhs)).
+__global__ __launch_bounds__(256) void solve_tip_couple_kernel(SolveParams p) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t j = blockIdx.z, i = blockIdx.x, b = p.b, a = p.a;
+  const double* M = p.LR + i * a * b;
+  const double* x = p.vec + j * p.N + i * b;
+  for (int64_t r = w; r < a; r += 4) {
+    double acc = 0.0;
+    for (int64_t k = lane; k < b; k += 64) acc += M[r * b + k] * x[k];
+    acc = wave_sum(acc);
+    if (lane == 0) p.ptip[(j * p.n + i) * a + r] = acc;
+  }
+}
+
+// part[j][s][k] = sum over the 64 rows r of split s of M[r][k] x[r], with
+// M = L_{i+1,i} and x = x_{i+1} for s < nb, M = L_{n,i} and x = x_n after;
+// lanes along k, the four waves over the rows; grid (b/64, splits, nrhs).
+__global__ __launch_bounds__(256) void solve_bwd_couple_kernel(SolveParams p, int64_t i, int nb) {
+  __shared__ double red[256];
+  const int ph = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t j = blockIdx.z, s = blockIdx.y, b = p.b, a = p.a;
+  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+  const bool sub = s < nb;
+  const double* M = sub ? p.LB + i * b * b : p.LR + i * a * b;
+  const double* x = sub ? p.vec + j * p.N + (i + 1) * b : p.vec + j * p.N + p.n * b;
+  const int64_t R = sub ? b : a;
+  const int64_t r0 = (sub ? s : s - nb) * 64, r1 = std::min<int64_t>(R, r0 + 64);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (k < b) {
+    int64_t r = r0 + ph;
+    for (; r + 12 < r1; r += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += M[(r + 4 * u) * b + k] * x[r + 4 * u];
+    }
+    for (; r < r1; r += 4) acc[0] += M[r * b + k] * x[r];
+  }
+  red[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (ph == 0 && k < b) p.part[(j * p.SP + s) * b + k] = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+}
+
+// Block i forward: z_i = L_ii^{-1} (z_i - sum_s part[s]) (nsplit partials), tile by tile.
+__global__ __launch_bounds__(NT) void solve_fwd_diag_kernel(SolveParams p, int64_t i, int nsplit) {
   __shared__ double v[64];
   __shared__ double red[256];
   const int tid = threadIdx.x;
-  const int64_t j = blockIdx.x;
-  const int64_t n = p.n, b = p.b, a = p.a, N = p.N;
-  const int64_t bb = b * b, ab = a * b;
-  double* z = p.vec + j * N;
-  for (int64_t r = tid; r < N; r += NT) z[r] = p.rhs[r * p.nrhs + j];
+  const int64_t j = blockIdx.x, b = p.b, bb = b * b;
+  double* z = p.vec + j * p.N + i * b;
+  if (nsplit > 0) {
+    const double* pt = p.part + j * p.SP * b;
+    for (int64_t r = tid; r < b; r += NT) {
+      double t = 0.0;
+      for (int s2 = 0; s2 < nsplit; ++s2) t += pt[s2 * b + r];
+      z[r] -= t;
+    }
+  }
   __syncthreads();
-
-  // ---- forward: z_i = L_ii^{-1} (y_i - L_{i,i-1} z_{i-1}); tip last
-  for (int64_t i = 0; i < n; ++i) {
-    const double* Ld = p.LD + i * bb;
-    for (int c = 0; c < p.T; ++c) {
-      const int ext = (int)std::min<int64_t>(64, b - (int64_t)c * 64);
-      const int64_t r0 = i * b + (int64_t)c * 64;
-      if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
-      __syncthreads();
-      if (i > 0) rowdot_acc(p.LB + (i - 1) * bb + (int64_t)c * 64 * b, b, ext, b, z + (i - 1) * b, v, -1.0, tid);
-      rowdot_acc(Ld + (int64_t)c * 64 * b, b, ext, (int64_t)c * 64, z + i * b, v, -1.0, tid);
-      __syncthreads();
-      // z_c = W_cc v
-      const double* W = p.Wd + (i * p.T + c) * 4096;
-      if (tid < 64) red[tid] = 0.0;
-      __syncthreads();
-      rowdot_acc(W, 64, ext, ext, v, red, 1.0, tid);
-      __syncthreads();
-      if (tid < ext) z[r0 + tid] = red[tid];
-      __syncthreads();
-    }
+  const double* Ld = p.LD + i * bb;
+  for (int c = 0; c < p.T; ++c) {
+    const int ext = (int)std::min<int64_t>(64, b - (int64_t)c * 64);
+    const int64_t r0 = (int64_t)c * 64;
+    if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
+    __syncthreads();
+    if (c > 0) rowdot_acc(Ld + r0 * b, b, ext, r0, z, v, -1.0, tid);
+    __syncthreads();
+    if (tid < 64) red[tid] = 0.0;
+    __syncthreads();
+    rowdot_acc(p.Wd + (i * p.T + c) * 4096, 64, ext, ext, v, red, 1.0, tid);
+    __syncthreads();
+    if (tid < ext) z[r0 + tid] = red[tid];
+    __syncthreads();
   }
-  if (a > 0) {
-    for (int c = 0; c < p.TA; ++c) {
-      const int ext = (int)std::min<int64_t>(64, a - (int64_t)c * 64);
-      const int64_t r0 = n * b + (int64_t)c * 64;
-      if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
-      __syncthreads();
-      for (int64_t i = 0; i < n; ++i)
-        rowdot_acc(p.LR + i * ab + (int64_t)c * 64 * b, b, ext, b, z + i * b, v, -1.0, tid);
-      rowdot_acc(p.LT + (int64_t)c * 64 * a, a, ext, (int64_t)c * 64, z + n * b, v, -1.0, tid);
-      __syncthreads();
-      if (tid < 64) red[tid] = 0.0;
-      __syncthreads();
-      rowdot_acc(p.Wt + (int64_t)c * 4096, 64, ext, ext, v, red, 1.0, tid);
-      __syncthreads();
-      if (tid < ext) z[r0 + tid] = red[tid];
-      __syncthreads();
-    }
-  }
+}
 
-  // ---- backward: x_n = L_nn^{-T} z_n; x_i = L_ii^{-T}(z_i - L_{i+1,i}^T x_{i+1} - L_{n,i}^T x_n)
+// Tip forward: z_n = L_nn^{-1} (z_n - sum_i ptip[i]) (blocks summed in order), then
+// the tip backward x_n = L_nn^{-T} z_n.
+__global__ __launch_bounds__(NT) void solve_tip_kernel(SolveParams p) {
+  __shared__ double v[64];
+  __shared__ double red[256];
   __shared__ double red2[256];
-  if (a > 0) {
-    for (int c = p.TA - 1; c >= 0; --c) {
-      const int ext = (int)std::min<int64_t>(64, a - (int64_t)c * 64);
-      const int64_t r0 = n * b + (int64_t)c * 64;
-      if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
-      __syncthreads();
-      const int64_t below = a - ((int64_t)c * 64 + ext);
-      if (below > 0)
-        coldot_acc(p.LT + ((int64_t)c * 64 + ext) * a + (int64_t)c * 64, a, below, ext, z + n * b + (int64_t)c * 64 + ext,
-                   v, red, -1.0, tid);
-      // x_c = W_cc^T v
-      if (tid < 64) red2[tid] = 0.0;
-      __syncthreads();
-      coldot_acc(p.Wt + (int64_t)c * 4096, 64, ext, ext, v, red2, red, 1.0, tid);
-      if (tid < ext) z[r0 + tid] = red2[tid];
-      __syncthreads();
+  const int tid = threadIdx.x;
+  const int64_t j = blockIdx.x, a = p.a, n = p.n;
+  double* z = p.vec + j * p.N + n * p.b;
+  for (int64_t r = tid; r < a; r += NT) {
+    double t = 0.0;
+    for (int64_t i = 0; i < n; ++i) t += p.ptip[(j * n + i) * a + r];
+    z[r] -= t;
+  }
+  __syncthreads();
+  for (int c = 0; c < p.TA; ++c) {
+    const int ext = (int)std::min<int64_t>(64, a - (int64_t)c * 64);
+    const int64_t r0 = (int64_t)c * 64;
+    if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
+    __syncthreads();
+    if (c > 0) rowdot_acc(p.LT + r0 * a, a, ext, r0, z, v, -1.0, tid);
+    __syncthreads();
+    if (tid < 64) red[tid] = 0.0;
+    __syncthreads();
+    rowdot_acc(p.Wt + (int64_t)c * 4096, 64, ext, ext, v, red, 1.0, tid);
+    __syncthreads();
+    if (tid < ext) z[r0 + tid] = red[tid];
+    __syncthreads();
+  }
+  for (int c = p.TA - 1; c >= 0; --c) {
+    const int ext = (int)std::min<int64_t>(64, a - (int64_t)c * 64);
+    const int64_t r0 = (int64_t)c * 64;
+    if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
+    __syncthreads();
+    const int64_t below = a - (r0 + ext);
+    if (below > 0) coldot_acc(p.LT + (r0 + ext) * a + r0, a, below, ext, z + r0 + ext, v, red, -1.0, tid);
+    if (tid < 64) red2[tid] = 0.0;
+    __syncthreads();
+    coldot_acc(p.Wt + (int64_t)c * 4096, 64, ext, ext, v, red2, red, 1.0, tid);
+    if (tid < ext) z[r0 + tid] = red2[tid];
+    __syncthreads();
+  }
+}
+
+// Block i backward: x_i = L_ii^{-T} (z_i - sum_s part[s]), tile by tile from the last.
+__global__ __launch_bounds__(NT) void solve_bwd_diag_kernel(SolveParams p, int64_t i, int nsplit) {
+  __shared__ double v[64];
+  __shared__ double red[256];
+  __shared__ double red2[256];
+  const int tid = threadIdx.x;
+  const int64_t j = blockIdx.x, b = p.b, bb = b * b;
+  double* z = p.vec + j * p.N + i * b;
+  if (nsplit > 0) {
+    const double* pt = p.part + j * p.SP * b;
+    for (int64_t r = tid; r < b; r += NT) {
+      double t = 0.0;
+      for (int s2 = 0; s2 < nsplit; ++s2) t += pt[s2 * b + r];
+      z[r] -= t;
     }
   }
-  for (int64_t i = n - 1; i >= 0; --i) {
-    const double* Ld = p.LD + i * bb;
-    for (int c = p.T - 1; c >= 0; --c) {
-      const int ext = (int)std::min<int64_t>(64, b - (int64_t)c * 64);
-      const int64_t r0 = i * b + (int64_t)c * 64;
-      if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
-      __syncthreads();
-      if (i < n - 1) coldot_acc(p.LB + i * bb + (int64_t)c * 64, b, b, ext, z + (i + 1) * b, v, red, -1.0, tid);
-      if (a > 0) coldot_acc(p.LR + i * ab + (int64_t)c * 64, b, a, ext, z + n * b, v, red, -1.0, tid);
-      const int64_t below = b - ((int64_t)c * 64 + ext);
-      if (below > 0)
-        coldot_acc(Ld + ((int64_t)c * 64 + ext) * b + (int64_t)c * 64, b, below, ext, z + i * b + (int64_t)c * 64 + ext, v,
-                   red, -1.0, tid);
-      if (tid < 64) red2[tid] = 0.0;
-      __syncthreads();
-      coldot_acc(p.Wd + (i * p.T + c) * 4096, 64, ext, ext, v, red2, red, 1.0, tid);
-      if (tid < ext) z[r0 + tid] = red2[tid];
-      __syncthreads();
-    }
+  __syncthreads();
+  const double* Ld = p.LD + i * bb;
+  for (int c = p.T - 1; c >= 0; --c) {
+    const int ext = (int)std::min<int64_t>(64, b - (int64_t)c * 64);
+    const int64_t r0 = (int64_t)c * 64;
+    if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
+    __syncthreads();
+    const int64_t below = b - (r0 + ext);
+    if (below > 0) coldot_acc(Ld + (r0 + ext) * b + r0, b, below, ext, z + r0 + ext, v, red, -1.0, tid);
+    if (tid < 64) red2[tid] = 0.0;
+    __syncthreads();
+    coldot_acc(p.Wd + (i * p.T + c) * 4096, 64, ext, ext, v, red2, red, 1.0, tid);
+    if (tid < ext) z[r0 + tid] = red2[tid];
+    __syncthreads();
   }
-  for (int64_t r = tid; r < N; r += NT) p.rhs[r * p.nrhs + j] = z[r];
+}
+
+static void solve_splits(int64_t b, int64_t a, int& SF, int& SB, int& SR, int64_t& SP) {
+  SF = (int)std::max<int64_t>(1, (b + 255) / 256);
+  SB = (int)((b + 63) / 64);
+  SR = (int)((a + 63) / 64);
+  SP = std::max<int64_t>(SF, (int64_t)SB + SR);
 }
 
 size_t solve_work_bytes(int64_t n, int64_t b, int64_t a, int64_t nrhs) {
   const int64_t T = (b + 63) / 64, TA = (a + 63) / 64;
   const int64_t N = n * b + a;
+  int SF, SB, SR;
+  int64_t SP;
+  solve_splits(b, a, SF, SB, SR, SP);
   size_t bytes = 0;
   auto take = [&](size_t x) { bytes += (x + 255) & ~size_t(255); };
   take(8 * 4096 * (size_t)(n * T));
   take(8 * 4096 * (size_t)std::max<int64_t>(TA, 1));
   take(8 * (size_t)(N * nrhs));
+  take(8 * (size_t)(SP * b * nrhs));
+  take(8 * (size_t)std::max<int64_t>(1, n * a * nrhs));
   return bytes;
 }
 
@@ -360,21 +488,55 @@ hipError_t solve_launch(int64_t n, int64_t b, int64_t a, const double* LD, const
   SolveParams p;
   p.n = n; p.b = b; p.a = a; p.nrhs = nrhs; p.N = n * b + a;
   p.T = (int)T; p.TA = (int)TA;
-  p.LD = LD; p.LB = LB; p.LR = LR; p.LT = LT; p.rhs = rhs;
+  p.LD = LD; p.LB = LB; p.LR = LR; p.LT = LT;
+  solve_splits(b, a, p.SF, p.SB, p.SR, p.SP);
   double* Wd = reinterpret_cast<double*>(w + take(8 * 4096 * (size_t)(n * T)));
   double* Wt = reinterpret_cast<double*>(w + take(8 * 4096 * (size_t)std::max<int64_t>(TA, 1)));
   p.vec = reinterpret_cast<double*>(w + take(8 * (size_t)(p.N * nrhs)));
+  p.part = reinterpret_cast<double*>(w + take(8 * (size_t)(p.SP * b * nrhs)));
+  p.ptip = reinterpret_cast<double*>(w + take(8 * (size_t)std::max<int64_t>(1, n * a * nrhs)));
   p.Wd = Wd; p.Wt = Wt;
+  auto ok = [&]() { return hipGetLastError(); };
   hipLaunchKernelGGL(tile_inverses_kernel, dim3((unsigned)(n * T)), dim3(NT), 0, stream, LD, b, b * b, (int)T, Wd);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (hipError_t e = ok()) return e;
   if (a > 0) {
     hipLaunchKernelGGL(tile_inverses_kernel, dim3((unsigned)TA), dim3(NT), 0, stream, LT, a, (int64_t)0, (int)TA, Wt);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (hipError_t e = ok()) return e;
   }
-  hipLaunchKernelGGL(solve_kernel, dim3((unsigned)nrhs), dim3(NT), 0, stream, p);
-  return hipGetLastError();
+  const unsigned gN = (unsigned)std::min<int64_t>(1024, (p.N + 255) / 256);
+  hipLaunchKernelGGL(solve_gather_kernel, dim3(gN, (unsigned)nrhs), dim3(256), 0, stream, rhs, nrhs, p.N, p.vec);
+  if (hipError_t e = ok()) return e;
+  // forward over the blocks
+  for (int64_t i = 0; i < n; ++i) {
+    if (i > 0) {
+      hipLaunchKernelGGL(solve_fwd_couple_kernel, dim3((unsigned)((b + 15) / 16), (unsigned)p.SF, (unsigned)nrhs), dim3(256),
+                         0, stream, p, i);
+      if (hipError_t e = ok()) return e;
+    }
+    hipLaunchKernelGGL(solve_fwd_diag_kernel, dim3((unsigned)nrhs), dim3(NT), 0, stream, p, i, i > 0 ? p.SF : 0);
+    if (hipError_t e = ok()) return e;
+  }
+  // the tip, forward then backward
+  if (a > 0) {
+    hipLaunchKernelGGL(solve_tip_couple_kernel, dim3((unsigned)n, 1, (unsigned)nrhs), dim3(256), 0, stream, p);
+    if (hipError_t e = ok()) return e;
+    hipLaunchKernelGGL(solve_tip_kernel, dim3((unsigned)nrhs), dim3(NT), 0, stream, p);
+    if (hipError_t e = ok()) return e;
+  }
+  // backward over the blocks
+  for (int64_t i = n - 1; i >= 0; --i) {
+    const int nb = i < n - 1 ? p.SB : 0;
+    const int ns = nb + (a > 0 ? p.SR : 0);
+    if (ns > 0) {
+      hipLaunchKernelGGL(solve_bwd_couple_kernel, dim3((unsigned)((b + 63) / 64), (unsigned)ns, (unsigned)nrhs), dim3(256), 0,
+                         stream, p, i, nb);
+      if (hipError_t e = ok()) return e;
+    }
+    hipLaunchKernelGGL(solve_bwd_diag_kernel, dim3((unsigned)nrhs), dim3(NT), 0, stream, p, i, ns);
+    if (hipError_t e = ok()) return e;
+  }
+  hipLaunchKernelGGL(solve_scatter_kernel, dim3(gN, (unsigned)nrhs), dim3(256), 0, stream, rhs, nrhs, p.N, p.vec);
+  return ok();
 }
 
 }  // namespace bta
