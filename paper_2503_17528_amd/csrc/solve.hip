@@ -216,8 +216,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // out[r] (r < R <= 64) += sign * sum_{k<K} M[r*ld + k] x[k]   (row access, lanes over k).
 // Wave w takes rows w, w+4, ..., w+60 together, so the loads of all its rows
-// are in flight at once (one row at a time would pay the memory latency per row).
-__device__ void rowdot_acc(const double* M, int64_t ld, int R, int64_t K, const double* x, double* out, double sign, int tid) {
+// are in flight at once; the per-lane partial sums are then reduced through
+// LDS (part: 64 x 65 doubles), four threads per row, instead of one chain of
+// cross-lane shuffles per row.  Ends with a barrier.
+__device__ void rowdot_acc(const double* M, int64_t ld, int R, int64_t K, const double* x, double* out, double sign,
+                           double* part, int tid) {
   const int w = tid >> 6, lane = tid & 63;
   double s[16];
 #pragma unroll
@@ -231,11 +234,16 @@ __device__ void rowdot_acc(const double* M, int64_t ld, int R, int64_t K, const 
     }
   }
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int r = w + 4 * j;
-    const double t = wave_sum(s[j]);
-    if (lane == 0 && r < R) out[r] += sign * t;
-  }
+  for (int j = 0; j < 16; ++j) part[(w + 4 * j) * 65 + lane] = s[j];
+  __syncthreads();
+  const int r = tid >> 2, q = tid & 3;
+  double t = 0.0;
+#pragma unroll
+  for (int l = 0; l < 16; ++l) t += part[r * 65 + 16 * q + l];
+  t += __shfl_xor(t, 1, 64);
+  t += __shfl_xor(t, 2, 64);
+  if (q == 0 && r < R) out[r] += sign * t;
+  __syncthreads();
 }
 
 // out[k] (k < Kc <= 64) += sign * sum_{r<R} M[r*ld + k] x[r]   (column access).
@@ -350,6 +358,7 @@ __global__ __launch_bounds__(256) void solve_bwd_couple_kernel(SolveParams p, in
 __global__ __launch_bounds__(NT) void solve_fwd_diag_kernel(SolveParams p, int64_t i, int nsplit) {
   __shared__ double v[64];
   __shared__ double red[256];
+  __shared__ double rpart[64 * 65];
   const int tid = threadIdx.x;
   const int64_t j = blockIdx.x, b = p.b, bb = b * b;
   double* z = p.vec + j * p.N + i * b;
@@ -368,11 +377,11 @@ __global__ __launch_bounds__(NT) void solve_fwd_diag_kernel(SolveParams p, int64
     const int64_t r0 = (int64_t)c * 64;
     if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
     __syncthreads();
-    if (c > 0) rowdot_acc(Ld + r0 * b, b, ext, r0, z, v, -1.0, tid);
+    if (c > 0) rowdot_acc(Ld + r0 * b, b, ext, r0, z, v, -1.0, rpart, tid);
     __syncthreads();
     if (tid < 64) red[tid] = 0.0;
     __syncthreads();
-    rowdot_acc(p.Wd + (i * p.T + c) * 4096, 64, ext, ext, v, red, 1.0, tid);
+    rowdot_acc(p.Wd + (i * p.T + c) * 4096, 64, ext, ext, v, red, 1.0, rpart, tid);
     __syncthreads();
     if (tid < ext) z[r0 + tid] = red[tid];
     __syncthreads();
@@ -385,6 +394,7 @@ __global__ __launch_bounds__(NT) void solve_tip_kernel(SolveParams p) {
   __shared__ double v[64];
   __shared__ double red[256];
   __shared__ double red2[256];
+  __shared__ double rpart[64 * 65];
   const int tid = threadIdx.x;
   const int64_t j = blockIdx.x, a = p.a, n = p.n;
   double* z = p.vec + j * p.N + n * p.b;
@@ -399,11 +409,11 @@ __global__ __launch_bounds__(NT) void solve_tip_kernel(SolveParams p) {
     const int64_t r0 = (int64_t)c * 64;
     if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
     __syncthreads();
-    if (c > 0) rowdot_acc(p.LT + r0 * a, a, ext, r0, z, v, -1.0, tid);
+    if (c > 0) rowdot_acc(p.LT + r0 * a, a, ext, r0, z, v, -1.0, rpart, tid);
     __syncthreads();
     if (tid < 64) red[tid] = 0.0;
     __syncthreads();
-    rowdot_acc(p.Wt + (int64_t)c * 4096, 64, ext, ext, v, red, 1.0, tid);
+    rowdot_acc(p.Wt + (int64_t)c * 4096, 64, ext, ext, v, red, 1.0, rpart, tid);
     __syncthreads();
     if (tid < ext) z[r0 + tid] = red[tid];
     __syncthreads();
