@@ -225,12 +225,15 @@ __device__ void rowdot_acc(const double* M, int64_t ld, int R, int64_t K, const 
   double s[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) s[j] = 0.0;
+  // branchless: rows past R read row R-1 and contribute zero (a per-row branch
+  // would make the compiler wait for each load before the next)
   for (int64_t k = lane; k < K; k += 64) {
     const double xk = x[k];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int r = w + 4 * j;
-      if (r < R) s[j] += M[(int64_t)r * ld + k] * xk;
+      const double m = M[(int64_t)(r < R ? r : R - 1) * ld + k];
+      s[j] += (r < R ? m : 0.0) * xk;
     }
   }
 #pragma unroll
@@ -355,20 +358,22 @@ __global__ __launch_bounds__(256) void solve_bwd_couple_kernel(SolveParams p, in
 }
 
 // Block i forward: z_i = L_ii^{-1} (z_i - sum_s part[s]) (nsplit partials), tile by tile.
-__global__ __launch_bounds__(NT) void solve_fwd_diag_kernel(SolveParams p, int64_t i, int nsplit) {
+// The block's vector is kept in LDS (dynamic, b doubles, b <= 4096), so the
+// tile chain does not round-trip through global memory.
+__global__ __launch_bounds__(NT) void solve_fwd_diag_kernel(SolveParams p, int64_t i, int nsplit, int in_lds) {
+  extern __shared__ double zsh[];
   __shared__ double v[64];
   __shared__ double red[256];
   __shared__ double rpart[64 * 65];
   const int tid = threadIdx.x;
   const int64_t j = blockIdx.x, b = p.b, bb = b * b;
-  double* z = p.vec + j * p.N + i * b;
-  if (nsplit > 0) {
-    const double* pt = p.part + j * p.SP * b;
-    for (int64_t r = tid; r < b; r += NT) {
-      double t = 0.0;
-      for (int s2 = 0; s2 < nsplit; ++s2) t += pt[s2 * b + r];
-      z[r] -= t;
-    }
+  double* zg = p.vec + j * p.N + i * b;
+  double* z = in_lds ? zsh : zg;
+  const double* pt = p.part + j * p.SP * b;
+  for (int64_t r = tid; r < b; r += NT) {
+    double t = 0.0;
+    for (int s2 = 0; s2 < nsplit; ++s2) t += pt[s2 * b + r];
+    z[r] = zg[r] - t;
   }
   __syncthreads();
   const double* Ld = p.LD + i * bb;
@@ -378,14 +383,14 @@ __global__ __launch_bounds__(NT) void solve_fwd_diag_kernel(SolveParams p, int64
     if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
     __syncthreads();
     if (c > 0) rowdot_acc(Ld + r0 * b, b, ext, r0, z, v, -1.0, rpart, tid);
-    __syncthreads();
     if (tid < 64) red[tid] = 0.0;
     __syncthreads();
     rowdot_acc(p.Wd + (i * p.T + c) * 4096, 64, ext, ext, v, red, 1.0, rpart, tid);
-    __syncthreads();
     if (tid < ext) z[r0 + tid] = red[tid];
     __syncthreads();
   }
+  if (in_lds)
+    for (int64_t r = tid; r < b; r += NT) zg[r] = z[r];
 }
 
 // Tip forward: z_n = L_nn^{-1} (z_n - sum_i ptip[i]) (blocks summed in order), then
@@ -433,21 +438,22 @@ __global__ __launch_bounds__(NT) void solve_tip_kernel(SolveParams p) {
   }
 }
 
-// Block i backward: x_i = L_ii^{-T} (z_i - sum_s part[s]), tile by tile from the last.
-__global__ __launch_bounds__(NT) void solve_bwd_diag_kernel(SolveParams p, int64_t i, int nsplit) {
+// Block i backward: x_i = L_ii^{-T} (z_i - sum_s part[s]), tile by tile from the
+// last, the block's vector in LDS when it fits (as in the forward).
+__global__ __launch_bounds__(NT) void solve_bwd_diag_kernel(SolveParams p, int64_t i, int nsplit, int in_lds) {
+  extern __shared__ double zsh[];
   __shared__ double v[64];
   __shared__ double red[256];
   __shared__ double red2[256];
   const int tid = threadIdx.x;
   const int64_t j = blockIdx.x, b = p.b, bb = b * b;
-  double* z = p.vec + j * p.N + i * b;
-  if (nsplit > 0) {
-    const double* pt = p.part + j * p.SP * b;
-    for (int64_t r = tid; r < b; r += NT) {
-      double t = 0.0;
-      for (int s2 = 0; s2 < nsplit; ++s2) t += pt[s2 * b + r];
-      z[r] -= t;
-    }
+  double* zg = p.vec + j * p.N + i * b;
+  double* z = in_lds ? zsh : zg;
+  const double* pt = p.part + j * p.SP * b;
+  for (int64_t r = tid; r < b; r += NT) {
+    double t = 0.0;
+    for (int s2 = 0; s2 < nsplit; ++s2) t += pt[s2 * b + r];
+    z[r] = zg[r] - t;
   }
   __syncthreads();
   const double* Ld = p.LD + i * bb;
@@ -464,6 +470,8 @@ __global__ __launch_bounds__(NT) void solve_bwd_diag_kernel(SolveParams p, int64
     if (tid < ext) z[r0 + tid] = red2[tid];
     __syncthreads();
   }
+  if (in_lds)
+    for (int64_t r = tid; r < b; r += NT) zg[r] = z[r];
 }
 
 static void solve_splits(int64_t b, int64_t a, int& SF, int& SB, int& SR, int64_t& SP) {
@@ -514,6 +522,10 @@ hipError_t solve_launch(int64_t n, int64_t b, int64_t a, const double* LD, const
     if (hipError_t e = ok()) return e;
   }
   const unsigned gN = (unsigned)std::min<int64_t>(1024, (p.N + 255) / 256);
+  // the diagonal-block kernels keep the block's vector in LDS up to b = 4096
+  // (32 KB of dynamic LDS, within the default limit)
+  const int in_lds = b <= 4096 ? 1 : 0;
+  const size_t zbytes = in_lds ? 8 * (size_t)b : 0;
   hipLaunchKernelGGL(solve_gather_kernel, dim3(gN, (unsigned)nrhs), dim3(256), 0, stream, rhs, nrhs, p.N, p.vec);
   if (hipError_t e = ok()) return e;
   // forward over the blocks
@@ -523,7 +535,7 @@ hipError_t solve_launch(int64_t n, int64_t b, int64_t a, const double* LD, const
                          0, stream, p, i);
       if (hipError_t e = ok()) return e;
     }
-    hipLaunchKernelGGL(solve_fwd_diag_kernel, dim3((unsigned)nrhs), dim3(NT), 0, stream, p, i, i > 0 ? p.SF : 0);
+    hipLaunchKernelGGL(solve_fwd_diag_kernel, dim3((unsigned)nrhs), dim3(NT), zbytes, stream, p, i, i > 0 ? p.SF : 0, in_lds);
     if (hipError_t e = ok()) return e;
   }
   // the tip, forward then backward
@@ -542,7 +554,7 @@ hipError_t solve_launch(int64_t n, int64_t b, int64_t a, const double* LD, const
                          stream, p, i, nb);
       if (hipError_t e = ok()) return e;
     }
-    hipLaunchKernelGGL(solve_bwd_diag_kernel, dim3((unsigned)nrhs), dim3(NT), 0, stream, p, i, ns);
+    hipLaunchKernelGGL(solve_bwd_diag_kernel, dim3((unsigned)nrhs), dim3(NT), zbytes, stream, p, i, ns, in_lds);
     if (hipError_t e = ok()) return e;
   }
   hipLaunchKernelGGL(solve_scatter_kernel, dim3(gN, (unsigned)nrhs), dim3(256), 0, stream, rhs, nrhs, p.N, p.vec);
