@@ -35,8 +35,9 @@ def parse():
     ap.add_argument("--b", type=int, default=2048)
     ap.add_argument("--a", type=int, default=8)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=["custom", "large", "batched", "autograd"], default="custom",
+    ap.add_argument("--workload", choices=["custom", "large", "arrow", "batched", "autograd"], default="custom",
                     help="large: the n=256, b=4096, a=16 workload (diagonal of L_ii in [1,3]); "
+                         "arrow: the wide-arrowhead workload n=512, b=1024, a=256; "
                          "batched: 64 matrices, n in [16,96], b in {128,256,384}, a in {2,4,6}, one batched "
                          "factorization + selected inversion per step (graph-replayed); "
                          "autograd: f = logdet Q + y^T Q^-1 y at n=256, b=512, a=4, forward + backward per step; "
@@ -239,8 +240,8 @@ def main():
         print(json.dumps(run(args, torch, bta, synth, L)), flush=True)
         return
 
-    if args.workload == "large":
-        wl = synth.LARGE
+    if args.workload in ("large", "arrow"):
+        wl = synth.LARGE if args.workload == "large" else synth.ARROW
         n, b, a, reading = wl.n, wl.b, wl.a, wl.reading
     else:
         n, b, a = args.n, args.b, args.a

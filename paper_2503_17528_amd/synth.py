@@ -97,6 +97,8 @@ SMALL = workload(16, 64, 4, "literal", name="bta_n16_b64_a4")
 BENCH = workload(128, 2048, 8, "scaled", name="bta_n128_b2048_a8")
 AUTOGRAD = workload(256, 512, 4, "literal", name="bta_n256_b512_a4")
 LARGE = workload(256, 4096, 16, "scaled", diag=(1.0, 3.0), name="bta_n256_b4096_a16")
+# wide arrowhead, the shape of the paper's synthetic scaling set (b = 1024, a = 256, largest n)
+ARROW = workload(512, 1024, 256, "scaled", name="bta_n512_b1024_a256")
 
 
 def batched_workloads(seed: int, count: int = 64) -> list:

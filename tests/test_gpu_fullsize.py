@@ -103,7 +103,7 @@ def _exact_columns(torch, Lgen, X, n, b, a, cols):
     return worst
 
 
-@pytest.mark.parametrize("wl", [synth.BENCH, synth.AUTOGRAD], ids=lambda w: w.name)
+@pytest.mark.parametrize("wl", [synth.BENCH, synth.AUTOGRAD, synth.ARROW], ids=lambda w: w.name)
 def test_fullsize_factor_selinv(torch_cuda, wl):
     from paper_2503_17528_amd import bta
 

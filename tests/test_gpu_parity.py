@@ -17,6 +17,8 @@ pytestmark = pytest.mark.gpu
 SHAPES = [
     (1, 3, 0), (1, 64, 4), (2, 5, 1), (3, 64, 0), (4, 100, 3), (2, 130, 70),
     (16, 64, 4), (5, 192, 6), (3, 257, 2), (6, 128, 0), (2, 64, 64), (1, 200, 17),
+    # arrow tip wider than the diagonal blocks (the paper's b = 1024, a = 256 ratio and beyond)
+    (4, 128, 256), (3, 96, 257),
 ]
 
 
@@ -92,7 +94,7 @@ def test_selinv_gemm_kernels(torch_cuda, n, b, a, mode):
     _check(Lg, Xg, F, Xo, n, b, a)
 
 
-@pytest.mark.parametrize("n,b,a", [(4, 100, 3), (3, 64, 0), (2, 130, 70)])
+@pytest.mark.parametrize("n,b,a", [(4, 100, 3), (3, 64, 0), (2, 130, 70), (3, 128, 256)])
 def test_inplace_matches(torch_cuda, n, b, a):
     say(f"case in-place n={n} b={b} a={a}")
     Q = synth.make_np(synth.workload(n, b, a), 8)
@@ -147,7 +149,8 @@ def test_not_positive_definite_reports_row(torch_cuda, where):
     assert ei.value.row == F["info"]
 
 
-@pytest.mark.parametrize("n,b,a,nrhs", [(1, 3, 0, 1), (4, 100, 3, 1), (3, 64, 0, 2), (2, 130, 70, 3), (16, 64, 4, 1)])
+@pytest.mark.parametrize("n,b,a,nrhs", [(1, 3, 0, 1), (4, 100, 3, 1), (3, 64, 0, 2), (2, 130, 70, 3), (16, 64, 4, 1),
+                                            (4, 128, 256, 2)])
 def test_solve_and_logdet(torch_cuda, n, b, a, nrhs):
     from paper_2503_17528_amd import bta
 

@@ -35,12 +35,12 @@ def test_factor_schedule_is_topological_and_in_bounds(L, n, b, a):
     assert sum(counts) == n * T * (T + 1) // 2 + (n - 1) * T * T + n * T * TA + n * TA * (TA + 1) // 2 + TA * (TA + 1) // 2
 
 
-@pytest.mark.parametrize("n,b,a", [(128, 2048, 8), (256, 512, 4), (16, 64, 4), (96, 384, 6)])
+@pytest.mark.parametrize("n,b,a", [(128, 2048, 8), (256, 512, 4), (16, 64, 4), (96, 384, 6), (512, 1024, 256), (3, 128, 256)])
 def test_factor_schedule_workload_sizes(L, n, b, a):
     assert L.bta_internal_factor_schedule_check(n, b, a, None) == 0
 
 
-@pytest.mark.parametrize("n,b,a", SHAPES + [(128, 2048, 8), (256, 4096, 16), (256, 512, 4), (33, 384, 6)])
+@pytest.mark.parametrize("n,b,a", SHAPES + [(128, 2048, 8), (256, 4096, 16), (256, 512, 4), (33, 384, 6), (512, 1024, 256), (3, 128, 257)])
 def test_selinv_launch_windows_in_bounds(L, n, b, a):
     assert L.bta_internal_selinv_dry_check(n, b, a) == 0
 

@@ -138,7 +138,8 @@ def test_exact_rational_example():
 
 
 @pytest.mark.parametrize("wl", [synth.SMALL, synth.workload(6, 40, 3), synth.workload(3, 96, 0),
-                                synth.workload(4, 128, 6, "scaled", diag=(1, 3))], ids=lambda w: w.name)
+                                synth.workload(4, 128, 6, "scaled", diag=(1, 3)),
+                                synth.workload(4, 32, 128, "scaled")], ids=lambda w: w.name)
 def test_recovers_known_factor(wl):
     Q = synth.make_np(wl, 11, with_factor=True)
     F = oracle.pobtaf(Q["D"], Q["B"], Q["R"], Q["T"])
@@ -150,7 +151,8 @@ def test_recovers_known_factor(wl):
     assert abs(oracle.logdet(F["LD"], F["LT"]) - ld) < 1e-12 * abs(ld)
 
 
-@pytest.mark.parametrize("wl", [synth.SMALL, synth.workload(5, 64, 0), synth.workload(8, 48, 5)], ids=lambda w: w.name)
+@pytest.mark.parametrize("wl", [synth.SMALL, synth.workload(5, 64, 0), synth.workload(8, 48, 5),
+                                synth.workload(4, 32, 128, "scaled")], ids=lambda w: w.name)
 def test_sigma_times_q_pattern_identities(wl):
     """(Sigma Q)_jj = I, (Sigma Q)_{n,j} = 0, (Sigma Q)_nn = I use only selected
     blocks of Sigma, so they check X at any size."""
