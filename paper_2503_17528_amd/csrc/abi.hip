@@ -274,7 +274,7 @@ size_t bta_batched_workspace_bytes(int op, int count, const bta_desc* descs) {
     if (!dims_ok(descs[m].n, descs[m].b, descs[m].a)) return 0;
   std::vector<int64_t> n, b, a;
   batch_sizes(count, descs, n, b, a);
-  if (op == BTA_OP_FACTOR) return bta::factor_batch_plan(count, n.data(), b.data(), a.data()).bytes;
+  if (op == BTA_OP_FACTOR) return bta::factor_batch_plan(count, n.data(), b.data(), a.data(), 0).bytes;
   if (op == BTA_OP_SELINV) return bta::selinv_batch_bytes(count, n.data(), b.data(), a.data());
   return 0;
 }
@@ -284,10 +284,10 @@ int bta_factor_batched(int count, const bta_desc* descs, void* work, size_t work
   if (st) return st;
   std::vector<int64_t> n, b, a;
   batch_sizes(count, descs, n, b, a);
-  const bta::FactorBatchPlan bp = bta::factor_batch_plan(count, n.data(), b.data(), a.data());
-  st = check_work(work, work_bytes, bp.bytes);
-  if (st) return st;
   st = device_ok();
+  if (st) return st;
+  const bta::FactorBatchPlan bp = bta::factor_batch_plan(count, n.data(), b.data(), a.data(), bta::device_cu_count());
+  st = check_work(work, work_bytes, bp.bytes);
   if (st) return st;
   const std::vector<bta::BatchMatrix> mats = batch_mats(count, descs);
   hipError_t e = bta::factor_batch_launch(bp, mats.data(), work, reinterpret_cast<hipStream_t>(stream), bta::device_cu_count());

@@ -45,7 +45,7 @@ struct FactorBatchPlan {
   long long nflags = 0, ntasks = 0, nseg = 0;
   size_t off_ctl = 0, off_mats = 0, off_segs = 0, off_flags = 0, bytes = 0;
 };
-FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b, const int64_t* a);
+FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b, const int64_t* a, int num_cus);
 hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mats, void* work, hipStream_t stream,
                                int num_cus);
 

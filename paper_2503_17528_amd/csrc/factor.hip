@@ -50,7 +50,8 @@ enum : int { T_DIAG = 0, T_OFFD = 1, T_SUB = 2, T_ARW = 3, T_TUPD = 4, T_TIPD = 
 
 // The chain-workgroup schedule is switched off: its first GPU run (n = 1,
 // b = 3, a = 0) did not complete, and no cause has been established yet.
-// With it off, every diagonal tile runs as one DIAG task.
+// With it off, every diagonal tile runs as one DIAG task and the chain code
+// is compiled out of the kernels.
 constexpr bool kFactorChain = false;
 
 struct FactorParams {
@@ -409,6 +410,68 @@ __device__ __forceinline__ void diag_partials(const FactorParams& p, const Task&
   __syncthreads();
 }
 
+// Four consecutive k of LDS row `row`, from k group kg (the k permutation of mma_tile).
+__device__ __forceinline__ d4 lds_k4(const double* S, int row, int kg, int kl) {
+  const double* q = S + row * LDS_LD + kg * 16 + kl;
+  const d2v lo = *reinterpret_cast<const d2v*>(q);
+  const d2v hi = *reinterpret_cast<const d2v*>(q + 2);
+  return d4{lo[0], lo[1], hi[0], hi[1]};
+}
+
+// x = As Bs^T with Bs lower triangular (the inverse W of a diagonal tile), so
+// that 16-column block J of x only takes the k groups K <= J.  Wave w holds
+// rows 32*(w&1) .. +32 and the column blocks {J0, J1} = {0, 3} or {1, 2}:
+// ten of the sixteen k groups per wave instead of sixteen.
+template <int J0, int J1>
+__device__ __forceinline__ void mma_lower_rhs(d4 (&x)[2][2], const double* As, const double* Bs, int rb, int lane) {
+  const int m = lane & 15, kl = (lane >> 4) * 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) x[i][0] = x[i][1] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kg = 0; kg <= J1; ++kg) {
+    d4 a[2], b0 = d4{0.0, 0.0, 0.0, 0.0}, b1;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = lds_k4(As, 16 * (rb + i) + m, kg, kl);
+    if (kg <= J0) b0 = lds_k4(Bs, 16 * J0 + m, kg, kl);
+    b1 = lds_k4(Bs, 16 * J1 + m, kg, kl);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (kg <= J0) x[i][0] = mfma16(a[i][q], b0[q], x[i][0]);
+        x[i][1] = mfma16(a[i][q], b1[q], x[i][1]);
+      }
+  }
+}
+
+// S(I,J) -= X(I,:) X(J,:)^T for one 16-block of the lower triangle (the part
+// the Cholesky reads).
+template <int I, int J>
+__device__ __forceinline__ void syrk_block(double* S, const double* X, int lane) {
+  const int m = lane & 15, kl = (lane >> 4) * 4;
+  d4 t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kg = 0; kg < 4; ++kg) {
+    const d4 a = lds_k4(X, 16 * I + m, kg, kl);
+    const d4 b = lds_k4(X, 16 * J + m, kg, kl);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t = mfma16(a[q], b[q], t);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) S[(16 * I + acc_row(lane, j)) * LDS_LD + 16 * J + acc_col(lane)] -= t[j];
+}
+
+// The ten lower 16-blocks over the four waves: three, three, two and two.
+__device__ __forceinline__ void syrk_lower(double* S, const double* X, int tid) {
+  const int lane = tid & 63;
+  switch (tid >> 6) {
+    case 0: syrk_block<0, 0>(S, X, lane); syrk_block<1, 0>(S, X, lane); syrk_block<3, 3>(S, X, lane); break;
+    case 1: syrk_block<1, 1>(S, X, lane); syrk_block<2, 0>(S, X, lane); syrk_block<3, 2>(S, X, lane); break;
+    case 2: syrk_block<2, 1>(S, X, lane); syrk_block<2, 2>(S, X, lane); break;
+    default: syrk_block<3, 0>(S, X, lane); syrk_block<3, 1>(S, X, lane); break;
+  }
+}
+
 // The rest of diagonal tile g = (i, c) from its partial sums: L(g,g-1) =
 // -acc2 W(g-1)^T is stored and published, acc1 += L(g,g-1) L(g,g-1)^T, and the
 // diagonal tile is factored and inverted (L and W stored, flag published).
@@ -457,19 +520,32 @@ __device__ __forceinline__ void diag_finish(const FactorParams& p, int i, int c,
       acc_to_lds(acc2, sh.u.f.As, tid);
     }
     __syncthreads();
-    Acc x;  // -L(g,g-1)
-    acc_zero(x);
-    mma_tile(x, sh.u.f.As, sh.u.f.Bs, tid);
-    acc_store_dev(x, pout, b, prows, pcols, -1.0, tid);
-    __syncthreads();
-    acc_to_lds(x, sh.u.f.As, tid);
-    __syncthreads();
-    mma_tile(acc1, sh.u.f.As, sh.u.f.As, tid);  // + L(g,g-1) L(g,g-1)^T = x x^T
-    publish(pflag, tid);
-    if (rec && tid == 0) rec[1] = __builtin_amdgcn_s_memrealtime();
+    // x = -L(g,g-1) = acc2 W(g-1)^T, W lower triangular
+    const int w = tid >> 6, lane = tid & 63, rb = 2 * (w & 1);
+    d4 x[2][2];
+    if (w < 2) mma_lower_rhs<0, 3>(x, sh.u.f.As, sh.u.f.Bs, rb, lane);
+    else mma_lower_rhs<1, 2>(x, sh.u.f.As, sh.u.f.Bs, rb, lane);
+    const int jb0 = w < 2 ? 0 : 1, jb1 = w < 2 ? 3 : 2;
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = 16 * (rb + ii) + acc_row(lane, j), q = 16 * (jj ? jb1 : jb0) + acc_col(lane);
+          if (r < prows && q < pcols) st_dev(pout + (int64_t)r * b + q, -x[ii][jj][j]);
+        }
+    __syncthreads();  // As and Bs are read
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          sh.u.f.Bs[(16 * (rb + ii) + acc_row(lane, j)) * LDS_LD + 16 * (jj ? jb1 : jb0) + acc_col(lane)] = x[ii][jj][j];
   }
 
-  // factor and invert A(g,g) - sum over all k < g (acc1 holds its negative)
+  // A(g,g) - sum over k < g-1 (acc1 holds its negative) into As
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -477,6 +553,15 @@ __device__ __forceinline__ void diag_finish(const FactorParams& p, int i, int c,
 #pragma unroll
       for (int j = 0; j < 4; ++j) sh.u.f.As[tile_row(tid, bi, j) * LDS_LD + tile_col(tid, bj)] = -acc1.v[bi][bj][j];
   __syncthreads();
+  if (has_pre) {
+    // minus L(g,g-1) L(g,g-1)^T = x x^T on the lower triangle, then publish L(g,g-1)
+    // (its barrier also orders these LDS updates before the factorization)
+    syrk_lower(sh.u.f.As, sh.u.f.Bs, tid);
+    publish(pflag, tid);
+    if (rec && tid == 0) rec[1] = __builtin_amdgcn_s_memrealtime();
+  }
+
+  // factor and invert A(g,g) - sum over all k < g
   const int f = uni(chol_inv_tile_mfma<2>(sh.u.f.As, sh.u.f.Bs, sh.rinv, sh.pan, &sh.fail, tid));
   if (rec && tid == 0) rec[2] = __builtin_amdgcn_s_memrealtime();
   if (f != 0 && f <= rows && tid == 0) {
@@ -568,7 +653,7 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
     if (p.trace && tid == 0) tr0 = __builtin_amdgcn_s_memrealtime();
     if (t.type == T_DIAG) {
       unsigned long long* rec = p.trace ? p.trace + 8 * tk : nullptr;
-      if (p.chain) run_part(p, t, sh, tid, tr1, rec);
+      if (kFactorChain && p.chain) run_part(p, t, sh, tid, tr1, rec);
       else run_diag(p, t, sh, tid, tr1, rec);
       if (rec && tid == 0) {
         rec[0] = tr0;
@@ -760,7 +845,7 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
 // Persistent workers: take tickets until the task list is exhausted.
 __device__ __forceinline__ void factor_worker(const FactorParams& p, Shared& sh) {
   const int tid = threadIdx.x;
-  if (p.chain && blockIdx.x == 0) {
+  if (kFactorChain && p.chain && blockIdx.x == 0) {
     chain_run(p, sh, tid);
     return;
   }
@@ -929,31 +1014,78 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
 }
 
 // ---------------------------------------------------------------------------
-// Step-major interleaving of the matrices of a batch: segment (step s, matrix m)
-// holds the tasks of block step s of matrix m; the last step also carries the
-// tip tasks.  *total receives the number of tickets.
+// Band-column interleaving of the matrices of a batch.  Segment (m, i, c)
+// holds the tasks of band column c of block step i of matrix m (the step's
+// tip updates go with its last column, the final tip tasks with the last
+// column of the last step).  Segments are ordered by the column's position on
+// its matrix's chain of diagonal tiles, i*T_m + c, so that each matrix's
+// columns are dispatched at the pace of its own chain rather than in lockstep
+// with wider matrices; equal positions go longest chain first.  Per matrix the
+// local ticket order is kept.  *total receives the number of tickets.
 static std::vector<BatchSeg> batch_segments(const FactorBatchPlan& bp, const int64_t* n, long long* total) {
-  std::vector<BatchSeg> segs;
-  segs.reserve((size_t)bp.nseg);
-  int64_t maxn = 0;
-  for (int m = 0; m < bp.count; ++m) maxn = std::max<int64_t>(maxn, n[m]);
-  long long t = 0;
-  for (int64_t st = 0; st < maxn; ++st) {
-    for (int m = 0; m < bp.count; ++m) {
-      if (st >= n[m]) continue;
-      const FactorPlan& fp = bp.plans[m];
-      const long long local0 = st * fp.step_full;
-      const long long len = (st < n[m] - 1) ? fp.step_full : fp.ntasks - local0;
-      segs.push_back(BatchSeg{t, local0, m, 0});
-      t += len;
+  struct Col {
+    long long key, chain, local0, len;
+    int m;
+  };
+  std::vector<Col> cols;
+  cols.reserve((size_t)bp.nseg);
+  for (int m = 0; m < bp.count; ++m) {
+    const FactorPlan& fp = bp.plans[m];
+    const int T = fp.T, TA = fp.TA, L = fp.look;
+    long long local = 0;
+    for (int64_t i = 0; i < n[m]; ++i) {
+      const bool has_sub = i < n[m] - 1;
+      for (int c = 0; c < T; ++c) {
+        // the column group of decode(): DIAG tasks, OFFD, SUB and ARW rows
+        const int ndg = (c == 0) ? L + 1 : ((c + L <= T - 1) ? 1 : 0);
+        const int no = (c <= T - 2) ? T - c - 2 : 0;
+        const int ns = has_sub ? (c == T - 1 ? T - 1 : T) : 0;
+        long long len = ndg + no + ns + TA;
+        if (c == T - 1) {
+          len += (long long)TA * (TA + 1) / 2;               // the step's tip updates
+          if (!has_sub) len += (long long)TA * (TA + 1) / 2;  // the tip itself
+        }
+        if (len > 0) cols.push_back(Col{i * T + c, n[m] * (long long)T, local, len, m});  // no segment for an empty column
+        local += len;
+      }
     }
+  }
+  std::stable_sort(cols.begin(), cols.end(), [](const Col& x, const Col& y) {
+    if (x.key != y.key) return x.key < y.key;
+    if (x.chain != y.chain) return x.chain > y.chain;
+    return x.m < y.m;
+  });
+  std::vector<BatchSeg> segs;
+  segs.reserve(cols.size());
+  long long t = 0;
+  for (const Col& c : cols) {
+    segs.push_back(BatchSeg{t, c.local0, c.m, 0});
+    t += c.len;
   }
   *total = t;
   return segs;
 }
 
-// Batched host plan.
-FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b, const int64_t* a) {
+// Bound on the batch's dispatched tasks that wait on a larger ticket.  Only
+// DIAG tasks dispatched ahead of their column do: DIAG(d), dispatched with
+// column d - L, waits on tasks of columns up to d - 2 of its step, so between
+// two segments of its matrix at most max(0, L - 2) of them are pending, and
+// inside the segment being dispatched at most L + 1 (none without lookahead).
+static long long batch_ahead_bound(const std::vector<FactorPlan>& plans, int cap) {
+  long long s = 0;
+  int inside = 0;
+  for (const FactorPlan& fp : plans) {
+    const int L = std::min(fp.look, cap);
+    s += std::max(0, L - 2);
+    if (L > 0) inside = std::max(inside, L + 1);
+  }
+  return s + inside;
+}
+static long long batch_ahead_bound(const FactorBatchPlan& bp) { return batch_ahead_bound(bp.plans, 1 << 30); }
+
+// Batched host plan.  num_cus (0: not known) caps the DIAG lookahead so that
+// the whole batch's forward waits stay below the number of workgroups.
+FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b, const int64_t* a, int num_cus) {
   FactorBatchPlan bp;
   bp.count = count;
   bp.plans.resize(count);
@@ -961,9 +1093,9 @@ FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b,
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
   bp.off_ctl = take(64);
   bp.off_mats = take(sizeof(FactorParams) * (size_t)count);
-  // segments: one per (step, matrix) with n_m > step
-  int64_t maxn = 0, nseg = 0;
-  for (int m = 0; m < count; ++m) { maxn = std::max<int64_t>(maxn, n[m]); nseg += n[m]; }
+  // segments: at most one per band column of every matrix
+  int64_t nseg = 0;
+  for (int m = 0; m < count; ++m) nseg += n[m] * ((b[m] + 63) / 64);
   bp.nseg = nseg;
   bp.off_segs = take(sizeof(BatchSeg) * (size_t)nseg);
   long long nflags = 0;
@@ -985,6 +1117,12 @@ FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b,
   long long t = 0;
   for (int m = 0; m < count; ++m) t += bp.plans[m].ntasks;
   bp.ntasks = t;
+  if (num_cus > 0 && num_cus < t) {
+    // the largest common lookahead cap that keeps the forward waits below the grid
+    int cap = FACTOR_LOOKAHEAD;
+    while (cap > 0 && batch_ahead_bound(bp.plans, cap) > num_cus - 1) --cap;
+    for (int m = 0; m < count; ++m) bp.plans[m].look = std::min(bp.plans[m].look, cap);
+  }
   return bp;
 }
 
@@ -1037,9 +1175,7 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
   args.ntasks = t;
   args.ctl = ctl;
   const long long grid = std::min<long long>(t, (long long)num_cus);
-  int look = 0;
-  for (int m = 0; m < bp.count; ++m) look = std::max(look, bp.plans[m].look);
-  if (grid < t && grid <= look + 1) return hipErrorInvalidConfiguration;  // lookahead needs more workers
+  if (grid < t && grid <= batch_ahead_bound(bp)) return hipErrorInvalidConfiguration;  // lookahead needs more workers
   timing_mark(KT_FACTOR, true, stream);
   hipLaunchKernelGGL(factor_batched_kernel, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, args);
   timing_mark(KT_FACTOR, false, stream);
@@ -1056,8 +1192,12 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
 // inside its array.  counts[] receives the number of tiles of each kind (a
 // DIAG task also produces the tile left of its diagonal tile, counted under
 // OFFD or SUB).  Returns 0 when the schedule is valid, else an error code.
-int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* [7] or null */) {
-  const FactorPlan fp = factor_plan(n, b, a);
+// `look` is the DIAG lookahead to replay (the plan's own when negative);
+// maxdep_out (optional) receives, per ticket, the largest ticket it waits on.
+int factor_schedule_replay(int64_t n, int64_t b, int64_t a, int look, long long* counts /* [7] or null */,
+                           std::vector<long long>* maxdep_out) {
+  FactorPlan fp = factor_plan(n, b, a);
+  if (look >= 0) fp.look = std::min<int>(look, fp.T - 1);
   FactorParams p{};
   p.n = (int)n; p.b = (int)b; p.a = (int)a; p.T = fp.T; p.TA = fp.TA;
   const uintptr_t G = uintptr_t(1) << 40;
@@ -1184,6 +1324,7 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
     ahead_max = std::max<long long>(ahead_max, (long long)open.size());
   }
   if (ahead_max > fp.look + 1) return 11;
+  if (maxdep_out) *maxdep_out = std::move(maxdep);
   const long long T = fp.T, TA = fp.TA;
   const long long expect[7] = {n * T, n * T * (T - 1) / 2, (n - 1) * T * T, n * T * TA, n * TA * (TA + 1) / 2, TA,
                                TA * (TA - 1) / 2};
@@ -1192,6 +1333,10 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
     if (cnt[k] != expect[k]) return 9;
   }
   return 0;
+}
+
+int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* [7] or null */) {
+  return factor_schedule_replay(n, b, a, -1, counts, nullptr);
 }
 
 }  // namespace bta
@@ -1228,16 +1373,33 @@ extern "C" __attribute__((visibility("default"))) int bta_internal_factor_traced
              : 1;
 }
 
-// Host check of the batch interleaving: every ticket maps (by the kernel's
-// binary search) to a matrix and a local ticket; per matrix the local tickets
-// come out as 0, 1, 2, ... ntasks-1 exactly once, in order.
+// Host check of the batch interleaving for a launch with `num_cus` workgroups:
+// every ticket maps (by the kernel's binary search) to a matrix and a local
+// ticket, per matrix the local tickets come out as 0, 1, ... ntasks-1 in
+// order, every segment holds exactly the tasks of its band column, and a
+// replay of the whole dispatch order with every matrix's dependencies never
+// has more dispatched tasks waiting on a larger ticket than the launch's bound
+// (itself below the number of workgroups).  *ahead (optional) receives the
+// replay's maximum.  Returns 0 or an error code.
 extern "C" __attribute__((visibility("default"))) int bta_internal_factor_batch_check(int count, const int64_t* n,
-                                                                                       const int64_t* b, const int64_t* a) {
-  const bta::FactorBatchPlan bp = bta::factor_batch_plan(count, n, b, a);
+                                                                                       const int64_t* b, const int64_t* a,
+                                                                                       int num_cus, long long* ahead) {
+  const bta::FactorBatchPlan bp = bta::factor_batch_plan(count, n, b, a, num_cus);
   long long total = 0;
   const std::vector<bta::BatchSeg> segs = bta::batch_segments(bp, n, &total);
-  if (total != bp.ntasks) return 1;
+  if (total != bp.ntasks || (long long)segs.size() > bp.nseg) return 1;
+  std::vector<std::vector<long long>> maxdep(count), global(count);
+  std::vector<bta::FactorParams> ps(count);
+  for (int m = 0; m < count; ++m) {
+    if (bta::factor_schedule_replay(n[m], b[m], a[m], bp.plans[m].look, nullptr, &maxdep[m]) != 0) return 5;
+    global[m].assign((size_t)bp.plans[m].ntasks, -1);
+    bta::FactorParams& p = ps[m];
+    p.n = (int)n[m]; p.b = (int)b[m]; p.a = (int)a[m]; p.T = bp.plans[m].T; p.TA = bp.plans[m].TA;
+    p.ntasks = bp.plans[m].ntasks; p.step_full = bp.plans[m].step_full; p.step_last = bp.plans[m].step_last;
+    p.look = bp.plans[m].look;
+  }
   std::vector<long long> next(count, 0);
+  std::vector<int> seg_of(total > 0 ? (size_t)total : 1);
   for (long long tk = 0; tk < total; ++tk) {
     int lo = 0, hi = (int)segs.size() - 1;
     while (lo < hi) {
@@ -1248,9 +1410,51 @@ extern "C" __attribute__((visibility("default"))) int bta_internal_factor_batch_
     const long long local = segs[lo].local0 + (tk - segs[lo].t0);
     if (m < 0 || m >= count || local != next[m]) return 2;
     ++next[m];
+    global[m][(size_t)local] = tk;
+    seg_of[(size_t)tk] = lo;
   }
   for (int m = 0; m < count; ++m)
     if (next[m] != bp.plans[m].ntasks) return 3;
+  // segment contents: the column a task is dispatched with (DIAG tasks L
+  // columns early, tip work with the last column) is the segment's column
+  {
+    std::vector<long long> first_key(count, -1);
+    for (size_t q = 0; q < segs.size(); ++q) {
+      const long long len = (q + 1 < segs.size() ? segs[q + 1].t0 : total) - segs[q].t0;
+      const int m = segs[q].mat;
+      const bta::FactorParams& p = ps[m];
+      long long key = -1;
+      for (long long e = 0; e < len; ++e) {
+        const bta::Task t = bta::decode(p, segs[q].local0 + e);
+        long long k;
+        if (t.type == bta::T_TIPD || t.type == bta::T_TIPO) k = (long long)(p.n - 1) * p.T + p.T - 1;
+        else if (t.type == bta::T_TUPD) k = (long long)t.i * p.T + p.T - 1;
+        else if (t.type == bta::T_DIAG) k = (long long)t.i * p.T + (t.c <= p.look ? 0 : t.c - p.look);
+        else k = (long long)t.i * p.T + t.c;
+        if (key < 0) key = k;
+        if (k != key) return 4;
+      }
+      if (key <= first_key[m]) return 4;  // columns of a matrix in order, each once
+      first_key[m] = key;
+    }
+  }
+  // replay: dispatched tasks that wait on a larger ticket
+  long long amax = 0;
+  std::vector<long long> open;
+  for (long long tk = 0; tk < total; ++tk) {
+    const bta::BatchSeg& sg = segs[(size_t)seg_of[(size_t)tk]];
+    const long long local = sg.local0 + (tk - sg.t0);
+    const long long md = maxdep[sg.mat][(size_t)local];
+    if (md >= 0) {
+      const long long g = global[sg.mat][(size_t)md];
+      if (g > tk) open.push_back(g);
+    }
+    open.erase(std::remove_if(open.begin(), open.end(), [&](long long x) { return x <= tk; }), open.end());
+    amax = std::max<long long>(amax, (long long)open.size());
+  }
+  if (ahead) *ahead = amax;
+  if (amax > bta::batch_ahead_bound(bp)) return 6;
+  if (num_cus > 0 && std::min<long long>(total, num_cus) < total && bta::batch_ahead_bound(bp) >= num_cus) return 7;
   return 0;
 }
 

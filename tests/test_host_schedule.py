@@ -46,18 +46,31 @@ def test_selinv_launch_windows_in_bounds(L, n, b, a):
 
 
 def test_batched_factor_interleaving(L):
+    """The batch's band-column ticket order: every ticket maps to its matrix in
+    local order, every segment holds one band column, and a replay with every
+    matrix's dependencies stays within the launch's bound on forward waits."""
     from paper_2503_17528_amd import synth
 
-    L.bta_internal_factor_batch_check.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 3
+    L.bta_internal_factor_batch_check.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 3 + [ctypes.c_int, ctypes.c_void_p]
+    arr = lambda xs: (ctypes.c_int64 * len(xs))(*xs)
+    ahead = ctypes.c_longlong(-1)
     for seed in range(3):
         wls = synth.batched_workloads(seed)
-        arr = lambda xs: (ctypes.c_int64 * len(xs))(*xs)
         n = arr([w.n for w in wls]); b = arr([w.b for w in wls]); a = arr([w.a for w in wls])
-        assert L.bta_internal_factor_batch_check(len(wls), n, b, a) == 0
-    mixed = [(1, 5, 0), (3, 64, 2), (2, 130, 70), (5, 1, 1), (4, 200, 0)]
-    arr = lambda xs: (ctypes.c_int64 * len(xs))(*xs)
-    assert L.bta_internal_factor_batch_check(len(mixed), arr([m[0] for m in mixed]), arr([m[1] for m in mixed]),
-                                             arr([m[2] for m in mixed])) == 0
+        for cus in (256, 64, 8):
+            assert L.bta_internal_factor_batch_check(len(wls), n, b, a, cus, ctypes.byref(ahead)) == 0, (seed, cus)
+            assert 0 <= ahead.value < cus
+    mixed = [(1, 5, 0), (3, 64, 2), (2, 130, 70), (5, 1, 1), (4, 200, 0), (6, 520, 3), (2, 600, 130)]
+    for cus in (256, 32, 4, 2):
+        assert L.bta_internal_factor_batch_check(len(mixed), arr([m[0] for m in mixed]), arr([m[1] for m in mixed]),
+                                                 arr([m[2] for m in mixed]), cus, ctypes.byref(ahead)) == 0, cus
+    # one matrix: the single-matrix lookahead is kept, and it does wait ahead
+    one = [(8, 1024, 8)]
+    assert L.bta_internal_factor_batch_check(1, arr([8]), arr([1024]), arr([8]), 256, ctypes.byref(ahead)) == 0
+    assert ahead.value > 0
+    # no lookahead (many matrices per workgroup): nothing waits ahead
+    assert L.bta_internal_factor_batch_check(1, arr([8]), arr([1024]), arr([8]), 1, ctypes.byref(ahead)) == 0
+    assert ahead.value == 0
 
 
 def test_batched_selinv_merge_is_independent(L):
@@ -85,3 +98,23 @@ def test_factor_schedule_other_lookaheads(L, look):
             assert L.bta_internal_factor_schedule_check(n, b, a, None) == 0, (look, n, b, a)
     finally:
         L.bta_internal_factor_lookahead(prev)
+
+
+def test_batched_factor_interleaving_random_batches(L):
+    """Random batches (ragged tiles, T = 1, a = 0, arrow tips wider than the
+    blocks) on several grids: the replayed forward waits never exceed the
+    launch's bound, which stays below the number of workgroups."""
+    import random
+
+    L.bta_internal_factor_batch_check.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 3 + [ctypes.c_int, ctypes.c_void_p]
+    arr = lambda xs: (ctypes.c_int64 * len(xs))(*xs)
+    ahead = ctypes.c_longlong(-1)
+    rng = random.Random(1)
+    for _ in range(60):
+        cnt = rng.randint(1, 40)
+        ms = [(rng.randint(1, 12), rng.choice([1, 5, 64, 65, 128, 200, 300, 520, 700]), rng.choice([0, 1, 4, 64, 70, 130]))
+              for _ in range(cnt)]
+        cus = rng.choice([2, 4, 16, 64, 256])
+        rc = L.bta_internal_factor_batch_check(cnt, arr([m[0] for m in ms]), arr([m[1] for m in ms]),
+                                               arr([m[2] for m in ms]), cus, ctypes.byref(ahead))
+        assert rc == 0, (rc, cus, ms)
