@@ -64,8 +64,7 @@ def test_batched_factor_interleaving(L):
     for cus in (256, 32, 4, 2):
         assert L.bta_internal_factor_batch_check(len(mixed), arr([m[0] for m in mixed]), arr([m[1] for m in mixed]),
                                                  arr([m[2] for m in mixed]), cus, ctypes.byref(ahead)) == 0, cus
-    # one matrix: the single-matrix lookahead is kept, and it does wait ahead
-    one = [(8, 1024, 8)]
+    # one matrix with lookahead: its DIAG tasks do wait ahead
     assert L.bta_internal_factor_batch_check(1, arr([8]), arr([1024]), arr([8]), 256, ctypes.byref(ahead)) == 0
     assert ahead.value > 0
     # no lookahead (many matrices per workgroup): nothing waits ahead
