@@ -225,15 +225,26 @@ __device__ void rowdot_acc(const double* M, int64_t ld, int R, int64_t K, const 
   double s[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) s[j] = 0.0;
-  // branchless: rows past R read row R-1 and contribute zero (a per-row branch
-  // would make the compiler wait for each load before the next)
-  for (int64_t k = lane; k < K; k += 64) {
-    const double xk = x[k];
+  // branchless: rows past R read row R-1 and columns past K column 0, and
+  // contribute zero (a per-row branch would make the compiler wait for each
+  // load before the next); two 64-wide k chunks per trip, so that 32 loads per
+  // lane are in flight
+  for (int64_t k0 = 0; k0 < K; k0 += 128) {
+    const int64_t k1 = k0 + lane, k2 = k0 + 64 + lane;
+    const bool in1 = k1 < K, in2 = k2 < K;
+    const int64_t ka = in1 ? k1 : 0, kb = in2 ? k2 : 0;
+    const double xa = in1 ? x[ka] : 0.0, xb = in2 ? x[kb] : 0.0;
+    double ma[16], mb[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const int r = w + 4 * j;
-      const double m = M[(int64_t)(r < R ? r : R - 1) * ld + k];
-      s[j] += (r < R ? m : 0.0) * xk;
+      const int64_t row = (int64_t)((w + 4 * j) < R ? (w + 4 * j) : R - 1) * ld;
+      ma[j] = M[row + ka];
+      mb[j] = M[row + kb];
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double t = ma[j] * xa + mb[j] * xb;
+      s[j] += (w + 4 * j < R) ? t : 0.0;
     }
   }
 #pragma unroll
@@ -250,21 +261,23 @@ __device__ void rowdot_acc(const double* M, int64_t ld, int R, int64_t K, const 
 }
 
 // out[k] (k < Kc <= 64) += sign * sum_{r<R} M[r*ld + k] x[r]   (column access).
-// Eight independent partial sums per thread keep eight rows' loads in flight.
+// Sixteen independent partial sums per thread keep sixteen rows' loads in flight.
 __device__ void coldot_acc(const double* M, int64_t ld, int64_t R, int Kc, const double* x, double* out, double* red,
                            double sign, int tid) {
   const int k = tid & 63, ph = tid >> 6;
-  double s[8];
+  double s[16];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) s[u] = 0.0;
+  for (int u = 0; u < 16; ++u) s[u] = 0.0;
   if (k < Kc) {
     int64_t r = ph;
-    for (; r + 28 < R; r += 32) {
+    for (; r + 60 < R; r += 64) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s[u] += M[(r + 4 * u) * ld + k] * x[r + 4 * u];
+      for (int u = 0; u < 16; ++u) s[u] += M[(r + 4 * u) * ld + k] * x[r + 4 * u];
     }
     for (; r < R; r += 4) s[0] += M[r * ld + k] * x[r];
   }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) s[u] += s[u + 8];
   red[ph * 64 + k] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
   __syncthreads();
   if (tid < 64 && tid < Kc) out[tid] += sign * (red[tid] + red[64 + tid] + red[128 + tid] + red[192 + tid]);
@@ -360,7 +373,7 @@ __global__ __launch_bounds__(256) void solve_bwd_couple_kernel(SolveParams p, in
 // Block i forward: z_i = L_ii^{-1} (z_i - sum_s part[s]) (nsplit partials), tile by tile.
 // The block's vector is kept in LDS (dynamic, b doubles, b <= 4096), so the
 // tile chain does not round-trip through global memory.
-__global__ __launch_bounds__(NT) void solve_fwd_diag_kernel(SolveParams p, int64_t i, int nsplit, int in_lds) {
+__global__ __launch_bounds__(NT, 1) void solve_fwd_diag_kernel(SolveParams p, int64_t i, int nsplit, int in_lds) {
   extern __shared__ double zsh[];
   __shared__ double v[64];
   __shared__ double red[256];
@@ -395,7 +408,7 @@ __global__ __launch_bounds__(NT) void solve_fwd_diag_kernel(SolveParams p, int64
 
 // Tip forward: z_n = L_nn^{-1} (z_n - sum_i ptip[i]) (blocks summed in order), then
 // the tip backward x_n = L_nn^{-T} z_n.
-__global__ __launch_bounds__(NT) void solve_tip_kernel(SolveParams p) {
+__global__ __launch_bounds__(NT, 1) void solve_tip_kernel(SolveParams p) {
   __shared__ double v[64];
   __shared__ double red[256];
   __shared__ double red2[256];
