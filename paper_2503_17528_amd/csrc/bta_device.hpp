@@ -567,7 +567,11 @@ __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double*
         if (!ok && fail == 0) fail = k + 1;
         const double ri = rsqrt_refined(d);
         if (r == 0) rinv[k] = ri;
-        const double lv = (r > k) ? s[m] * ri : ((r == k) ? d * ri : 0.0);
+        // rows below the pivot get L(r,k) = s * ri, the pivot row sqrt(d) = d * ri
+        // (its s is d); rows above hold upper-triangle values that no later step
+        // reads (the trailing updates and broadcasts only use rows > k) and that
+        // are written back as zeros
+        const double lv = s[m] * ri;
         s[m] = lv;
         if (BC == 2) {
           // column m+1 (the next pivot) by a cross-lane read; the other columns

@@ -179,20 +179,23 @@ __host__ __device__ __forceinline__ Task decode(const FactorParams& p, long long
 // Tile views of the block arrays.
 __host__ __device__ inline int ext(int total, int t) { int e = total - 64 * t; return e < 64 ? e : 64; }
 
-struct alignas(16) Shared {
-  union {
-    double stage[2][2][PT];  // k loop: pieced operand tiles, double buffered (direct loads)
-    struct {
-      double As[TS * LDS_LD];
-      double Bs[TS * LDS_LD];
-    } f;  // finishing a tile: row-major padded tiles
-  } u;
+struct alignas(256) Shared {
+  // the small arrays first: their LDS addresses fit the 16-bit offset of the
+  // LDS instructions, so the panel loop of the diagonal tiles reads them
+  // without address arithmetic
   double pan[64 * 17];  // diagonal tile factorization workspace
   double rinv[64];
   long long ticket;
   int fail;
   int ok;    // result of wait_ready
   int upto;  // end of the run of final k tiles (k loop)
+  union alignas(256) {
+    double stage[2][2][PT];  // k loop: pieced operand tiles, double buffered (direct loads)
+    struct {
+      double As[TS * LDS_LD];
+      double Bs[TS * LDS_LD];
+    } f;  // finishing a tile: row-major padded tiles
+  } u;
 };
 
 // One k step of a left-looking task: operand tiles and their completion flags.
