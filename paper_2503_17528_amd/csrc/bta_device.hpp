@@ -253,6 +253,19 @@ __device__ __forceinline__ void tile_store_dev(const double* lds, double* out, i
   }
 }
 
+// tile_store_dev of a lower-triangular tile whose LDS image holds stale values
+// above the diagonal: exact zeros are stored there instead.
+__device__ __forceinline__ void tile_store_lower_dev(const double* lds, double* out, int64_t ld, int rows, int tid) {
+  const int c2 = (tid & 31) * 2, r0 = tid >> 5;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int row = 8 * j + r0;
+    if (row < rows && c2 < rows) st_dev(out + (int64_t)row * ld + c2, c2 <= row ? lds[row * LDS_LD + c2] : 0.0);
+    if (row < rows && c2 + 1 < rows)
+      st_dev(out + (int64_t)row * ld + c2 + 1, c2 + 1 <= row ? lds[row * LDS_LD + c2 + 1] : 0.0);
+  }
+}
+
 // acc += A_lds * B_lds^T over one 64-wide k tile: A_lds rows are output rows,
 // B_lds rows are output columns, both k-contiguous with stride LDS_LD.
 // The 16 k values of each MFMA group are permuted so that every lane reads 4
@@ -538,8 +551,9 @@ __device__ __forceinline__ void blk_store(const d4& c, double* X, int ld, int la
 }
 
 // Cholesky factor and inverse of the SPD tile S (64 x 64, LDS row stride
-// LDS_LD; only its lower triangle is read).  On return S holds L (zeros above
-// the diagonal) and Wl holds W = L^{-1} (zeros above the diagonal).  Returns 0,
+// LDS_LD; only its lower triangle is read).  On return the lower triangle of S
+// holds L (the values above it are stale: store it with tile_store_lower_dev)
+// and Wl holds W = L^{-1} (zeros above the diagonal).  Returns 0,
 // or the 1-based column of the first pivot that is not a positive finite
 // number.  Right-looking by 16-column panels: wave p factors panel p alone
 // (lane r holds row r; pivots broadcast across the wave, no barrier), the
@@ -551,8 +565,6 @@ __device__ __forceinline__ void blk_store(const d4& c, double* X, int ld, int la
 template <int BC>
 __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double* rinv, double* tmp, int* fail_sh, int tid) {
   const int r = tid & 63, q = tid >> 6;
-  if (tid == 0) *fail_sh = 0x7fffffff;
-  int fail = 0;
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
     if (q == p) {
@@ -563,8 +575,7 @@ __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double*
       for (int m = 0; m < 16; ++m) {
         const int k = 16 * p + m;
         const double d = rd_lane(s[m], k);
-        const bool ok = (d > 0.0) && (d <= 1.7976931348623157e308);
-        if (!ok && fail == 0) fail = k + 1;
+        // (pivots are checked once after the panels, from rinv)
         const double ri = rsqrt_refined(d);
         if (r == 0) rinv[k] = ri;
         // rows below the pivot get L(r,k) = s * ri, the pivot row sqrt(d) = d * ri
@@ -589,8 +600,10 @@ __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double*
           for (int mm = m + 1; mm < 16; ++mm) s[mm] -= lv * bcast<BC>(lv, 16 * p + mm);
         }
       }
+      // the rows above the diagonal keep stale values: nothing reads them, and
+      // the stores of L write zeros there
 #pragma unroll
-      for (int m = 0; m < 16; ++m) S[r * LDS_LD + 16 * p + m] = (r >= 16 * p + m) ? s[m] : 0.0;
+      for (int m = 0; m < 16; ++m) S[r * LDS_LD + 16 * p + m] = s[m];
     }
     __syncthreads();
     if (p < 3) {
@@ -608,7 +621,14 @@ __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double*
       __syncthreads();
     }
   }
-  if (fail != 0 && r == 0) atomicMin(fail_sh, fail);
+  // first pivot that is not a positive finite number: its reciprocal square
+  // root is then NaN (d <= 0, NaN or +inf; zero gives 0 * inf) instead of a
+  // positive finite number
+  if (q == 0) {
+    const double ri = rinv[r];
+    const unsigned long long bad = __builtin_amdgcn_ballot_w64(!(ri > 0.0 && ri < 1.7976931348623157e308));
+    if (r == 0) *fail_sh = bad ? __builtin_ctzll(bad) + 1 : 0x7fffffff;
+  }
 
   // ---- W: diagonal 16 x 16 blocks, wave q inverts block q, lane j < 16 computes column j
   {
@@ -735,7 +755,14 @@ __device__ __forceinline__ int chol_inv_tile_v4(double* S, double* Wl, double* r
       __syncthreads();
     }
   }
-  if (fail != 0 && r == 0) atomicMin(fail_sh, fail);
+  // first pivot that is not a positive finite number: its reciprocal square
+  // root is then NaN (d <= 0, NaN or +inf; zero gives 0 * inf) instead of a
+  // positive finite number
+  if (q == 0) {
+    const double ri = rinv[r];
+    const unsigned long long bad = __builtin_amdgcn_ballot_w64(!(ri > 0.0 && ri < 1.7976931348623157e308));
+    if (r == 0) *fail_sh = bad ? __builtin_ctzll(bad) + 1 : 0x7fffffff;
+  }
 
   // ---- W: diagonal 16 x 16 blocks, wave q inverts block q, lane j < 16 computes column j (left-looking)
   {

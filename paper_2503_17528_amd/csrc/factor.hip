@@ -576,7 +576,7 @@ __device__ __forceinline__ void diag_finish(const FactorParams& p, int i, int c,
   double* Wout = p.Wd + ((int64_t)i * T + c) * 4096;
   tile_store_dev(sh.u.f.Bs, Wout, 64, 64, 64, tid);
   publish(p.flags + fl_D(p, i, c, c), tid);
-  tile_store_dev(sh.u.f.As, out, b, rows, rows, tid);
+  tile_store_lower_dev(sh.u.f.As, out, b, rows, tid);
   __builtin_amdgcn_s_setprio(0);
   // exact zeros in the mirrored upper tile of the diagonal block (no task reads them)
   if (c > 0) {
@@ -804,7 +804,7 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
       }
       double* Wout = p.Wt + (int64_t)t.c * 4096;
       tile_store_dev(sh.u.f.Bs, Wout, 64, 64, 64, tid);
-      tile_store_dev(sh.u.f.As, out, ld, rows, cols, tid);
+      tile_store_lower_dev(sh.u.f.As, out, ld, rows, tid);  // (rows == cols: the tile is diagonal)
     } else {
       // X = (A - sum) W(c,c)^T
       const double* Wc = (t.type == T_TIPO) ? p.Wt + (int64_t)t.c * 4096
