@@ -741,6 +741,22 @@ __global__ __launch_bounds__(512, 2) void gemm_l128_kernel(GemmArgs args) {
   gemm_tile_dl2<4, 2, 2, 4, L0>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
 }
 
+// Whether the direct-to-LDS bodies can take a problem: 16-byte aligned
+// operands, even leading dimensions, strides and k extents (their loads move
+// pairs of doubles).
+__host__ __device__ inline bool dl_ok(const GProb& p) {
+  auto al = [](const double* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+  for (int s = 0; s < p.nseg; ++s) {
+    const GSeg& g = p.seg[s];
+    if (!al(g.A) || !al(g.B)) return false;
+    if ((g.lda | g.ldb | g.sA0 | g.sA1 | g.sB0 | g.sB1) & 1) return false;
+    if (g.K & 1) return false;
+    if (g.at && (p.M & 1)) return false;
+    if (g.bt && (p.N & 1)) return false;
+  }
+  return true;
+}
+
 // The same tile bodies over a problem list in device memory (batched launches):
 // tile_begin[] holds the first tile of every problem.
 __device__ __forceinline__ int find_prob_list(const long long* tile_begin, int nprob, long long t) {
@@ -752,12 +768,16 @@ __device__ __forceinline__ int find_prob_list(const long long* tile_begin, int n
   return __builtin_amdgcn_readfirstlane(lo);
 }
 
+// 64 x 64 tiles: the lean direct-to-LDS body where the problem allows it
+// (a workgroup-uniform test), the register-staged body otherwise.
+constexpr int LIST64_LDS = 2 * 64 * 66 > 2 * DL2<2, 2, 2, 2>::STAGE ? 2 * 64 * 66 : 2 * DL2<2, 2, 2, 2>::STAGE;
 __global__ __launch_bounds__(NT, 2) void gemm_list_kernel(const GProb* probs, const long long* tile_begin, int nprob) {
-  __shared__ double As[64 * 66];
-  __shared__ double Bs[64 * 66];
+  __shared__ __align__(16) double lds[LIST64_LDS];
   const int j = find_prob_list(tile_begin, nprob, blockIdx.x);
   const GProb& P = probs[j];  // read in place: a private copy would live in scratch
-  gemm_tile_body<2, 2, 64>(P, blockIdx.x - tile_begin[j], threadIdx.x, As, Bs);
+  const long long local = blockIdx.x - tile_begin[j];
+  if (dl_ok(P)) gemm_tile_dl2<2, 2, 2, 2, 4>(P, local, threadIdx.x, lds);
+  else gemm_tile_body<2, 2, 64>(P, local, threadIdx.x, lds, lds + 64 * 66);
 }
 
 __global__ __launch_bounds__(NT, 1) void gemm128_list_kernel(const GProb* probs, const long long* tile_begin, int nprob) {
@@ -861,18 +881,6 @@ static long long plan_tiles(GemmArgs& args, GProb* probs, int nprob, int TM, int
 }
 
 // Operands the direct-to-LDS body can move in 16-byte pieces.
-static bool dl_ok(const GProb& p) {
-  auto al = [](const double* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
-  for (int s = 0; s < p.nseg; ++s) {
-    const GSeg& g = p.seg[s];
-    if (!al(g.A) || !al(g.B)) return false;
-    if ((g.lda | g.ldb | g.sA0 | g.sA1 | g.sB0 | g.sB1) & 1) return false;
-    if (g.K & 1) return false;
-    if (g.at && (p.M & 1)) return false;
-    if (g.bt && (p.N & 1)) return false;
-  }
-  return true;
-}
 
 // 0: choose per launch; 1: register-staged kernels only; 2: direct-to-LDS
 // kernels wherever the operands allow; 3 / 4: first direct-to-LDS body with 64
