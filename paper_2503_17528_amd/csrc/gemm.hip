@@ -780,12 +780,15 @@ __global__ __launch_bounds__(NT, 2) void gemm_list_kernel(const GProb* probs, co
   else gemm_tile_body<2, 2, 64>(P, local, threadIdx.x, lds, lds + 64 * 66);
 }
 
+// 128 x 128 tiles, likewise (the first direct-to-LDS body: 256 threads).
+constexpr int LIST128_LDS = 2 * 128 * 34 > 2 * DLCfg<4, 4>::STAGE ? 2 * 128 * 34 : 2 * DLCfg<4, 4>::STAGE;
 __global__ __launch_bounds__(NT, 1) void gemm128_list_kernel(const GProb* probs, const long long* tile_begin, int nprob) {
-  __shared__ double As[128 * 34];
-  __shared__ double Bs[128 * 34];
+  __shared__ __align__(16) double lds[LIST128_LDS];
   const int j = find_prob_list(tile_begin, nprob, blockIdx.x);
   const GProb& P = probs[j];  // read in place: a private copy would live in scratch
-  gemm_tile_body<4, 4, 32>(P, blockIdx.x - tile_begin[j], threadIdx.x, As, Bs);
+  const long long local = blockIdx.x - tile_begin[j];
+  if (dl_ok(P)) gemm_tile_dl<4, 4, 4>(P, local, threadIdx.x, lds);
+  else gemm_tile_body<4, 4, 32>(P, local, threadIdx.x, lds, lds + 128 * 34);
 }
 
 hipError_t gemm_list_launch(const GProb* d_probs, const long long* d_tile_begin, int nprob, long long ntiles, int big,
