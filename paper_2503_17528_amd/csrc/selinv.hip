@@ -245,8 +245,9 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
 
   // ---- per-block preprocessing and the arrow-row recursion on a side
   // stream, chunk by chunk from the last block down, so that the backward
-  // sweep (on `s`) can start on the first finished chunk while later chunks
-  // fill the CUs the sweep leaves idle.
+  // sweep (on `s`) can start on the first finished blocks while later chunks
+  // fill the CUs the sweep leaves idle; each step of the sweep waits for its
+  // own block only (an event per block, after its arrow row).
   const bool dry = recording();
   hipStream_t sa = dry ? s : side_stream();
   if (!dry) {
@@ -296,7 +297,10 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       set_stage(1, (int)k, 101);
       BTA_TRY(copy2d_launch(T1, b, bb, XB + i0 * bb, b, bb, ib, ib, nsub, sa));
     }
-    // arrow rows of the chunk: X_{n,i} = -(X_{n,i+1} P_B + X_nn P_R)
+    // arrow rows of the chunk: X_{n,i} = -(X_{n,i+1} P_B + X_nn P_R); block i
+    // is ready for the sweep once its row is (event 1 + i)
+    if (a == 0 && !dry)
+      for (int64_t i = i1 - 1; i >= i0; --i) BTA_TRY(hipEventRecord(event_at(1 + (int)i), sa));
     for (int64_t i = i1 - 1; a > 0 && i >= i0; --i) {
       set_stage(1, (int)k, 200 + (int)(i1 - 1 - i));
       GProb p = prob_init();
@@ -312,8 +316,8 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       p.M = ia; p.N = ib;
       p.alpha = -1.0;
       BTA_TRY(gemm_launch(&p, 1, sa));
+      if (!dry) BTA_TRY(hipEventRecord(event_at(1 + (int)i), sa));
     }
-    if (!dry) BTA_TRY(hipEventRecord(event_at(1 + (int)k), sa));
   }
 
   // ---- backward sweep.  X_{i+1,i} goes to one of two buffers; its copy over
@@ -322,14 +326,10 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
   // later.
   hipStream_t sc = dry ? s : copy_stream();
   if (!dry && !sc) return hipErrorInvalidResourceHandle;
-  const int E0 = 1 + (int)chunks.size();
-  size_t next_chunk = 0;
+  const int E0 = 1 + (int)n;
   for (int64_t i = n - 1; i >= 0; --i) {
-    // first step of a preprocessing chunk: wait for that chunk
-    if (next_chunk < chunks.size() && i == chunks[next_chunk].second - 1) {
-      if (!dry) BTA_TRY(hipStreamWaitEvent(s, event_at(1 + (int)next_chunk), 0));
-      ++next_chunk;
-    }
+    // block i's preprocessing and arrow row
+    if (!dry) BTA_TRY(hipStreamWaitEvent(s, event_at(1 + (int)i), 0));
     const bool has_sub = i < n - 1;
     const int step = (int)(n - 1 - i);
     set_stage(2, step, 0);
