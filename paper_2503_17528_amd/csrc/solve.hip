@@ -284,6 +284,26 @@ __device__ void coldot_acc(const double* M, int64_t ld, int64_t R, int Kc, const
   __syncthreads();
 }
 
+// rowdot_acc over one 64 x 64 tile M (row stride 64) whose elements were
+// loaded before: m[j] = M[(w + 4j) * 64 + lane] (wave w, rows w + 4j).
+// Rows >= R and columns >= K contribute zero.  Ends with a barrier.
+__device__ void rowdot_tile_regs(const double (&m)[16], int R, int K, const double* x, double* out, double sign,
+                                 double* part, int tid) {
+  const int w = tid >> 6, lane = tid & 63;
+  const double xk = lane < K ? x[lane] : 0.0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) part[(w + 4 * j) * 65 + lane] = (w + 4 * j < R) ? m[j] * xk : 0.0;
+  __syncthreads();
+  const int r = tid >> 2, q = tid & 3;
+  double t = 0.0;
+#pragma unroll
+  for (int l = 0; l < 16; ++l) t += part[r * 65 + 16 * q + l];
+  t += __shfl_xor(t, 1, 64);
+  t += __shfl_xor(t, 2, 64);
+  if (q == 0 && r < R) out[r] += sign * t;
+  __syncthreads();
+}
+
 struct SolveParams {
   int64_t n, b, a, nrhs, N;
   int T, TA;
@@ -393,12 +413,17 @@ __global__ __launch_bounds__(NT, 1) void solve_fwd_diag_kernel(SolveParams p, in
   for (int c = 0; c < p.T; ++c) {
     const int ext = (int)std::min<int64_t>(64, b - (int64_t)c * 64);
     const int64_t r0 = (int64_t)c * 64;
+    // the tile's inverse does not depend on z: its loads go out first
+    double wr[16];
+    const double* Wc = p.Wd + (i * p.T + c) * 4096;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) wr[j] = Wc[((tid >> 6) + 4 * j) * 64 + (tid & 63)];
     if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
     __syncthreads();
     if (c > 0) rowdot_acc(Ld + r0 * b, b, ext, r0, z, v, -1.0, rpart, tid);
     if (tid < 64) red[tid] = 0.0;
     __syncthreads();
-    rowdot_acc(p.Wd + (i * p.T + c) * 4096, 64, ext, ext, v, red, 1.0, rpart, tid);
+    rowdot_tile_regs(wr, ext, ext, v, red, 1.0, rpart, tid);
     if (tid < ext) z[r0 + tid] = red[tid];
     __syncthreads();
   }
