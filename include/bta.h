@@ -30,8 +30,12 @@
  *    BTA_EINVAL.  Arrays must be 8-byte aligned.
  *  - n >= 1, b >= 1, a >= 0.  With a == 0, R/T (and LR/LT, XR/XT) may be
  *    NULL; with n == 1, B (and LB, XB) may be NULL.
- *  - Calls on different streams may run concurrently only if they use
- *    different workspaces.
+ *  - The library is reentrant per stream: calls enqueued on different
+ *    streams, from one or several host threads, may run concurrently as long
+ *    as they use different workspaces and outputs.  The library's own helper
+ *    streams and events (used by bta_selinv and bta_selinv_batched) are leased
+ *    per call, so concurrent calls never share them.
+ *  - No C++ exception and no abort crosses this interface.
  */
 #ifndef BTA_H
 #define BTA_H
@@ -51,10 +55,12 @@ extern "C" {
 
 typedef struct ihipStream_t* bta_stream_t; /* a hipStream_t */
 
+/* Status of a call.  A matrix that is not positive definite is a numerical
+ * outcome, known only once the work has run: it is reported on the device
+ * through d_info (bta_factor), never as a status (value 2 is unused). */
 typedef enum {
   BTA_OK = 0,
   BTA_EINVAL = 1,   /* invalid argument (dims, NULL, overlap, alignment, workspace) */
-  BTA_ENOTPD = 2,   /* reserved: the matrix is not positive definite (see d_info) */
   BTA_EHIP = 3,     /* a HIP runtime call failed; bta_last_error() has its text */
   BTA_ENOTSUP = 4   /* no supported HIP device (not gfx950) */
 } bta_status;
@@ -81,7 +87,7 @@ BTA_API size_t bta_workspace_bytes(int op, int64_t n, int64_t b, int64_t a, int6
  *       progress watchdog fired.  On a nonzero d_info the outputs are
  *       unspecified and must not be passed to bta_selinv or bta_solve.
  */
-BTA_API int bta_factor(int64_t n, int64_t b, int64_t a,
+BTA_API bta_status bta_factor(int64_t n, int64_t b, int64_t a,
                const double* D, const double* B, const double* R, const double* T,
                double* LD, double* LB, double* LR, double* LT,
                void* work, size_t work_bytes, int64_t* d_info, bta_stream_t stream);
@@ -93,24 +99,29 @@ BTA_API int bta_factor(int64_t n, int64_t b, int64_t a,
  *       Sigma_{i,i} and Sigma_{n,n} full symmetric, Sigma_{i+1,i},
  *       Sigma_{n,i}.
  */
-BTA_API int bta_selinv(int64_t n, int64_t b, int64_t a,
+BTA_API bta_status bta_selinv(int64_t n, int64_t b, int64_t a,
                const double* LD, const double* LB, const double* LR, const double* LT,
                double* XD, double* XB, double* XR, double* XT,
                void* work, size_t work_bytes, bta_stream_t stream);
 
 /*
  * Solve A x = rhs with the factor (block forward then back substitution; not
- * in the paper).  rhs is [N][nrhs] row-major and is overwritten by x.
+ * in the paper, which stops at the selected inverse: the textbook triangular
+ * solves with L and L^T, needed for the objective of Gaussian models below).
+ * rhs is [N][nrhs] row-major and is overwritten by x.
+ * Workspace: bta_workspace_bytes(BTA_OP_SOLVE, n, b, a, nrhs).
  */
-BTA_API int bta_solve(int64_t n, int64_t b, int64_t a,
+BTA_API bta_status bta_solve(int64_t n, int64_t b, int64_t a,
               const double* LD, const double* LB, const double* LR, const double* LT,
               double* rhs, int64_t nrhs, void* work, size_t work_bytes, bta_stream_t stream);
 
 /*
- * log det A = 2 * sum log diag(L) over the diagonal blocks and the tip.
- * d_out: device double receiving the result.
+ * log det A = 2 * sum log diag(L) over the diagonal blocks and the tip (not
+ * in the paper: the determinant of A = L L^T read off the factor's diagonal).
+ * d_out: device double receiving the result; the sum runs in a fixed order
+ * (deterministic).  Workspace: bta_workspace_bytes(BTA_OP_LOGDET, n, b, a, 0).
  */
-BTA_API int bta_logdet(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT,
+BTA_API bta_status bta_logdet(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT,
                double* d_out, void* work, size_t work_bytes, bta_stream_t stream);
 
 /*
@@ -119,7 +130,7 @@ BTA_API int bta_logdet(int64_t n, int64_t b, int64_t a, const double* LD, const 
  * [N][nrhs] row-major device arrays (they may be the same array); d_out is a
  * device double.  Workspace: bta_workspace_bytes(BTA_OP_LOGDET, ...).
  */
-BTA_API int bta_logdet_quad(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT,
+BTA_API bta_status bta_logdet_quad(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT,
                     const double* y, const double* x, int64_t nrhs, double* d_out,
                     void* work, size_t work_bytes, bta_stream_t stream);
 
@@ -132,7 +143,7 @@ BTA_API int bta_logdet_quad(int64_t n, int64_t b, int64_t a, const double* LD, c
  * and gy = 2s*x when gy is not NULL.  s = *d_scale (device double), or 1 when
  * d_scale is NULL.  Elementwise: G* may alias X* exactly (in place).
  */
-BTA_API int bta_grad_logdet_quad(int64_t n, int64_t b, int64_t a,
+BTA_API bta_status bta_grad_logdet_quad(int64_t n, int64_t b, int64_t a,
                     const double* XD, const double* XB, const double* XR, const double* XT,
                     const double* x, int64_t nrhs, const double* d_scale,
                     double* GD, double* GB, double* GR, double* GT, double* gy, bta_stream_t stream);
@@ -156,7 +167,7 @@ typedef struct {
 BTA_API size_t bta_batched_workspace_bytes(int op, int count, const bta_desc* descs);
 
 /* POBTAF for every matrix of the batch, all in one persistent kernel launch. */
-BTA_API int bta_factor_batched(int count, const bta_desc* descs, void* work, size_t work_bytes,
+BTA_API bta_status bta_factor_batched(int count, const bta_desc* descs, void* work, size_t work_bytes,
                                bta_stream_t stream);
 
 /* POBTASI for every matrix of the batch: the launches of all matrices are
@@ -164,7 +175,7 @@ BTA_API int bta_factor_batched(int count, const bta_desc* descs, void* work, siz
  * tile shape of every merged GEMM launch is chosen by the autotuner (measured
  * on first use of a shape class), and the whole launch sequence is captured
  * once in a HIP graph per descriptor set and replayed. */
-BTA_API int bta_selinv_batched(int count, const bta_desc* descs, void* work, size_t work_bytes,
+BTA_API bta_status bta_selinv_batched(int count, const bta_desc* descs, void* work, size_t work_bytes,
                                bta_stream_t stream);
 
 /* Static text for a status code. */

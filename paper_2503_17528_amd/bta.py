@@ -19,7 +19,10 @@ from typing import Optional, Tuple
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbta.so")
 
-BTA_OK, BTA_EINVAL, BTA_ENOTPD, BTA_EHIP, BTA_ENOTSUP = 0, 1, 2, 3, 4
+BTA_OK, BTA_EINVAL, BTA_EHIP, BTA_ENOTSUP = 0, 1, 3, 4
+# Binding-level code of NotPositiveDefinite: the C ABI reports a failed pivot
+# on the device (d_info), never as a status.
+NOT_POSITIVE_DEFINITE = 2
 BTA_OP_FACTOR, BTA_OP_SELINV, BTA_OP_SOLVE, BTA_OP_LOGDET = 0, 1, 2, 3
 
 EXPORTED = ("bta_workspace_bytes", "bta_factor", "bta_selinv", "bta_solve", "bta_logdet",
@@ -43,7 +46,7 @@ class BTAError(RuntimeError):
 
 class NotPositiveDefinite(BTAError):
     def __init__(self, row: int):
-        super().__init__(BTA_ENOTPD, f"matrix is not positive definite: first failing pivot at global row {row} (1-based)")
+        super().__init__(NOT_POSITIVE_DEFINITE, f"matrix is not positive definite: first failing pivot at global row {row} (1-based)")
         self.row = row
 
 
@@ -362,7 +365,7 @@ class Batch:
             for m, info in enumerate(self.info):
                 v = int(info.item())
                 if v != 0:
-                    raise BTAError(BTA_ENOTPD, f"matrix {m}: info={v}")
+                    raise BTAError(NOT_POSITIVE_DEFINITE, f"matrix {m}: info={v}")
         return self.L
 
     def selinv(self, stream=None):

@@ -16,8 +16,8 @@ namespace {
 
 thread_local std::string g_last_error;
 
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int code, const char* fmt, ...) {
+bta_status fail(bta_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+bta_status fail(bta_status code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -27,7 +27,7 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-int hip_fail(hipError_t e, const char* where) {
+bta_status hip_fail(hipError_t e, const char* where) {
   return fail(BTA_EHIP, "%s: %s", where, hipGetErrorString(e));
 }
 
@@ -47,7 +47,7 @@ struct Arr {
 // Every array present must be non-null and 8-byte aligned; arrays may
 // coincide exactly only within an (input, output) pair; any other overlap is
 // an error.
-int check_arrays(const Arr* arr, int count, const int* pair_of) {
+bta_status check_arrays(const Arr* arr, int count, const int* pair_of) {
   for (int i = 0; i < count; ++i) {
     if (arr[i].bytes == 0) continue;
     if (!arr[i].p) return fail(BTA_EINVAL, "%s is NULL", arr[i].name);
@@ -67,7 +67,7 @@ int check_arrays(const Arr* arr, int count, const int* pair_of) {
   return BTA_OK;
 }
 
-int device_ok() {
+bta_status device_ok() {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -81,7 +81,7 @@ int device_ok() {
 
 size_t blk_bytes(int64_t count, int64_t r, int64_t c) { return (size_t)std::max<int64_t>(count, 0) * r * c * 8; }
 
-int check_work(void* work, size_t work_bytes, size_t need) {
+bta_status check_work(void* work, size_t work_bytes, size_t need) {
   if (need == 0) return BTA_OK;
   if (!work) return fail(BTA_EINVAL, "workspace is NULL (%zu bytes needed)", need);
   if (reinterpret_cast<uintptr_t>(work) & 255) return fail(BTA_EINVAL, "workspace must be 256-byte aligned");
@@ -104,7 +104,7 @@ size_t bta_workspace_bytes(int op, int64_t n, int64_t b, int64_t a, int64_t nrhs
   }
 }
 
-int bta_factor(int64_t n, int64_t b, int64_t a, const double* D, const double* B, const double* R, const double* T,
+bta_status bta_factor(int64_t n, int64_t b, int64_t a, const double* D, const double* B, const double* R, const double* T,
                double* LD, double* LB, double* LR, double* LT, void* work, size_t work_bytes, int64_t* d_info,
                bta_stream_t stream) {
   if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
@@ -113,7 +113,7 @@ int bta_factor(int64_t n, int64_t b, int64_t a, const double* D, const double* B
       {T, blk_bytes(1, a, a), "T"},        {LD, blk_bytes(n, b, b), "LD"},   {LB, blk_bytes(n - 1, b, b), "LB"},
       {LR, blk_bytes(n, a, b), "LR"},      {LT, blk_bytes(1, a, a), "LT"},   {d_info, 8, "d_info"}};
   const int pair[9] = {4, 5, 6, 7, 0, 1, 2, 3, -1};
-  int st = check_arrays(arr, 9, pair);
+  bta_status st = check_arrays(arr, 9, pair);
   if (st) return st;
   const bta::FactorPlan fp = bta::factor_plan(n, b, a);
   st = check_work(work, work_bytes, fp.bytes);
@@ -125,7 +125,7 @@ int bta_factor(int64_t n, int64_t b, int64_t a, const double* D, const double* B
   return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_factor launch");
 }
 
-int bta_selinv(int64_t n, int64_t b, int64_t a, const double* LD, const double* LB, const double* LR, const double* LT,
+bta_status bta_selinv(int64_t n, int64_t b, int64_t a, const double* LD, const double* LB, const double* LR, const double* LT,
                double* XD, double* XB, double* XR, double* XT, void* work, size_t work_bytes, bta_stream_t stream) {
   if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
   const Arr arr[8] = {
@@ -133,7 +133,7 @@ int bta_selinv(int64_t n, int64_t b, int64_t a, const double* LD, const double* 
       {LT, blk_bytes(1, a, a), "LT"}, {XD, blk_bytes(n, b, b), "XD"},     {XB, blk_bytes(n - 1, b, b), "XB"},
       {XR, blk_bytes(n, a, b), "XR"}, {XT, blk_bytes(1, a, a), "XT"}};
   const int pair[8] = {4, 5, 6, 7, 0, 1, 2, 3};
-  int st = check_arrays(arr, 8, pair);
+  bta_status st = check_arrays(arr, 8, pair);
   if (st) return st;
   const bta::SelinvPlan sp = bta::selinv_plan(n, b, a);
   st = check_work(work, work_bytes, sp.bytes);
@@ -144,7 +144,7 @@ int bta_selinv(int64_t n, int64_t b, int64_t a, const double* LD, const double* 
   return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_selinv launch");
 }
 
-int bta_solve(int64_t n, int64_t b, int64_t a, const double* LD, const double* LB, const double* LR, const double* LT,
+bta_status bta_solve(int64_t n, int64_t b, int64_t a, const double* LD, const double* LB, const double* LR, const double* LT,
               double* rhs, int64_t nrhs, void* work, size_t work_bytes, bta_stream_t stream) {
   if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
   if (nrhs < 1 || nrhs > (1 << 20)) return fail(BTA_EINVAL, "invalid nrhs=%lld", (long long)nrhs);
@@ -152,7 +152,7 @@ int bta_solve(int64_t n, int64_t b, int64_t a, const double* LD, const double* L
   const Arr arr[5] = {{LD, blk_bytes(n, b, b), "LD"}, {LB, blk_bytes(n - 1, b, b), "LB"}, {LR, blk_bytes(n, a, b), "LR"},
                       {LT, blk_bytes(1, a, a), "LT"}, {rhs, blk_bytes(1, N, nrhs), "rhs"}};
   const int pair[5] = {-1, -1, -1, -1, -1};
-  int st = check_arrays(arr, 5, pair);
+  bta_status st = check_arrays(arr, 5, pair);
   if (st) return st;
   st = check_work(work, work_bytes, bta::solve_work_bytes(n, b, a, nrhs));
   if (st) return st;
@@ -162,12 +162,12 @@ int bta_solve(int64_t n, int64_t b, int64_t a, const double* LD, const double* L
   return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_solve launch");
 }
 
-int bta_logdet(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT, double* d_out, void* work,
+bta_status bta_logdet(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT, double* d_out, void* work,
                size_t work_bytes, bta_stream_t stream) {
   if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
   const Arr arr[3] = {{LD, blk_bytes(n, b, b), "LD"}, {LT, blk_bytes(1, a, a), "LT"}, {d_out, 8, "d_out"}};
   const int pair[3] = {-1, -1, -1};
-  int st = check_arrays(arr, 3, pair);
+  bta_status st = check_arrays(arr, 3, pair);
   if (st) return st;
   st = check_work(work, work_bytes, bta::logdet_work_bytes(n, b, a));
   if (st) return st;
@@ -177,7 +177,7 @@ int bta_logdet(int64_t n, int64_t b, int64_t a, const double* LD, const double* 
   return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_logdet launch");
 }
 
-int bta_logdet_quad(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT, const double* y, const double* x,
+bta_status bta_logdet_quad(int64_t n, int64_t b, int64_t a, const double* LD, const double* LT, const double* y, const double* x,
                     int64_t nrhs, double* d_out, void* work, size_t work_bytes, bta_stream_t stream) {
   if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
   if (nrhs < 1 || nrhs > (1 << 20)) return fail(BTA_EINVAL, "invalid nrhs=%lld", (long long)nrhs);
@@ -185,7 +185,7 @@ int bta_logdet_quad(int64_t n, int64_t b, int64_t a, const double* LD, const dou
   const Arr arr[5] = {{LD, blk_bytes(n, b, b), "LD"}, {LT, blk_bytes(1, a, a), "LT"}, {y, blk_bytes(1, N, nrhs), "y"},
                       {x, blk_bytes(1, N, nrhs), "x"}, {d_out, 8, "d_out"}};
   const int pair[5] = {-1, -1, 3, 2, -1};  // y and x may coincide (f = logdet + y^T y)
-  int st = check_arrays(arr, 5, pair);
+  bta_status st = check_arrays(arr, 5, pair);
   if (st) return st;
   st = check_work(work, work_bytes, bta::logdet_work_bytes(n, b, a));
   if (st) return st;
@@ -195,7 +195,7 @@ int bta_logdet_quad(int64_t n, int64_t b, int64_t a, const double* LD, const dou
   return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_logdet_quad launch");
 }
 
-int bta_grad_logdet_quad(int64_t n, int64_t b, int64_t a, const double* XD, const double* XB, const double* XR,
+bta_status bta_grad_logdet_quad(int64_t n, int64_t b, int64_t a, const double* XD, const double* XB, const double* XR,
                          const double* XT, const double* x, int64_t nrhs, const double* d_scale, double* GD, double* GB,
                          double* GR, double* GT, double* gy, bta_stream_t stream) {
   if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
@@ -206,7 +206,7 @@ int bta_grad_logdet_quad(int64_t n, int64_t b, int64_t a, const double* XD, cons
                        {GR, blk_bytes(n, a, b), "GR"}, {GT, blk_bytes(1, a, a), "GT"}, {x, blk_bytes(1, N, nrhs), "x"},
                        {d_scale, d_scale ? 8u : 0u, "d_scale"}, {gy, gy ? blk_bytes(1, N, nrhs) : 0u, "gy"}};
   const int pair[11] = {4, 5, 6, 7, 0, 1, 2, 3, -1, -1, -1};
-  int st = check_arrays(arr, 11, pair);
+  bta_status st = check_arrays(arr, 11, pair);
   if (st) return st;
   st = device_ok();
   if (st) return st;
@@ -217,14 +217,14 @@ int bta_grad_logdet_quad(int64_t n, int64_t b, int64_t a, const double* XD, cons
 
 namespace {
 
-int validate_batch(int count, const bta_desc* d, bool factor) {
+bta_status validate_batch(int count, const bta_desc* d, bool factor) {
   if (count < 1 || count > (1 << 20)) return fail(BTA_EINVAL, "invalid batch count %d", count);
   if (!d) return fail(BTA_EINVAL, "descriptor array is NULL");
   std::vector<std::pair<uintptr_t, uintptr_t>> spans;
   for (int m = 0; m < count; ++m) {
     const int64_t n = d[m].n, b = d[m].b, a = d[m].a;
     if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "matrix %d: invalid sizes n=%lld b=%lld a=%lld", m, (long long)n, (long long)b, (long long)a);
-    int st;
+    bta_status st;
     if (factor) {
       const Arr arr[9] = {{d[m].D, blk_bytes(n, b, b), "D"},   {d[m].B, blk_bytes(n - 1, b, b), "B"}, {d[m].R, blk_bytes(n, a, b), "R"},
                           {d[m].T, blk_bytes(1, a, a), "T"},   {d[m].LD, blk_bytes(n, b, b), "LD"}, {d[m].LB, blk_bytes(n - 1, b, b), "LB"},
@@ -279,8 +279,8 @@ size_t bta_batched_workspace_bytes(int op, int count, const bta_desc* descs) {
   return 0;
 }
 
-int bta_factor_batched(int count, const bta_desc* descs, void* work, size_t work_bytes, bta_stream_t stream) {
-  int st = validate_batch(count, descs, true);
+bta_status bta_factor_batched(int count, const bta_desc* descs, void* work, size_t work_bytes, bta_stream_t stream) {
+  bta_status st = validate_batch(count, descs, true);
   if (st) return st;
   std::vector<int64_t> n, b, a;
   batch_sizes(count, descs, n, b, a);
@@ -294,8 +294,8 @@ int bta_factor_batched(int count, const bta_desc* descs, void* work, size_t work
   return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_factor_batched launch");
 }
 
-int bta_selinv_batched(int count, const bta_desc* descs, void* work, size_t work_bytes, bta_stream_t stream) {
-  int st = validate_batch(count, descs, false);
+bta_status bta_selinv_batched(int count, const bta_desc* descs, void* work, size_t work_bytes, bta_stream_t stream) {
+  bta_status st = validate_batch(count, descs, false);
   if (st) return st;
   std::vector<int64_t> n, b, a;
   batch_sizes(count, descs, n, b, a);
@@ -312,7 +312,6 @@ const char* bta_status_string(int status) {
   switch (status) {
     case BTA_OK: return "BTA_OK";
     case BTA_EINVAL: return "BTA_EINVAL: invalid argument";
-    case BTA_ENOTPD: return "BTA_ENOTPD: matrix is not positive definite";
     case BTA_EHIP: return "BTA_EHIP: HIP runtime error";
     case BTA_ENOTSUP: return "BTA_ENOTSUP: unsupported device";
     default: return "unknown bta status";

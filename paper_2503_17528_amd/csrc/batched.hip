@@ -17,6 +17,7 @@
 
 #include "bta_device.hpp"
 #include "bta_internal.hpp"
+#include "bta_testing.h"
 
 #define BTA_TRY_E(x)                    \
   do {                                  \
@@ -348,8 +349,9 @@ hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, h
   if (e0) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); }
 
   // capture the merged sequence for the next calls with this descriptor set
-  hipStream_t cap = capture_stream();
-  if (!cap) return hipErrorInvalidResourceHandle;
+  SyncLease lease;
+  if (!lease.get()) return hipErrorInvalidResourceHandle;
+  hipStream_t cap = lease.get()->capture;
   BTA_TRY_E(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
   hipError_t ce = hipSuccess;
   for (size_t k = 0; k < mp.stages.size() && ce == hipSuccess; ++k) ce = launch_stage(mp.stages[k], dtab, choice[k], cap);
@@ -372,7 +374,7 @@ hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, h
 // operation overlaps a read or a write of another one in the same stage);
 // (3) every matrix contributes its operations in its own stage order.
 // Returns 0 when the plan is valid.
-extern "C" __attribute__((visibility("default"))) int bta_internal_selinv_batch_check(int count, const int64_t* n,
+BTA_TESTING_API int bta_internal_selinv_batch_check(int count, const int64_t* n,
                                                                                       const int64_t* b, const int64_t* a) {
   using namespace bta;
   std::vector<BatchMatrix> mats(count);
@@ -440,7 +442,7 @@ extern "C" __attribute__((visibility("default"))) int bta_internal_selinv_batch_
 
 // Autotuner decisions recorded so far (for inspection): writes up to `cap`
 // bytes of "shape class=choice" lines.
-extern "C" __attribute__((visibility("default"))) int bta_internal_autotune_dump(char* out, int cap) {
+BTA_TESTING_API int bta_internal_autotune_dump(char* out, int cap) {
   std::lock_guard<std::mutex> lk(g_mu);
   std::string s;
   for (auto& kv : g_tuned) s += kv.first + "=" + (kv.second ? "128" : "64") + "\n";

@@ -69,47 +69,6 @@ struct Stage {
   double v[16];
 };
 
-__device__ __forceinline__ void stage_load(Stage& s, const OpTile& t, int tid) {
-  if (!t.trans) {
-    const int m = tid >> 2, k0 = (tid & 3) * 16;
-    const double* src = t.p + (int64_t)m * t.ld + k0;
-    const bool row_ok = m < t.rows;
-    const bool full = row_ok && (k0 + 16 <= t.cols) && ((t.ld & 1) == 0) && ((((uintptr_t)src) & 15) == 0);
-    if (full) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        d2v x = *reinterpret_cast<const d2v*>(src + 2 * j);
-        s.v[2 * j] = x[0];
-        s.v[2 * j + 1] = x[1];
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 16; ++j) s.v[j] = (row_ok && k0 + j < t.cols) ? src[j] : 0.0;
-    }
-  } else {
-    const int k = tid >> 2, m0 = (tid & 3) * 16;
-    const double* src = t.p + (int64_t)k * t.ld + m0;
-    const bool k_ok = k < t.cols;
-    const bool full = k_ok && (m0 + 16 <= t.rows) && ((t.ld & 1) == 0) && ((((uintptr_t)src) & 15) == 0);
-    if (full) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        d2v x = *reinterpret_cast<const d2v*>(src + 2 * j);
-        s.v[2 * j] = x[0];
-        s.v[2 * j + 1] = x[1];
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 16; ++j) s.v[j] = (k_ok && m0 + j < t.rows) ? src[j] : 0.0;
-    }
-  }
-}
-
-__device__ __forceinline__ void stage_zero(Stage& s) {
-#pragma unroll
-  for (int j = 0; j < 16; ++j) s.v[j] = 0.0;
-}
-
 // Device-coherent (agent scope, sc1) element access for data exchanged between
 // workgroups of one persistent kernel: such loads and stores do not depend on
 // the per-XCD L2 being written back or invalidated.
@@ -157,14 +116,34 @@ __device__ __forceinline__ void lds_dma16_dev(const double* src, double* lds_wav
   __builtin_amdgcn_global_load_lds(static_cast<const void*>(src),
                                    (__attribute__((address_space(3))) void*)(lds_wave_base), 16, 0, 16 /* sc1 */);
 }
+// The same 16-byte piece through the caches (no scope bits): allowed only for
+// data that is final before its first read on this XCD and whose cache lines
+// hold nothing else that changes during the kernel (see tile_load_lds_dev).
+__device__ __forceinline__ void lds_dma16_cached(const double* src, double* lds_wave_base) {
+  __builtin_amdgcn_global_load_lds(static_cast<const void*>(src),
+                                   (__attribute__((address_space(3))) void*)(lds_wave_base), 16, 0, 0);
+}
 
 // Issue the loads of tile t into the pieced LDS image dst (elements outside
 // t.rows x t.cols read as zero).  Wave w, instruction j fills rows 16w + 2j and
 // 16w + 2j + 1.  The caller waits (vmcnt) and synchronizes before reading dst.
-__device__ __forceinline__ void tile_load_lds_dev(double* dst, const OpTile& t, int tid) {
+// cached (workgroup-uniform): read through the L2 instead of device-coherent
+// loads.  Valid for a published (write-once) tile whose rows start on 128-byte
+// cache lines and whose leading dimension is a multiple of 16 doubles: no line
+// of it can then have entered this XCD's L2 before the tile was final (it is
+// only read after its flag), and the consumer's acquire invalidates the CU's L1.
+__device__ __forceinline__ void tile_load_lds_dev(double* dst, const OpTile& t, int tid, bool cached = false) {
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const bool fast = ((t.ld & 1) == 0) && ((t.cols & 1) == 0) && ((reinterpret_cast<uintptr_t>(t.p) & 15) == 0);
-  if (fast) {
+  if (fast && cached) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int slot = (w * 8 + j) * 64 + lane;
+      const int m = slot >> 5, pc = (slot & 31) ^ (m & 15);
+      const double* src = (m < t.rows && 2 * pc < t.cols) ? t.p + (int64_t)m * t.ld + 2 * pc : k_zero_pair;
+      lds_dma16_cached(src, dst + (w * 8 + j) * 128);
+    }
+  } else if (fast) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int slot = (w * 8 + j) * 64 + lane;
@@ -299,42 +278,6 @@ __device__ __forceinline__ void mma_tile(Acc& c, const double* As, const double*
 }
 
 // Write the accumulator tile into LDS as a row-major 64 x 64 image (stride LDS_LD).
-// Two products sharing the left tile: c1 += A A^T and c2 += A B^T (64 x 64 x 64
-// each), one 16-wide k group at a time so that only one group of operands is
-// live in registers.
-__device__ __forceinline__ void mma_tile2(Acc& c1, Acc& c2, const double* As, const double* Bs, int tid) {
-  const int w = tid >> 6, lane = tid & 63;
-  const int r0 = 32 * (w >> 1) + (lane & 15);
-  const int c0 = 32 * (w & 1) + (lane & 15);
-  const int kl = (lane >> 4) * 4;
-#pragma unroll
-  for (int kg = 0; kg < 4; ++kg) {
-    d4 ar[2], ac[2], bc[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const double* pr = As + (r0 + 16 * i) * LDS_LD + kg * 16 + kl;
-      const double* pc = As + (c0 + 16 * i) * LDS_LD + kg * 16 + kl;
-      const double* pb = Bs + (c0 + 16 * i) * LDS_LD + kg * 16 + kl;
-      const d2v r01 = *reinterpret_cast<const d2v*>(pr), r23 = *reinterpret_cast<const d2v*>(pr + 2);
-      const d2v c01 = *reinterpret_cast<const d2v*>(pc), c23 = *reinterpret_cast<const d2v*>(pc + 2);
-      const d2v b01 = *reinterpret_cast<const d2v*>(pb), b23 = *reinterpret_cast<const d2v*>(pb + 2);
-      ar[i] = d4{r01[0], r01[1], r23[0], r23[1]};
-      ac[i] = d4{c01[0], c01[1], c23[0], c23[1]};
-      bc[i] = d4{b01[0], b01[1], b23[0], b23[1]};
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          c1.v[i][j] = mfma16(ar[i][s], ac[j][s], c1.v[i][j]);
-          c2.v[i][j] = mfma16(ar[i][s], bc[j][s], c2.v[i][j]);
-        }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-}
-
 __device__ __forceinline__ void acc_to_lds(const Acc& c, double* lds, int tid) {
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -375,117 +318,12 @@ __device__ __forceinline__ void acc_store_dev(const Acc& c, double* p, int64_t l
       }
 }
 
-// Store the accumulator (times `scale`) into a rows x cols window of a
-// row-major global tile.  mode 0: all; mode 1: lower triangle only (r >= c);
-// mode 2: lower triangle with exact zeros written above the diagonal.
-__device__ __forceinline__ void acc_store(const Acc& c, double* p, int64_t ld, int rows, int cols, double scale, int mode, int tid) {
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = tile_row(tid, bi, j), q = tile_col(tid, bj);
-        if (r < rows && q < cols) {
-          double v = scale * c.v[bi][bj][j];
-          if (mode == 1 && q > r) continue;
-          if (mode == 2 && q > r) v = 0.0;
-          p[(int64_t)r * ld + q] = v;
-        }
-      }
-}
-
 // ---------------------------------------------------------------------------
-// In-LDS Cholesky of a 64 x 64 SPD tile fused with the inverse of its factor.
-// Input: the tile in LDS `S` (row-major, stride LDS_LD; lower triangle read).
-// Output: L (lower, zeros above) and W = L^{-1} (lower, zeros above) back in
-// `S` and `Wl` (both row-major, stride LDS_LD).  Returns (uniformly) the
-// 1-based index of the first pivot that is not positive and finite, else 0.
-//
-// Thread (r = tid%64, q = tid/64) keeps row r, columns 16q .. 16q+15 of both
-// S and W in registers.  Column k is finished by wave k/16: it takes the pivot
-// from lane k, scales its column and publishes it through LDS; one barrier per
-// column; every thread then applies the rank-1 update to its part of the
-// trailing matrix.  The rows of W follow by forward substitution on the
-// identity, which only needs row k of W inside the same wave (cross-lane
-// reads, no barrier).  The 16 columns of a wave are walked by an unrolled
-// loop so that every register index is static.
+// Cross-lane read: lane `lane`'s value of x, broadcast to the whole wave.
 __device__ __forceinline__ double rd_lane(double x, int lane) {
   int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
   int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
   return __hiloint2double(hi, lo);
-}
-
-__device__ int chol_inv_tile(double* S, double* Wl, double* colbuf /* [2][64] */, double* pivbuf /* [2] */,
-                             int* fail_sh, int tid) {
-  const int r = tid & 63, q = tid >> 6;
-  double s[16], w[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    s[m] = S[r * LDS_LD + 16 * q + m];
-    w[m] = (r == 16 * q + m) ? 1.0 : 0.0;
-  }
-  if (tid == 0) *fail_sh = 0x7fffffff;  // "no failure"; lowered by atomicMin below
-  int fail = 0;
-  for (int qo = 0; qo < 4; ++qo) {  // owner wave of columns 16qo .. 16qo+15
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int k = 16 * qo + m;
-      double* col = colbuf + (k & 1) * 64;
-      if (q == qo) {
-        const double d = rd_lane(s[m], k);
-        const bool ok = (d > 0.0) && (d <= 1.7976931348623157e308);
-        if (!ok && fail == 0) fail = k + 1;
-        const double sq = sqrt(d);
-        const double rinv = 1.0 / sq;
-        const double lv = (r > k) ? s[m] * rinv : ((r == k) ? sq : 0.0);
-        s[m] = lv;
-        col[r] = lv;
-        if (r == 0) pivbuf[k & 1] = rinv;
-      }
-      __syncthreads();
-      const double lr = col[r];
-      const double rinv = pivbuf[k & 1];
-      // trailing update of S: columns c = 16q + mm > k
-      if (q > qo) {
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) s[mm] -= lr * col[16 * q + mm];
-      } else if (q == qo) {
-#pragma unroll
-        for (int mm = m + 1; mm < 16; ++mm) s[mm] -= lr * col[16 * q + mm];
-      }
-      // W: finish row k (scale by 1/L_kk), then eliminate it from the rows below;
-      // columns c = 16q + mm <= k can be nonzero in row k
-      if (r == k) {
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) w[mm] *= rinv;
-      }
-      if (q < qo) {
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) {
-          const double wk = rd_lane(w[mm], k);
-          if (r > k) w[mm] -= lr * wk;
-        }
-      } else if (q == qo) {
-#pragma unroll
-        for (int mm = 0; mm <= m; ++mm) {
-          const double wk = rd_lane(w[mm], k);
-          if (r > k) w[mm] -= lr * wk;
-        }
-      }
-    }
-  }
-  if (fail != 0 && (tid & 63) == 0) atomicMin(fail_sh, fail);
-  // write back L and W (lower, zeros above)
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int c = 16 * q + m;
-    S[r * LDS_LD + c] = (c <= r) ? s[m] : 0.0;
-    Wl[r * LDS_LD + c] = (c <= r) ? w[m] : 0.0;
-  }
-  __syncthreads();
-  const int f = *fail_sh;
-  return f == 0x7fffffff ? 0 : f;
 }
 
 // 1/sqrt(d) from the hardware estimate y (relative error below 2^-24,
@@ -505,17 +343,6 @@ __device__ __forceinline__ double rsqrt_refined(double d) {
 }
 
 // ---------------------------------------------------------------- 64 x 64 Cholesky + inverse, MFMA-blocked
-// Broadcast of one lane's double to the whole wave: readlane (VALU, result via
-// SGPRs) or ds_bpermute (LDS crossbar, result straight in VGPRs).
-template <int BC>
-__device__ __forceinline__ double bcast(double x, int src) {
-  if (BC != 1) return rd_lane(x, src);
-  const int idx = src << 2;
-  const int lo = __builtin_amdgcn_ds_bpermute(idx, __double2loint(x));
-  const int hi = __builtin_amdgcn_ds_bpermute(idx, __double2hiint(x));
-  return __hiloint2double(hi, lo);
-}
-
 // c += sgn * A B^T for 16 x 16 blocks over 16 k, operands in LDS:
 // A(m,k) = A[m*lda + k]; B(n,k) = B[n*ldb + k] (bt false) or B[k*ldb + n] (bt true).
 // Lane l supplies row/col l%16 and k = 4*(l/16) + s for MFMA s (A rows 16-byte aligned).
@@ -562,7 +389,6 @@ __device__ __forceinline__ void blk_store(const d4& c, double* X, int ld, int la
 // column, reusing the pivots' reciprocal square roots), then the 2 x 2 block
 // recursion W21 = -W22 L21 W11, at 16 and at 32, on MFMA.
 // Scratch: rinv[64], tmp[4 * 16 * 17].
-template <int BC>
 __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double* rinv, double* tmp, int* fail_sh, int tid) {
   const int r = tid & 63, q = tid >> 6;
 #pragma unroll
@@ -584,20 +410,15 @@ __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double*
         // are written back as zeros
         const double lv = s[m] * ri;
         s[m] = lv;
-        if (BC == 2) {
-          // column m+1 (the next pivot) by a cross-lane read; the other columns
-          // through a double-buffered LDS copy of the column (results in VGPRs,
-          // off the next pivot's critical path)
-          if (m + 1 < 16) s[m + 1] -= lv * rd_lane(lv, k + 1);
-          if (m + 2 < 16) {
-            double* cb = tmp + (m & 1) * 64;
-            cb[r] = lv;
+        // column m+1 (the next pivot) by a cross-lane read; the other columns
+        // through a double-buffered LDS copy of the column (results in VGPRs,
+        // off the next pivot's critical path)
+        if (m + 1 < 16) s[m + 1] -= lv * rd_lane(lv, k + 1);
+        if (m + 2 < 16) {
+          double* cb = tmp + (m & 1) * 64;
+          cb[r] = lv;
 #pragma unroll
-            for (int mm = m + 2; mm < 16; ++mm) s[mm] -= lv * cb[16 * p + mm];
-          }
-        } else {
-#pragma unroll
-          for (int mm = m + 1; mm < 16; ++mm) s[mm] -= lv * bcast<BC>(lv, 16 * p + mm);
+          for (int mm = m + 2; mm < 16; ++mm) s[mm] -= lv * cb[16 * p + mm];
         }
       }
       // the rows above the diagonal keep stale values: nothing reads them, and
@@ -690,272 +511,6 @@ __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double*
   return f == 0x7fffffff ? 0 : f;
 }
 
-// 1/d from the hardware estimate refined by two Newton steps.
-__device__ __forceinline__ double rcp_refined(double d) {
-  double y = __builtin_amdgcn_rcp(d);
-  double e = __builtin_fma(-d, y, 1.0);
-  y = __builtin_fma(y, e, y);
-  e = __builtin_fma(-d, y, 1.0);
-  return __builtin_fma(y, e, y);
-}
-
-// Same contract as chol_inv_tile_mfma.  The panels are eliminated without
-// square roots: pivot k only needs 1/d_k, the Schur complement columns are
-// updated with t = a_k / d_k times the unscaled column a_k (broadcast through
-// LDS, the value for the next pivot's own row read across lanes), and the
-// finished panel is scaled by d_k^{-1/2} at the end, sixteen independent
-// reciprocal square roots instead of sixteen on the pivot chain.  The diagonal
-// blocks of W are computed left-looking, one lane per column, with the rows of
-// L read as broadcasts.
-// Scratch: rinv[64], tmp[4 * 16 * 17].
-__device__ __forceinline__ int chol_inv_tile_v4(double* S, double* Wl, double* rinv, double* tmp, int* fail_sh, int tid) {
-  const int r = tid & 63, q = tid >> 6;
-  if (tid == 0) *fail_sh = 0x7fffffff;
-  int fail = 0;
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    if (q == p) {
-      double s[16], dd[16];
-#pragma unroll
-      for (int m = 0; m < 16; ++m) s[m] = S[r * LDS_LD + 16 * p + m];
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int k = 16 * p + m;
-        double* cb = tmp + (m & 1) * 64;
-        if (m + 2 < 16) cb[r] = s[m];
-        const double d = rd_lane(s[m], k);
-        const double anext = (m + 1 < 16) ? rd_lane(s[m], k + 1) : 0.0;
-        dd[m] = d;
-        const bool ok = (d > 0.0) && (d <= 1.7976931348623157e308);
-        if (!ok && fail == 0) fail = k + 1;
-        const double t = s[m] * rcp_refined(d);
-        if (m + 1 < 16) s[m + 1] -= t * anext;
-#pragma unroll
-        for (int mm = m + 2; mm < 16; ++mm) s[mm] -= t * cb[16 * p + mm];
-      }
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const double ri = rsqrt_refined(dd[m]);
-        if (r == 0) rinv[16 * p + m] = ri;
-        S[r * LDS_LD + 16 * p + m] = (r >= 16 * p + m) ? s[m] * ri : 0.0;
-      }
-    }
-    __syncthreads();
-    if (p < 3) {
-      const int nb = (3 - p) * (4 - p) / 2;
-      for (int e = q; e < nb; e += 4) {
-        int J = p + 1, rem = e;
-        while (rem >= 4 - J) { rem -= 4 - J; ++J; }
-        const int I = J + rem;
-        d4 c;
-        blk_load(c, S + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
-        mma16x16(c, S + 16 * I * LDS_LD + 16 * p, LDS_LD, S + 16 * J * LDS_LD + 16 * p, LDS_LD, false, -1.0, r);
-        blk_store(c, S + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
-      }
-      __syncthreads();
-    }
-  }
-  // first pivot that is not a positive finite number: its reciprocal square
-  // root is then NaN (d <= 0, NaN or +inf; zero gives 0 * inf) instead of a
-  // positive finite number
-  if (q == 0) {
-    const double ri = rinv[r];
-    const unsigned long long bad = __builtin_amdgcn_ballot_w64(!(ri > 0.0 && ri < 1.7976931348623157e308));
-    if (r == 0) *fail_sh = bad ? __builtin_ctzll(bad) + 1 : 0x7fffffff;
-  }
-
-  // ---- W: diagonal 16 x 16 blocks, wave q inverts block q, lane j < 16 computes column j (left-looking)
-  {
-    const int Q = q, j = r;
-    double w[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const double* row = S + (16 * Q + i) * LDS_LD + 16 * Q;
-      double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-      for (int k = 0; k < i; ++k) {
-        if (k & 1) a1 += row[k] * w[k];
-        else a0 += row[k] * w[k];
-      }
-      w[i] = ((i == j ? 1.0 : 0.0) - (a0 + a1)) * rinv[16 * Q + i];
-    }
-    if (j < 16) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) Wl[(16 * Q + i) * LDS_LD + 16 * Q + j] = (i >= j) ? w[i] : 0.0;
-    }
-    for (int e = r; e < 16 * 48; e += 64) {
-      const int rr = e / 48, cc = e - rr * 48;
-      const int col = cc < 16 * Q ? cc : cc + 16;
-      Wl[(16 * Q + rr) * LDS_LD + col] = 0.0;
-    }
-  }
-  __syncthreads();
-  if (q < 2) {
-    const int I = 2 * q + 1, J = 2 * q;
-    double* T = tmp + q * 16 * 17;
-    d4 t = {0.0, 0.0, 0.0, 0.0};
-    mma16x16(t, S + 16 * I * LDS_LD + 16 * J, LDS_LD, Wl + 16 * J * LDS_LD + 16 * J, LDS_LD, true, 1.0, r);
-    blk_store(t, T, 17, r);
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    d4 o = {0.0, 0.0, 0.0, 0.0};
-    mma16x16(o, Wl + 16 * I * LDS_LD + 16 * I, LDS_LD, T, 17, true, -1.0, r);
-    blk_store(o, Wl + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
-  }
-  __syncthreads();
-  {
-    const int I = 2 + (q >> 1), J = q & 1;
-    double* U = tmp + q * 16 * 17;
-    d4 u = {0.0, 0.0, 0.0, 0.0};
-    for (int K = J; K < 2; ++K)
-      mma16x16(u, S + 16 * I * LDS_LD + 16 * K, LDS_LD, Wl + 16 * K * LDS_LD + 16 * J, LDS_LD, true, 1.0, r);
-    blk_store(u, U, 17, r);
-  }
-  __syncthreads();
-  {
-    const int I = 2 + (q >> 1), J = q & 1;
-    d4 o = {0.0, 0.0, 0.0, 0.0};
-    for (int K = 2; K <= I; ++K)
-      mma16x16(o, Wl + 16 * I * LDS_LD + 16 * K, LDS_LD, tmp + (2 * (K - 2) + J) * 16 * 17, 17, true, -1.0, r);
-    blk_store(o, Wl + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
-  }
-  __syncthreads();
-  const int f = *fail_sh;
-  return f == 0x7fffffff ? 0 : f;
-}
-
-// Blocked variant of chol_inv_tile (same contract).  The tile is processed in
-// four panels of 16 columns.  Panel p lives in wave p (thread (r, q) keeps
-// row r, columns 16q .. 16q+15): wave p factors its 64 x 16 panel alone, with
-// cross-lane reads and no barrier; the panel goes to LDS; the waves to its
-// right apply the rank-16 update to their columns.  The inverse then follows
-// blockwise: the four 16 x 16 diagonal blocks are inverted in parallel (one
-// per wave), and the off-diagonal blocks come from
-// W(I,J) = -W(I,I) * sum_{K=J}^{I-1} L(I,K) W(K,J), level by level, as
-// 16 x 16 x 16 MFMA products.
-__device__ __forceinline__ void mfma_16x16x16(d4& c, const double* A, int lda, bool a_trans, const double* B, int ldb,
-                                              bool b_trans, double sign, int lane) {
-  // c += sign * op(A) * op(B)^T over k = 0..15 with op(A)(m,k) = a_trans ? A[k*lda+m] : A[m*lda+k]
-  // and op(B)(n,k) = b_trans ? B[k*ldb+n] : B[n*ldb+k]; lane supplies row/col lane%16 and k = 4*(lane/16)+s
-  const int mn = lane & 15, kb = (lane >> 4) * 4;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int k = kb + s;
-    const double a = a_trans ? A[k * lda + mn] : A[mn * lda + k];
-    const double b = b_trans ? B[k * ldb + mn] : B[mn * ldb + k];
-    c = mfma16(sign * a, b, c);
-  }
-}
-
-__device__ int chol_inv_tile_blocked(double* S, double* Wl, double* pan /* [64][17] */, int* fail_sh, int tid) {
-  const int r = tid & 63, q = tid >> 6;
-  double s[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) s[m] = S[r * LDS_LD + 16 * q + m];
-  if (tid == 0) *fail_sh = 0x7fffffff;
-  int fail = 0;
-  for (int p = 0; p < 4; ++p) {
-    if (q == p) {
-      // factor the 64 x 16 panel in registers
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int k = 16 * p + m;
-        const double d = rd_lane(s[m], k);
-        const bool ok = (d > 0.0) && (d <= 1.7976931348623157e308);
-        if (!ok && fail == 0) fail = k + 1;
-        const double rinv = rsqrt_refined(d);
-        const double lv = (r > k) ? s[m] * rinv : ((r == k) ? d * rinv : 0.0);
-        s[m] = lv;
-#pragma unroll
-        for (int mm = m + 1; mm < 16; ++mm) s[mm] -= lv * rd_lane(lv, 16 * p + mm);
-      }
-#pragma unroll
-      for (int m = 0; m < 16; ++m) pan[r * 17 + m] = s[m];
-    }
-    __syncthreads();
-    if (q > p) {
-      // rank-16 update of columns 16q .. 16q+15 with panel p
-      double lr[16];
-#pragma unroll
-      for (int m = 0; m < 16; ++m) lr[m] = pan[r * 17 + m];
-#pragma unroll
-      for (int mm = 0; mm < 16; ++mm) {
-        const double* lc = pan + (16 * q + mm) * 17;
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) acc += lr[m] * lc[m];
-        s[mm] -= acc;
-      }
-    }
-    __syncthreads();
-  }
-  if (fail != 0 && (tid & 63) == 0) atomicMin(fail_sh, fail);
-  // L back to LDS (lower, zeros above)
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int c = 16 * q + m;
-    S[r * LDS_LD + c] = (c <= r) ? s[m] : 0.0;
-  }
-  __syncthreads();
-  // ---- W = L^{-1}: diagonal 16 x 16 blocks, one per wave (lanes 0..15 = rows)
-  {
-    const int q0 = 16 * q;
-    double w[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) w[m] = (r == m) ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const double lkk = S[(q0 + k) * LDS_LD + q0 + k];
-      if (r == k) {
-        const double inv = 1.0 / lkk;
-#pragma unroll
-        for (int m = 0; m <= k; ++m) w[m] *= inv;
-      }
-      const double lrk = (r < 16) ? S[(q0 + r) * LDS_LD + q0 + k] : 0.0;
-#pragma unroll
-      for (int m = 0; m <= k; ++m) {
-        const double wk = rd_lane(w[m], k);
-        if (r > k && r < 16) w[m] -= lrk * wk;
-      }
-    }
-    // write W(Q,Q) and zero the rest of the tile's block row Q of W
-    if (r < 16) {
-#pragma unroll
-      for (int m = 0; m < 16; ++m) Wl[(q0 + r) * LDS_LD + q0 + m] = (m <= r) ? w[m] : 0.0;
-    }
-    for (int e = r; e < 16 * 64; e += 64) {
-      const int rr = q0 + (e >> 6), cc = e & 63;
-      if (cc < q0 || cc >= q0 + 16) Wl[rr * LDS_LD + cc] = 0.0;  // off-diagonal blocks are filled below (lower) or stay zero (upper)
-    }
-  }
-  __syncthreads();
-  // ---- off-diagonal blocks, level d = I - J = 1, 2, 3 (block (I, J) by wave J)
-  double* tmp = pan;  // 16 x 17 scratch per wave (pan has 64 x 17)
-  for (int d = 1; d < 4; ++d) {
-    const int J = q, I = q + d;
-    if (I < 4) {
-      const int lane = r;
-      // T = sum_{K=J}^{I-1} L(I,K) W(K,J)
-      d4 t = {0.0, 0.0, 0.0, 0.0};
-      for (int K = J; K < I; ++K)
-        mfma_16x16x16(t, S + (16 * I) * LDS_LD + 16 * K, LDS_LD, false, Wl + (16 * K) * LDS_LD + 16 * J, LDS_LD, true, 1.0, lane);
-      double* Tq = tmp + q * 16 * 17;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) Tq[acc_row(lane, j) * 17 + acc_col(lane)] = t[j];
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
-      // W(I,J) = -W(I,I) T
-      d4 o = {0.0, 0.0, 0.0, 0.0};
-      mfma_16x16x16(o, Wl + (16 * I) * LDS_LD + 16 * I, LDS_LD, false, Tq, 17, true, -1.0, lane);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) Wl[(16 * I + acc_row(lane, j)) * LDS_LD + 16 * J + acc_col(lane)] = o[j];
-    }
-    __syncthreads();
-  }
-  const int f = *fail_sh;
-  return f == 0x7fffffff ? 0 : f;
-}
-
 // In-LDS inverse of a lower-triangular 64 x 64 tile by forward substitution on
 // the identity: thread (r, q) keeps row r, columns 16q .. 16q+15 of the
 // inverse; row k is finished (scaled by 1/L_kk) by lane k of every wave and
@@ -992,17 +547,11 @@ __device__ __forceinline__ void trinv_tile(const double* S, double* w, int tid) 
 }
 
 // ---------------------------------------------------------------------------
-// Cross-workgroup completion flags (one int per tile, 0 = pending).
-// Producer: every wave fences its own global writes at agent scope, then one
-// thread publishes the flag with release semantics.  Consumer: one thread
-// polls with relaxed loads, then an acquire fence makes the producer's writes
-// visible to the whole workgroup (L1 is per CU, L2 per XCD).
-__device__ __forceinline__ void publish_flag(int* flag, int tid) {
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
+// Cross-workgroup completion flags (one int per tile, 0 = pending).  Producer:
+// every wave's stores complete, a barrier, then one thread sets the flag with
+// an agent-scope release.  Consumer: one thread polls with relaxed loads, then
+// an agent-scope acquire makes the producer's writes visible to the whole
+// workgroup (L1 is per CU, L2 per XCD).
 __device__ __forceinline__ bool flag_set(const int* flag) {
   return __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }

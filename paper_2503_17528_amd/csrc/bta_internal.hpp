@@ -19,7 +19,7 @@ constexpr int FACTOR_LOOKAHEAD = 8;
 struct FactorPlan {
   int T, TA, look;
   long long nflags, step_full, step_last, ntasks;
-  size_t off_ctl, off_flags, off_Wd, off_Wt, off_P, off_Pacc, bytes;
+  size_t off_ctl, off_flags, off_Wd, off_Wt, off_P, bytes;
 };
 FactorPlan factor_plan(int64_t n, int64_t b, int64_t a);
 hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
@@ -134,11 +134,33 @@ hipError_t copy2d_launch(const double* src, int64_t lds, int64_t ss, double* dst
                          int rows, int cols, int nb, hipStream_t stream);
 
 int device_cu_count();
-// Library-owned side stream and reusable events of the current device.
-hipStream_t side_stream();
-hipStream_t copy_stream();
-hipStream_t capture_stream();
-hipEvent_t event_at(int k);
+
+// Library-owned streams and events for one call.  Every call that needs more
+// than the caller's stream leases a context for its whole enqueue sequence
+// (SyncLease) and returns it afterwards, so that calls enqueued concurrently by
+// different host threads never record each other's events: a stream wait
+// refers to the record made before it, and a context's next user only records
+// after the previous one has finished enqueueing.  Contexts are created on
+// first need (per device, default-priority non-blocking streams) and kept
+// until the process ends; they hold no device memory.
+struct SyncCtx {
+  int dev = -1;
+  hipStream_t side = nullptr;     // preprocessing and arrow rows of the selected inversion
+  hipStream_t copy = nullptr;     // copy-outs of the backward sweep
+  hipStream_t capture = nullptr;  // graph capture of the batched selected inversion
+  std::vector<hipEvent_t> ev;
+  hipEvent_t event(int k);  // event k of this context (created on demand; nullptr on failure)
+};
+class SyncLease {
+ public:
+  SyncLease();  // takes a free context of the current device (or makes one)
+  ~SyncLease();
+  SyncLease(const SyncLease&) = delete;
+  SyncLease& operator=(const SyncLease&) = delete;
+  SyncCtx* get() const { return ctx_; }  // nullptr if no context could be made
+ private:
+  SyncCtx* ctx_ = nullptr;
+};
 
 // Host dry run: when a recorder is installed on this thread, the launchers
 // above only record what they would touch (no HIP calls).  Used to check

@@ -1,0 +1,71 @@
+/*
+ * bta_testing.h -- internal hooks of libbta.so for the test suite and the
+ * benchmark.  They are not part of the C ABI (include/bta.h): they expose host
+ * replays of the kernels' schedules, measurement switches and single kernels,
+ * and may change without notice.  They are exported (default visibility) only
+ * so that the tests can reach them through ctypes; every other symbol of the
+ * library is hidden.  None of them allocates device memory.
+ */
+#ifndef BTA_TESTING_H
+#define BTA_TESTING_H
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#define BTA_TESTING_API extern "C" __attribute__((visibility("default")))
+
+/* ---- factorization (factor.hip) */
+/* DIAG lookahead in band columns for later factorizations (1..64); returns the
+ * previous value (any other argument only queries). */
+BTA_TESTING_API int bta_internal_factor_lookahead(int look);
+/* Cap on the single-matrix factor kernel's workgroups (0 = one per CU);
+ * returns the previous value (a negative argument only queries). */
+BTA_TESTING_API int bta_internal_factor_max_grid(int g);
+/* bta_factor with a trace buffer of 8 words per ticket (device memory); the
+ * number of records is returned through *ntasks.  Returns 0 on success. */
+BTA_TESTING_API int bta_internal_factor_traced(int64_t n, int64_t b, int64_t a, const double* D, const double* B,
+                                               const double* R, const double* T, double* LD, double* LB, double* LR,
+                                               double* LT, void* work, int64_t* info, unsigned long long* trace,
+                                               long long* ntasks, hipStream_t stream);
+/* 1: the factor kernels read their k-loop operand tiles through the L2 where
+ * the tiles are cache-line aligned; 0: device-coherent loads.  Returns the
+ * previous value (any other argument only queries). */
+BTA_TESTING_API int bta_internal_factor_cached_loads(int on);
+/* Host replay of the single-matrix task schedule (0 = valid); counts[7]
+ * receives the number of tiles of each task type. */
+BTA_TESTING_API int bta_internal_factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts);
+/* Host replay of the batched task interleaving for `num_cus` workgroups
+ * (0 = valid); *ahead receives the largest number of waiting tasks. */
+BTA_TESTING_API int bta_internal_factor_batch_check(int count, const int64_t* n, const int64_t* b, const int64_t* a,
+                                                    int num_cus, long long* ahead);
+
+/* ---- selected inversion (selinv.hip, batched.hip) */
+/* Host dry run of every launch of bta_selinv, out of place and in place: each
+ * operand window inside its array, no launch writing what it reads (0 = valid). */
+BTA_TESTING_API int bta_internal_selinv_dry_check(int64_t n, int64_t b, int64_t a);
+/* Host check of the merged batched plan (0 = valid). */
+BTA_TESTING_API int bta_internal_selinv_batch_check(int count, const int64_t* n, const int64_t* b, const int64_t* a);
+/* Autotuner decisions of this process as "key=choice" lines (up to cap bytes);
+ * returns the number of decisions. */
+BTA_TESTING_API int bta_internal_autotune_dump(char* out, int cap);
+
+/* ---- GEMM engine and measurement (gemm.hip) */
+/* GEMM kernel family of the selected inversion (0 automatic, 1 register-staged,
+ * 2 direct-to-LDS where allowed, 3..7 one direct-to-LDS body); returns the
+ * previous mode (-1 only queries). */
+BTA_TESTING_API int bta_internal_gemm_mode(int mode);
+/* One product through the grouped GEMM: C = beta*Cin + alpha*sum_k A(m,k) B(c,k). */
+BTA_TESTING_API int bta_internal_gemm(int M, int N, int K, const double* A, int64_t lda, int at, const double* B,
+                                      int64_t ldb, int bt, int tri, const double* Cin, double* C, int64_t ldc,
+                                      double alpha, double beta, int store, int lower_tiles, hipStream_t s);
+/* Per-kernel HIP-event timing of the main kernels (on with a pool of
+ * 2*max_launches events, off with on = 0); not thread safe. */
+BTA_TESTING_API int bta_internal_timing(int on, int max_launches);
+/* Per-kind milliseconds and launch counts of the timed spans (0 = complete). */
+BTA_TESTING_API int bta_internal_timing_read(double* ms, long long* launches);
+/* Register-only FP64 MFMA rate probe: grid workgroups of 256 threads, d_out
+ * holds grid*256 doubles; flops = grid * 4 * iters * 8 * 2048. */
+BTA_TESTING_API int bta_internal_mfma_probe(double* d_out, int grid, int iters, hipStream_t s);
+
+#endif /* BTA_TESTING_H */

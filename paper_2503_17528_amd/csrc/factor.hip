@@ -25,13 +25,8 @@
 // or L_{i,i-1}(0,T-1) at c = 0), is the last input of the diagonal tile, so
 // the two are produced together: one k loop accumulates both (they share
 // their left operands) up to k = g-2, then L(g, g-1) = (...) W(g-1)^T is
-// formed and its product added, and the diagonal tile is factored.  In the
-// single-matrix kernel the k loops run as PART tasks (in the DIAG slots of
-// the ticket order) that hand their two partial sums to one chain workgroup,
-// which walks the diagonal tiles in band order and keeps W(g-1) in LDS from
-// one link to the next: the critical path then holds no workgroup hop and no
-// reload of W.  The batched kernel runs each diagonal tile as one DIAG task
-// that does all of it.
+// formed and its product added, and the diagonal tile is factored, all by
+// one DIAG task.
 //
 // Workgroups take task tickets from an atomic counter in a fixed topological
 // order (column by column across the whole band), so a task only ever waits
@@ -43,16 +38,11 @@
 
 #include "bta_device.hpp"
 #include "bta_internal.hpp"
+#include "bta_testing.h"
 
 namespace bta {
 
 enum : int { T_DIAG = 0, T_OFFD = 1, T_SUB = 2, T_ARW = 3, T_TUPD = 4, T_TIPD = 5, T_TIPO = 6 };
-
-// The chain-workgroup schedule is switched off: its first GPU run (n = 1,
-// b = 3, a = 0) did not complete, and no cause has been established yet.
-// With it off, every diagonal tile runs as one DIAG task and the chain code
-// is compiled out of the kernels.
-constexpr bool kFactorChain = false;
 
 struct FactorParams {
   int n, b, a;
@@ -65,17 +55,15 @@ struct FactorParams {
   double* P;       // [n][TA][TA] 64x64 per-step tip updates
   int* flags;      // completion flags
   int* ctl;        // [0..1] 64-bit ticket counter, [2] abort flag
-  int chain;       // 1: diagonal tiles by the chain workgroup (block 0), DIAG tickets run as PART tasks
-  double* Pacc;    // chain: [n][T] the two partial sums of each diagonal tile (2 x 4096, accumulator order)
   int64_t* info;   // caller's info
   long long ntasks;
   long long step_full, step_last;  // tasks per step (with / without SUB)
   int look;                        // DIAG lookahead: DIAG(i,c) is dispatched with column c - look of its step
+  int cached;                      // 1: k-loop operand tiles are read through the L2 (line-aligned tiles only)
   long long spin_limit;
   unsigned long long* trace;  // optional: 8 words per ticket (start, k loop done, end, type | workgroup << 8,
                               // W ready (DIAG: of g-1), L(g,g-1) published (DIAG), tile factored (DIAG),
-                              // end of the last blocking wait in the k loop); chain: then 8 words per
-                              // link (start, partial sums ready, -, L(g,g-1) published, factored, end)
+                              // end of the last blocking wait in the k loop)
 };
 
 struct Task {
@@ -96,9 +84,6 @@ __host__ __device__ inline int64_t fl_U(const FactorParams& p, int i, int r, int
 }
 __host__ __device__ inline int64_t fl_tip(const FactorParams& p, int r, int c) {
   return fl_D(p, p.n, 0, 0) + (int64_t)r * p.TA + c;
-}
-__host__ __device__ inline int64_t fl_part(const FactorParams& p, int i, int c) {
-  return fl_D(p, p.n, 0, 0) + (int64_t)p.TA * p.TA + (int64_t)i * p.T + c;
 }
 
 __host__ __device__ __forceinline__ Task decode(const FactorParams& p, long long t) {
@@ -384,8 +369,8 @@ __device__ __forceinline__ void diag_partials(const FactorParams& p, const Task&
     ksources(p, pt, 0, &s0);
     if (!wait_ready(p, s0.fa, s0.fb, sh, tid)) aborted = true;
     upto = 1;
-    tile_load_lds_dev(sh.u.stage[0][0], s0.a, tid);
-    tile_load_lds_dev(sh.u.stage[0][1], s0.b, tid);
+    tile_load_lds_dev(sh.u.stage[0][0], s0.a, tid, p.cached != 0);
+    tile_load_lds_dev(sh.u.stage[0][1], s0.b, tid, p.cached != 0);
     for (int kk = 0; kk < nk && !aborted; ++kk) {
       if (tid < 64) {
         const int u = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, pt, kk + 1, nk, tid) : upto;
@@ -403,8 +388,8 @@ __device__ __forceinline__ void diag_partials(const FactorParams& p, const Task&
           if (rec && tid == 0) rec[7] = __builtin_amdgcn_s_memrealtime();
           upto = kk + 2;
         }
-        tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][0], sn.a, tid);
-        tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][1], sn.b, tid);
+        tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][0], sn.a, tid, p.cached != 0);
+        tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][1], sn.b, tid, p.cached != 0);
       }
       mma_ptile2(acc1, acc2, sh.u.stage[kk & 1][0], sh.u.stage[kk & 1][1], tid);
     }
@@ -478,10 +463,10 @@ __device__ __forceinline__ void syrk_lower(double* S, const double* X, int tid) 
 // The rest of diagonal tile g = (i, c) from its partial sums: L(g,g-1) =
 // -acc2 W(g-1)^T is stored and published, acc1 += L(g,g-1) L(g,g-1)^T, and the
 // diagonal tile is factored and inverted (L and W stored, flag published).
-// W(g-1) is loaded once its flag is set, or is already in sh.u.f.Bs (chain).
+// W(g-1) is loaded once its flag is set.
 // rec (optional): [0] W(g-1) ready, [1] L(g,g-1) published, [2] tile factored.
 __device__ __forceinline__ void diag_finish(const FactorParams& p, int i, int c, Shared& sh, int tid, Acc& acc1,
-                                            Acc& acc2, bool w_in_lds, unsigned long long* rec) {
+                                            Acc& acc2, unsigned long long* rec) {
   const int T = p.T, b = p.b;
   const int64_t bb = (int64_t)b * b;
   const int rows = ext(b, c);
@@ -512,16 +497,12 @@ __device__ __forceinline__ void diag_finish(const FactorParams& p, int i, int c,
   __builtin_amdgcn_s_setprio(3);
 
   if (has_pre) {
-    if (!w_in_lds) {
-      wait_ready(p, fWp, fWp, sh, tid);
-      if (rec && tid == 0) rec[0] = __builtin_amdgcn_s_memrealtime();
-      Stage rw;
-      stage_load_dev(rw, OpTile{Wp, 64, 64, 64, false}, tid);
-      acc_to_lds(acc2, sh.u.f.As, tid);
-      stage_store(rw, sh.u.f.Bs, tid);
-    } else {
-      acc_to_lds(acc2, sh.u.f.As, tid);
-    }
+    wait_ready(p, fWp, fWp, sh, tid);
+    if (rec && tid == 0) rec[0] = __builtin_amdgcn_s_memrealtime();
+    Stage rw;
+    stage_load_dev(rw, OpTile{Wp, 64, 64, 64, false}, tid);
+    acc_to_lds(acc2, sh.u.f.As, tid);
+    stage_store(rw, sh.u.f.Bs, tid);
     __syncthreads();
     // x = -L(g,g-1) = acc2 W(g-1)^T, W lower triangular
     const int w = tid >> 6, lane = tid & 63, rb = 2 * (w & 1);
@@ -565,7 +546,7 @@ __device__ __forceinline__ void diag_finish(const FactorParams& p, int i, int c,
   }
 
   // factor and invert A(g,g) - sum over all k < g
-  const int f = uni(chol_inv_tile_mfma<2>(sh.u.f.As, sh.u.f.Bs, sh.rinv, sh.pan, &sh.fail, tid));
+  const int f = uni(chol_inv_tile_mfma(sh.u.f.As, sh.u.f.Bs, sh.rinv, sh.pan, &sh.fail, tid));
   if (rec && tid == 0) rec[2] = __builtin_amdgcn_s_memrealtime();
   if (f != 0 && f <= rows && tid == 0) {
     const long long row0 = (long long)i * b + (long long)c * 64;
@@ -593,58 +574,7 @@ __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, S
   Acc acc1, acc2;
   diag_partials(p, t, sh, tid, acc1, acc2, rec);
   if (rec && tid == 0) tr1 = __builtin_amdgcn_s_memrealtime();
-  diag_finish(p, t.i, t.c, sh, tid, acc1, acc2, false, rec ? rec + 4 : nullptr);
-}
-
-// Partial sums of a diagonal tile for the chain: element e of thread tid of
-// acc1 (acc2) at Pacc[g][e * 256 + tid] (+ 4096), so that every store and load
-// instruction covers 2 KB of consecutive addresses.
-__device__ __forceinline__ void part_store(const Acc& c, double* P, int tid) {
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) st_dev(P + ((bi * 2 + bj) * 4 + j) * NT + tid, c.v[bi][bj][j]);
-}
-__device__ __forceinline__ void part_load(Acc& c, const double* P, int tid) {
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) c.v[bi][bj][j] = ld_dev(P + ((bi * 2 + bj) * 4 + j) * NT + tid);
-}
-
-__device__ __forceinline__ void run_part(const FactorParams& p, const Task& t, Shared& sh, int tid,
-                                         unsigned long long& tr1, unsigned long long* rec) {
-  Acc acc1, acc2;
-  diag_partials(p, t, sh, tid, acc1, acc2, rec);
-  if (rec && tid == 0) tr1 = __builtin_amdgcn_s_memrealtime();
-  double* P = p.Pacc + ((int64_t)t.i * p.T + t.c) * 8192;
-  part_store(acc1, P, tid);
-  part_store(acc2, P + 4096, tid);
-  publish(p.flags + fl_part(p, t.i, t.c), tid);
-}
-
-// The chain workgroup: diagonal tiles in band order.  Returns false on abort.
-__device__ __forceinline__ bool chain_run(const FactorParams& p, Shared& sh, int tid) {
-  for (int i = 0; i < p.n; ++i) {
-    for (int c = 0; c < p.T; ++c) {
-      unsigned long long* rec = p.trace ? p.trace + 8 * (p.ntasks + (long long)i * p.T + c) : nullptr;
-      if (rec && tid == 0) rec[0] = __builtin_amdgcn_s_memrealtime();
-      const int* fp = p.flags + fl_part(p, i, c);
-      if (!wait_ready(p, fp, fp, sh, tid)) return false;
-      Acc acc1, acc2;
-      const double* P = p.Pacc + ((int64_t)i * p.T + c) * 8192;
-      part_load(acc1, P, tid);
-      part_load(acc2, P + 4096, tid);
-      if (rec && tid == 0) rec[1] = __builtin_amdgcn_s_memrealtime();
-      diag_finish(p, i, c, sh, tid, acc1, acc2, true, rec ? rec + 2 : nullptr);
-      if (rec && tid == 0) rec[5] = __builtin_amdgcn_s_memrealtime();
-    }
-  }
-  return true;
+  diag_finish(p, t.i, t.c, sh, tid, acc1, acc2, rec ? rec + 4 : nullptr);
 }
 
 // One task of one matrix: accumulate, finish, publish.
@@ -656,8 +586,7 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
     if (p.trace && tid == 0) tr0 = __builtin_amdgcn_s_memrealtime();
     if (t.type == T_DIAG) {
       unsigned long long* rec = p.trace ? p.trace + 8 * tk : nullptr;
-      if (kFactorChain && p.chain) run_part(p, t, sh, tid, tr1, rec);
-      else run_diag(p, t, sh, tid, tr1, rec);
+      run_diag(p, t, sh, tid, tr1, rec);
       if (rec && tid == 0) {
         rec[0] = tr0;
         rec[1] = tr1;
@@ -756,8 +685,8 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
       ksources(p, t, 0, &s0);
       if (!wait_ready(p, s0.fa, s0.fb, sh, tid)) aborted = true;
       upto = 1;
-      tile_load_lds_dev(sh.u.stage[0][0], s0.a, tid);
-      tile_load_lds_dev(sh.u.stage[0][1], s0.b, tid);
+      tile_load_lds_dev(sh.u.stage[0][0], s0.a, tid, p.cached != 0);
+      tile_load_lds_dev(sh.u.stage[0][1], s0.b, tid, p.cached != 0);
       for (int kk = 0; kk < nk && !aborted; ++kk) {
         if (tid < 64) {
           const int u = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, t, kk + 1, nk, tid) : upto;
@@ -775,8 +704,8 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
             if (p.trace && tid == 0) p.trace[8 * tk + 7] = __builtin_amdgcn_s_memrealtime();
             upto = kk + 2;
           }
-          tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][0], sn.a, tid);
-          tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][1], sn.b, tid);
+          tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][0], sn.a, tid, p.cached != 0);
+          tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][1], sn.b, tid, p.cached != 0);
         }
         mma_ptile(acc, sh.u.stage[kk & 1][0], sh.u.stage[kk & 1][1], tid);
       }
@@ -797,7 +726,7 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
 #pragma unroll
           for (int j = 0; j < 4; ++j) sh.u.f.As[tile_row(tid, bi, j) * LDS_LD + tile_col(tid, bj)] = -acc.v[bi][bj][j];
       __syncthreads();
-      const int f = uni(chol_inv_tile_mfma<2>(sh.u.f.As, sh.u.f.Bs, sh.rinv, sh.pan, &sh.fail, tid));
+      const int f = uni(chol_inv_tile_mfma(sh.u.f.As, sh.u.f.Bs, sh.rinv, sh.pan, &sh.fail, tid));
       if (f != 0 && f <= rows && tid == 0) {
         const long long row0 = (long long)p.n * b + (long long)t.c * 64;
         atomicMin((unsigned long long*)p.info, (unsigned long long)(row0 + f));
@@ -848,10 +777,6 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
 // Persistent workers: take tickets until the task list is exhausted.
 __device__ __forceinline__ void factor_worker(const FactorParams& p, Shared& sh) {
   const int tid = threadIdx.x;
-  if (kFactorChain && p.chain && blockIdx.x == 0) {
-    chain_run(p, sh, tid);
-    return;
-  }
   for (;;) {
     if (tid == 0) sh.ticket = (long long)atomicAdd((unsigned long long*)p.ctl, 1ULL);
     __syncthreads();
@@ -954,13 +879,24 @@ static int g_factor_look = FACTOR_LOOKAHEAD;
 constexpr int BATCH_LOOKAHEAD = 2;
 // Upper bound on the factor kernel's workgroups (internal, for measurements; 0: one per CU).
 static int g_factor_max_grid = 0;
+// k-loop operands through the L2 where the tiles are line-aligned (internal switch).
+static int g_factor_cached = 0;
+
+// Whether every operand tile of a factorization starts its rows on 128-byte
+// cache lines: the L arrays 128-byte aligned and their leading dimensions
+// (b, and a for the tip) multiples of 16 doubles.
+static bool factor_lines_aligned(int64_t b, int64_t a, const double* LD, const double* LB, const double* LR,
+                                 const double* LT) {
+  auto al = [](const void* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) & 127) == 0; };
+  return b % 16 == 0 && (a == 0 || a % 16 == 0) && al(LD) && al(LB) && al(LR) && al(LT);
+}
 
 FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   FactorPlan fp{};
   const int64_t T = (b + 63) / 64, TA = (a + 63) / 64;
   fp.T = (int)T;
   fp.TA = (int)TA;
-  fp.nflags = n * (2 * T * T + TA * T + TA * TA) + TA * TA + n * T;  // ..., tip tiles, PART tasks
+  fp.nflags = n * (2 * T * T + TA * T + TA * TA) + TA * TA;  // per step D, B, R and tip-update tiles; tip tiles
   // per step: DIAG + OFFD tasks T(T-1)/2 + 1 (the T-1 tiles L_ii(c+1,c) are
   // computed by DIAG tasks), SUB T*T - 1 (L_{i+1,i}(0,T-1) likewise), ARW, TUPD
   fp.step_full = T * (T - 1) / 2 + 1 + T * T - 1 + T * TA + TA * (TA + 1) / 2;
@@ -974,7 +910,6 @@ FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   fp.off_Wd = take(sizeof(double) * 4096 * (size_t)(n * T));
   fp.off_Wt = take(sizeof(double) * 4096 * (size_t)(TA > 0 ? TA : 1));
   fp.off_P = take(sizeof(double) * 4096 * (size_t)(n * TA * TA > 0 ? n * TA * TA : 1));
-  fp.off_Pacc = take(sizeof(double) * 8192 * (size_t)(n * T));  // single-matrix kernel only
   fp.bytes = off;
   return fp;
 }
@@ -998,19 +933,17 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
   p.step_full = fp.step_full;
   p.step_last = fp.step_last;
   p.look = fp.look;
+  p.cached = (g_factor_cached && factor_lines_aligned(b, a, LD, LB, LR, LT)) ? 1 : 0;
   p.trace = trace;
   p.spin_limit = 1LL << 22;  // a few seconds of polling without progress before the watchdog fires
-  // chain workgroup when, besides it, more workgroups than the lookahead bound are resident
-  p.chain = (kFactorChain && num_cus >= fp.look + 3) ? 1 : 0;
-  p.Pacc = reinterpret_cast<double*>(w + fp.off_Pacc);
   const int rgrid = (int)std::min<long long>(1024, (fp.nflags + 255) / 256 + 1);
   hipLaunchKernelGGL(factor_reset_kernel, dim3(rgrid), dim3(256), 0, stream, p.flags, fp.nflags, p.ctl, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   long long cap = num_cus;
   if (g_factor_max_grid > 0) cap = std::min<long long>(cap, g_factor_max_grid);
-  const long long grid = std::min<long long>(fp.ntasks + p.chain, cap);
-  if (grid - p.chain < fp.ntasks && grid - p.chain <= fp.look + 1) return hipErrorInvalidConfiguration;  // lookahead needs more workers
+  const long long grid = std::min<long long>(fp.ntasks, cap);
+  if (grid < fp.ntasks && grid <= fp.look + 1) return hipErrorInvalidConfiguration;  // lookahead needs more workers
   timing_mark(KT_FACTOR, true, stream);
   hipLaunchKernelGGL(factor_kernel, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, p);
   timing_mark(KT_FACTOR, false, stream);
@@ -1119,7 +1052,7 @@ FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b,
   for (int m = 0; m < count; ++m) {
     const FactorPlan& fp = bp.plans[m];
     bp.ws_off[m][0] = take(fp.off_P - fp.off_Wd);          // Wd + Wt
-    bp.ws_off[m][1] = take(fp.off_Pacc - fp.off_P);        // P
+    bp.ws_off[m][1] = take(fp.bytes - fp.off_P);           // P
   }
   bp.bytes = off;
   long long t = 0;
@@ -1159,9 +1092,8 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
     p.step_last = fp.step_last;
     p.look = fp.look;
     p.spin_limit = 1LL << 22;
+    p.cached = (g_factor_cached && factor_lines_aligned(p.b, p.a, p.LD, p.LB, p.LR, p.LT)) ? 1 : 0;
     p.trace = nullptr;
-    p.chain = 0;
-    p.Pacc = nullptr;
   }
   std::vector<int64_t> ns(bp.count);
   for (int m = 0; m < bp.count; ++m) ns[m] = mats[m].n;
@@ -1258,19 +1190,10 @@ int factor_schedule_replay(int64_t n, int64_t b, int64_t a, int look, long long*
       owner[(size_t)pf] = tk;
       cnt[t.c > 0 ? T_OFFD : T_SUB]++;
     }
-    if (t.type == T_DIAG) {  // single-matrix kernel: the PART task's hand-off flag
-      const int64_t qf = fl_part(p, t.i, t.c);
-      if (qf < 0 || qf >= fp.nflags || owner[(size_t)qf] != -1) return 3;
-      owner[(size_t)qf] = tk;
-    }
   }
   // pass 2: dependencies.  A task other than DIAG waits only on tasks with
   // smaller tickets; a DIAG task (dispatched up to `look` columns early) waits
-  // only on tasks of smaller rank.  With the chain workgroup the outputs of a
-  // diagonal tile come from the chain once the PART task in its DIAG slot is
-  // done, and the chain needs nothing else but the previous link: ownership by
-  // that ticket is the same relation, so the same checks cover both kernels
-  // (the chain is one extra resident workgroup).  Together with the bound on the number of
+  // only on tasks of smaller rank.  Together with the bound on the number of
   // DIAG tasks ahead of the in-order frontier (checked below) this keeps the
   // schedule deadlock free whenever more workgroups than that bound are resident.
   std::vector<long long> maxdep((size_t)fp.ntasks, -1);  // largest ticket a task waits on
@@ -1351,29 +1274,38 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
 
 // Internal: DIAG lookahead in columns for later factorizations (1..64);
 // returns the previous value (any other argument only queries).
-extern "C" __attribute__((visibility("default"))) int bta_internal_factor_lookahead(int look) {
+BTA_TESTING_API int bta_internal_factor_lookahead(int look) {
   const int prev = bta::g_factor_look;
   if (look >= 1 && look <= 64) bta::g_factor_look = look;
   return prev;
 }
 
+// Internal: 1 reads the k-loop operand tiles through the L2 where they are
+// line-aligned, 0 with device-coherent loads; returns the previous value (any
+// other argument only queries).
+BTA_TESTING_API int bta_internal_factor_cached_loads(int on) {
+  const int prev = bta::g_factor_cached;
+  if (on == 0 || on == 1) bta::g_factor_cached = on;
+  return prev;
+}
+
 // Internal: cap on the single-matrix factor kernel's workgroups (0 = one per
 // CU); returns the previous value (a negative argument only queries).
-extern "C" __attribute__((visibility("default"))) int bta_internal_factor_max_grid(int g) {
+BTA_TESTING_API int bta_internal_factor_max_grid(int g) {
   const int prev = bta::g_factor_max_grid;
   if (g >= 0) bta::g_factor_max_grid = g;
   return prev;
 }
 
 // bta_factor with a trace buffer of 8 words per record (device memory): one
-// record per ticket, then one per chain link (n * ceil(b/64)); the number of
-// records is returned through *ntasks when the pointer is set.
-extern "C" __attribute__((visibility("default"))) int bta_internal_factor_traced(
+// record per ticket; the number of records is returned through *ntasks when
+// the pointer is set.
+BTA_TESTING_API int bta_internal_factor_traced(
     int64_t n, int64_t b, int64_t a, const double* D, const double* B, const double* R, const double* T, double* LD,
     double* LB, double* LR, double* LT, void* work, int64_t* info, unsigned long long* trace, long long* ntasks,
     hipStream_t stream) {
   const bta::FactorPlan fp = bta::factor_plan(n, b, a);
-  if (ntasks) *ntasks = fp.ntasks + n * fp.T;
+  if (ntasks) *ntasks = fp.ntasks;
   if (!trace) return 0;
   return bta::factor_launch(fp, n, b, a, D, B, R, T, LD, LB, LR, LT, work, info, stream, bta::device_cu_count(), trace) ==
                  hipSuccess
@@ -1389,7 +1321,7 @@ extern "C" __attribute__((visibility("default"))) int bta_internal_factor_traced
 // has more dispatched tasks waiting on a larger ticket than the launch's bound
 // (itself below the number of workgroups).  *ahead (optional) receives the
 // replay's maximum.  Returns 0 or an error code.
-extern "C" __attribute__((visibility("default"))) int bta_internal_factor_batch_check(int count, const int64_t* n,
+BTA_TESTING_API int bta_internal_factor_batch_check(int count, const int64_t* n,
                                                                                        const int64_t* b, const int64_t* a,
                                                                                        int num_cus, long long* ahead) {
   const bta::FactorBatchPlan bp = bta::factor_batch_plan(count, n, b, a, num_cus);
@@ -1466,7 +1398,7 @@ extern "C" __attribute__((visibility("default"))) int bta_internal_factor_batch_
   return 0;
 }
 
-extern "C" __attribute__((visibility("default"))) int bta_internal_factor_schedule_check(int64_t n, int64_t b, int64_t a,
+BTA_TESTING_API int bta_internal_factor_schedule_check(int64_t n, int64_t b, int64_t a,
                                                                                           long long* counts) {
   return bta::factor_schedule_check(n, b, a, counts);
 }

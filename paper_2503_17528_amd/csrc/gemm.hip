@@ -11,6 +11,7 @@
 
 #include "bta_device.hpp"
 #include "bta_internal.hpp"
+#include "bta_testing.h"
 
 namespace bta {
 
@@ -1114,7 +1115,7 @@ int device_cu_count() {
 
 // Internal timing controls (not part of the public header): enable with a
 // pool of event pairs, read back per-kind total milliseconds and launch counts.
-extern "C" __attribute__((visibility("default"))) int bta_internal_timing(int on, int max_launches) {
+BTA_TESTING_API int bta_internal_timing(int on, int max_launches) {
   using namespace bta;
   for (hipEvent_t e : g_timer.pool) (void)hipEventDestroy(e);
   g_timer.pool.clear();
@@ -1130,7 +1131,7 @@ extern "C" __attribute__((visibility("default"))) int bta_internal_timing(int on
 }
 
 // Internal GEMM kernel selection (see g_gemm_mode); returns the previous mode.
-extern "C" __attribute__((visibility("default"))) int bta_internal_gemm_mode(int mode) {
+BTA_TESTING_API int bta_internal_gemm_mode(int mode) {
   const int prev = bta::g_gemm_mode;
   if (mode >= 0 && mode <= 7) bta::g_gemm_mode = mode;
   return prev;
@@ -1139,7 +1140,7 @@ extern "C" __attribute__((visibility("default"))) int bta_internal_gemm_mode(int
 // Internal: one product through the grouped GEMM (tests and measurements):
 // C = beta * Cin + alpha * sum_k A(m,k) B(c,k), operand layouts and k range as
 // in the selected inversion's problems.  Returns a HIP error code.
-extern "C" __attribute__((visibility("default"))) int bta_internal_gemm(
+BTA_TESTING_API int bta_internal_gemm(
     int M, int N, int K, const double* A, int64_t lda, int at, const double* B, int64_t ldb, int bt, int tri,
     const double* Cin, double* C, int64_t ldc, double alpha, double beta, int store, int lower_tiles, hipStream_t s) {
   bta::GProb p{};
@@ -1152,7 +1153,39 @@ extern "C" __attribute__((visibility("default"))) int bta_internal_gemm(
   return (int)bta::gemm_launch(&p, 1, s);
 }
 
-extern "C" __attribute__((visibility("default"))) int bta_internal_timing_read(double* ms, long long* launches) {
+namespace bta {
+// Register-only FP64 MFMA loop: every wave runs `iters` rounds of eight
+// independent v_mfma_f64_16x16x4_f64 chains with no memory traffic inside the
+// loop, so the launch measures the sustained FP64 matrix rate of the device
+// (2048 flops per instruction).  Each thread stores one sum, which keeps the
+// chains live.
+__global__ __launch_bounds__(256) void mfma_probe_kernel(double* out, int iters) {
+  const int lane = threadIdx.x & 63;
+  const double a = 1.0 + 1e-3 * lane, b = 1.0 - 1e-3 * lane;
+  d4 c[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) c[j] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) c[j] = mfma16(a, b, c[j]);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s += c[j][0] + c[j][1] + c[j][2] + c[j][3];
+  out[(size_t)blockIdx.x * 256 + threadIdx.x] = s;
+}
+}  // namespace bta
+
+// Internal: launch the MFMA rate probe with `grid` workgroups of 256 threads
+// on `s`; d_out holds grid * 256 doubles.  Flops = grid * 4 * iters * 8 * 2048.
+BTA_TESTING_API int bta_internal_mfma_probe(double* d_out, int grid, int iters,
+                                                                               hipStream_t s) {
+  if (!d_out || grid < 1 || iters < 1) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(bta::mfma_probe_kernel, dim3((unsigned)grid), dim3(256), 0, s, d_out, iters);
+  return (int)hipGetLastError();
+}
+
+BTA_TESTING_API int bta_internal_timing_read(double* ms, long long* launches) {
   using namespace bta;
   for (int k = 0; k < KT_COUNT; ++k) { ms[k] = 0.0; launches[k] = 0; }
   for (auto& sp : g_timer.spans) {

@@ -26,6 +26,7 @@
 
 #include "bta_device.hpp"
 #include "bta_internal.hpp"
+#include "bta_testing.h"
 
 namespace bta {
 
@@ -121,56 +122,50 @@ static hipError_t trtri_batched(const double* L, int64_t ldL, int64_t sL, double
   return hipSuccess;
 }
 
-// Library-owned side stream and events (one set per device, default priority,
-// created on first use; no device memory).
+// ---------------------------------------------------------------- per-call stream contexts
 namespace {
-struct DevSync {
-  hipStream_t side = nullptr;
-  hipStream_t copy = nullptr;
-  hipStream_t capture = nullptr;
-  std::vector<hipEvent_t> ev;
-};
 std::mutex g_sync_mu;
-std::map<int, DevSync> g_sync;
+std::map<int, std::vector<SyncCtx*>> g_sync_free;  // idle contexts per device
 }  // namespace
 
-hipStream_t side_stream() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  std::lock_guard<std::mutex> lk(g_sync_mu);
-  DevSync& d = g_sync[dev];
-  if (!d.side && hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking) != hipSuccess) d.side = nullptr;
-  return d.side;
-}
-
-hipStream_t copy_stream() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  std::lock_guard<std::mutex> lk(g_sync_mu);
-  DevSync& d = g_sync[dev];
-  if (!d.copy && hipStreamCreateWithFlags(&d.copy, hipStreamNonBlocking) != hipSuccess) d.copy = nullptr;
-  return d.copy;
-}
-hipStream_t capture_stream() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  std::lock_guard<std::mutex> lk(g_sync_mu);
-  DevSync& d = g_sync[dev];
-  if (!d.capture && hipStreamCreateWithFlags(&d.capture, hipStreamNonBlocking) != hipSuccess) d.capture = nullptr;
-  return d.capture;
-}
-
-hipEvent_t event_at(int k) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  std::lock_guard<std::mutex> lk(g_sync_mu);
-  DevSync& d = g_sync[dev];
-  while ((int)d.ev.size() <= k) {
+hipEvent_t SyncCtx::event(int k) {
+  while ((int)ev.size() <= k) {
     hipEvent_t e;
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
-    d.ev.push_back(e);
+    ev.push_back(e);
   }
-  return d.ev[k];
+  return ev[k];
+}
+
+SyncLease::SyncLease() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  {
+    std::lock_guard<std::mutex> lk(g_sync_mu);
+    std::vector<SyncCtx*>& fr = g_sync_free[dev];
+    if (!fr.empty()) {
+      ctx_ = fr.back();
+      fr.pop_back();
+      return;
+    }
+  }
+  SyncCtx* c = new SyncCtx;
+  c->dev = dev;
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->copy, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) {
+    for (hipStream_t st : {c->side, c->copy, c->capture})
+      if (st) (void)hipStreamDestroy(st);
+    delete c;
+    return;
+  }
+  ctx_ = c;
+}
+
+SyncLease::~SyncLease() {
+  if (!ctx_) return;
+  std::lock_guard<std::mutex> lk(g_sync_mu);
+  g_sync_free[ctx_->dev].push_back(ctx_);
 }
 
 SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a) {
@@ -249,9 +244,12 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
   // fill the CUs the sweep leaves idle; each step of the sweep waits for its
   // own block only (an event per block, after its arrow row).
   const bool dry = recording();
-  hipStream_t sa = dry ? s : side_stream();
+  SyncLease lease;  // this call's side stream, copy stream and events
+  SyncCtx* cx = lease.get();
+  if (!dry && !cx) return hipErrorInvalidResourceHandle;
+  auto event_at = [cx](int k) { return cx->event(k); };
+  hipStream_t sa = dry ? s : cx->side;
   if (!dry) {
-    if (!sa) return hipErrorInvalidResourceHandle;
     BTA_TRY(hipEventRecord(event_at(0), s));
     BTA_TRY(hipStreamWaitEvent(sa, event_at(0), 0));
   }
@@ -324,8 +322,7 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
   // P_B (the X_{i+1,i} slot) runs on a copy stream after the step's second
   // product, off the sweep's critical path, and the buffer is reused two steps
   // later.
-  hipStream_t sc = dry ? s : copy_stream();
-  if (!dry && !sc) return hipErrorInvalidResourceHandle;
+  hipStream_t sc = dry ? s : cx->copy;
   const int E0 = 1 + (int)n;
   for (int64_t i = n - 1; i >= 0; --i) {
     // block i's preprocessing and arrow row
@@ -442,6 +439,6 @@ int selinv_dry_check(int64_t n, int64_t b, int64_t a) {
 
 }  // namespace bta
 
-extern "C" __attribute__((visibility("default"))) int bta_internal_selinv_dry_check(int64_t n, int64_t b, int64_t a) {
+BTA_TESTING_API int bta_internal_selinv_dry_check(int64_t n, int64_t b, int64_t a) {
   return bta::selinv_dry_check(n, b, a);
 }
