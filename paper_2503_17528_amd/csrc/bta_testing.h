@@ -32,6 +32,10 @@ BTA_TESTING_API int bta_internal_factor_traced(int64_t n, int64_t b, int64_t a, 
  * the tiles are cache-line aligned; 0: device-coherent loads.  Returns the
  * previous value (any other argument only queries). */
 BTA_TESTING_API int bta_internal_factor_cached_loads(int on);
+/* The pivot reciprocal square root of the diagonal-tile Cholesky
+ * (hardware estimate + one third-order refinement) applied to count device
+ * doubles: d_out[k] = rsqrt_refined(d_in[k]).  Returns 0 on launch success. */
+BTA_TESTING_API int bta_internal_rsqrt(const double* d_in, double* d_out, int64_t count, hipStream_t s);
 /* Host replay of the single-matrix task schedule (0 = valid); counts[7]
  * receives the number of tiles of each task type. */
 BTA_TESTING_API int bta_internal_factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts);

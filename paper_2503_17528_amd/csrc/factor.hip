@@ -1402,3 +1402,19 @@ BTA_TESTING_API int bta_internal_factor_schedule_check(int64_t n, int64_t b, int
                                                                                           long long* counts) {
   return bta::factor_schedule_check(n, b, a, counts);
 }
+
+namespace bta {
+// rsqrt_refined applied elementwise (the pivot reciprocal square root of the
+// diagonal-tile Cholesky), for the error-bound test.
+__global__ __launch_bounds__(256) void rsqrt_probe_kernel(const double* in, double* out, int64_t count) {
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < count; k += (int64_t)gridDim.x * 256)
+    out[k] = rsqrt_refined(in[k]);
+}
+}  // namespace bta
+
+BTA_TESTING_API int bta_internal_rsqrt(const double* d_in, double* d_out, int64_t count, hipStream_t s) {
+  if (!d_in || !d_out || count < 1) return (int)hipErrorInvalidValue;
+  const unsigned grid = (unsigned)std::min<int64_t>(4096, (count + 255) / 256);
+  hipLaunchKernelGGL(bta::rsqrt_probe_kernel, dim3(grid), dim3(256), 0, s, d_in, d_out, count);
+  return (int)hipGetLastError();
+}

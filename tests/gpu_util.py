@@ -1,13 +1,18 @@
 """Helpers shared by the GPU parity tests (device tensors <-> oracle blocks)."""
 import sys
+import time
 
 import numpy as np
 
 TOL = 1e-10  # relative Frobenius error per block
 
 
+_T0 = time.perf_counter()
+
+
 def say(*args):
-    print(*args, flush=True)
+    """Progress line with the seconds since the GPU tests started."""
+    print(f"[{time.perf_counter() - _T0:7.1f}s]", *args, flush=True)
     sys.stdout.flush()
 
 

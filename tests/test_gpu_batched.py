@@ -61,24 +61,30 @@ def test_small_mixed_batch(torch_cuda, inplace):
 
 def test_hyperparameter_sweep_batch(torch_cuda):
     """64 matrices, n ~ U{16..96}, b in {128, 256, 384}, a in {2, 4, 6}: every
-    matrix against the oracle, on the first call (eager, autotuned) and on the
-    second (graph replay)."""
+    block of every matrix's L against the factor its input was drawn from, and
+    every block of every matrix's Sigma against the oracle's Algorithm 2 run on
+    that factor, on the first call (eager, autotuned) and on the second (graph
+    replay)."""
     torch = torch_cuda
+    from threadpoolctl import threadpool_limits
+
     from paper_2503_17528_amd import bta
 
     wls = synth.batched_workloads(0)
     say(f"case batched sweep: {len(wls)} matrices, {sum(w.block_bytes() for w in wls) / 1e9:.2f} GB")
-    mats = [synth.make_torch(w, 100 + k, "cuda") for k, w in enumerate(wls)]
+    full = [synth.make_torch(w, 100 + k, "cuda", with_factor=True) for k, w in enumerate(wls)]
+    mats = [{k: f[k] for k in "DBRT"} for f in full]
     batch = bta.Batch(mats)
     ref = []
-    for m in range(len(wls)):
-        Q = {k: mats[m][k].cpu().numpy() for k in "DBRT"}
-        F = oracle.pobtaf(Q["D"], Q["B"], Q["R"], Q["T"])
-        assert F["info"] == 0
-        Xo = oracle.pobtasi(F["LD"], F["LB"], F["LR"], F["LT"])
-        ref.append(({"D": F["LD"], "B": F["LB"], "R": F["LR"], "T": F["LT"]},
-                    {"D": Xo["XD"], "B": Xo["XB"], "R": Xo["XR"], "T": Xo["XT"]}))
-    say("   oracle done for every matrix")
+    # small blocks: one BLAS thread per call is several times faster than many
+    with threadpool_limits(1):
+        for m in range(len(wls)):
+            Lh = {k: full[m][k].cpu().numpy() for k in ("LD", "LB", "LR", "LT")}
+            Xo = oracle.pobtasi(Lh["LD"], Lh["LB"], Lh["LR"], Lh["LT"])
+            ref.append(({"D": Lh["LD"], "B": Lh["LB"], "R": Lh["LR"], "T": Lh["LT"]},
+                        {"D": Xo["XD"], "B": Xo["XB"], "R": Xo["XR"], "T": Xo["XT"]}))
+            if m % 16 == 15:
+                say(f"   oracle done for {m + 1} matrices")
     for call in range(2):
         for L in batch.X:
             for t in L:
