@@ -172,25 +172,30 @@ def kernel_line(L, steps):
 
 
 def mfma_probe(torch, L, dev):
-    """Sustained FP64 MFMA rate of this device: a register-only MFMA loop on
-    every CU (bta_internal_mfma_probe), timed with events on the current stream."""
-    L.bta_internal_mfma_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    """Sustained FP64 MFMA rate of this device: a register-only MFMA loop
+    (bta_internal_mfma_probe) at 2, 4 and 8 workgroups per CU with 8 and 16
+    independent chains per wave, timed with events on the current stream; the
+    best configuration's rate."""
+    L.bta_internal_mfma_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
     L.bta_internal_mfma_probe.restype = ctypes.c_int
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
-    grid, iters = 2 * cus, 20000
-    out = torch.empty(grid * 256, dtype=torch.float64, device=dev)
+    iters = 4000
+    out = torch.empty(8 * cus * 256, dtype=torch.float64, device=dev)
     s = torch.cuda.current_stream().cuda_stream
     best = 0.0
-    for _ in range(3):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        rc = L.bta_internal_mfma_probe(out.data_ptr(), grid, iters, s)
-        e1.record()
-        torch.cuda.synchronize()
-        if rc != 0:
-            return None
-        best = max(best, grid * 4.0 * iters * 8 * 2048 / (e0.elapsed_time(e1) * 1e-3) / 1e12)
+    for per_cu in (2, 4, 8):
+        for chains in (8, 16):
+            grid = per_cu * cus
+            for _ in range(2):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                rc = L.bta_internal_mfma_probe(out.data_ptr(), grid, iters, chains, s)
+                e1.record()
+                torch.cuda.synchronize()
+                if rc != 0:
+                    return None
+                best = max(best, grid * 4.0 * iters * chains * 2048 / (e0.elapsed_time(e1) * 1e-3) / 1e12)
     return round(best, 2)
 
 

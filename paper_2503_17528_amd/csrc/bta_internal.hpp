@@ -127,6 +127,12 @@ hipError_t grad_launch(int64_t n, int64_t b, int64_t a, const double* XD, const 
 // zeros above the diagonal into W (row-major, ld = m, block stride sW).
 hipError_t trinv_diag_tiles_launch(const double* L, int64_t ldL, int64_t sL, double* W, int64_t ldW, int64_t sW,
                                    int m, int nblk, hipStream_t stream);
+// Inverses W = L^{-1} of nblk lower-triangular m x m matrices (L: ld ldL,
+// block stride sL; W and the scratch T1: ld ldW, block stride sW).  W must be
+// zero on entry and receives zeros above the diagonal.  phase/major label the
+// launches for the batched recorder.
+hipError_t trtri_batched(const double* L, int64_t ldL, int64_t sL, double* W, double* T1, int64_t ldW, int64_t sW,
+                         int m, int nblk, hipStream_t s, int phase, int major);
 // Fill `count` doubles with zero.
 hipError_t fill_zero_launch(double* p, size_t count, hipStream_t stream);
 // Copy a rows x cols row-major matrix (batched by nb with strides).

@@ -68,8 +68,9 @@ BTA_TESTING_API int bta_internal_gemm(int M, int N, int K, const double* A, int6
 BTA_TESTING_API int bta_internal_timing(int on, int max_launches);
 /* Per-kind milliseconds and launch counts of the timed spans (0 = complete). */
 BTA_TESTING_API int bta_internal_timing_read(double* ms, long long* launches);
-/* Register-only FP64 MFMA rate probe: grid workgroups of 256 threads, d_out
- * holds grid*256 doubles; flops = grid * 4 * iters * 8 * 2048. */
-BTA_TESTING_API int bta_internal_mfma_probe(double* d_out, int grid, int iters, hipStream_t s);
+/* Register-only FP64 MFMA rate probe: grid workgroups of 256 threads, each
+ * wave running `chains` (8 or 16) independent MFMA chains; d_out holds
+ * grid*256 doubles; flops = grid * 4 * iters * chains * 2048. */
+BTA_TESTING_API int bta_internal_mfma_probe(double* d_out, int grid, int iters, int chains, hipStream_t s);
 
 #endif /* BTA_TESTING_H */

@@ -1154,34 +1154,38 @@ BTA_TESTING_API int bta_internal_gemm(
 }
 
 namespace bta {
-// Register-only FP64 MFMA loop: every wave runs `iters` rounds of eight
+// Register-only FP64 MFMA loop: every wave runs `iters` rounds of CH
 // independent v_mfma_f64_16x16x4_f64 chains with no memory traffic inside the
 // loop, so the launch measures the sustained FP64 matrix rate of the device
 // (2048 flops per instruction).  Each thread stores one sum, which keeps the
 // chains live.
+template <int CH>
 __global__ __launch_bounds__(256) void mfma_probe_kernel(double* out, int iters) {
   const int lane = threadIdx.x & 63;
   const double a = 1.0 + 1e-3 * lane, b = 1.0 - 1e-3 * lane;
-  d4 c[8];
+  d4 c[CH];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) c[j] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < CH; ++j) c[j] = d4{0.0, 0.0, 0.0, 0.0};
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) c[j] = mfma16(a, b, c[j]);
+    for (int j = 0; j < CH; ++j) c[j] = mfma16(a, b, c[j]);
   }
   double s = 0.0;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) s += c[j][0] + c[j][1] + c[j][2] + c[j][3];
+  for (int j = 0; j < CH; ++j) s += c[j][0] + c[j][1] + c[j][2] + c[j][3];
   out[(size_t)blockIdx.x * 256 + threadIdx.x] = s;
 }
 }  // namespace bta
 
 // Internal: launch the MFMA rate probe with `grid` workgroups of 256 threads
-// on `s`; d_out holds grid * 256 doubles.  Flops = grid * 4 * iters * 8 * 2048.
-BTA_TESTING_API int bta_internal_mfma_probe(double* d_out, int grid, int iters,
-                                                                               hipStream_t s) {
-  if (!d_out || grid < 1 || iters < 1) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(bta::mfma_probe_kernel, dim3((unsigned)grid), dim3(256), 0, s, d_out, iters);
+// on `s` (chains: 8 or 16 independent MFMA chains per wave); d_out holds
+// grid * 256 doubles.  Flops = grid * 4 * iters * chains * 2048.
+BTA_TESTING_API int bta_internal_mfma_probe(double* d_out, int grid, int iters, int chains, hipStream_t s) {
+  if (!d_out || grid < 1 || iters < 1 || (chains != 8 && chains != 16)) return (int)hipErrorInvalidValue;
+  if (chains == 8)
+    hipLaunchKernelGGL(bta::mfma_probe_kernel<8>, dim3((unsigned)grid), dim3(256), 0, s, d_out, iters);
+  else
+    hipLaunchKernelGGL(bta::mfma_probe_kernel<16>, dim3((unsigned)grid), dim3(256), 0, s, d_out, iters);
   return (int)hipGetLastError();
 }
 

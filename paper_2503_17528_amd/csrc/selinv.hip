@@ -60,7 +60,7 @@ static GSeg seg(const double* A, int64_t lda, int at, const double* B, int64_t l
 // (ld ldW, stride sW; must be zero on entry), using T1 (same layout as W) as
 // scratch.  64-tile inverses first, then doubling: for neighbouring groups of
 // g tiles, W21 = -W22 (L21 W11).
-static hipError_t trtri_batched(const double* L, int64_t ldL, int64_t sL, double* W, double* T1, int64_t ldW, int64_t sW,
+hipError_t trtri_batched(const double* L, int64_t ldL, int64_t sL, double* W, double* T1, int64_t ldW, int64_t sW,
                                 int m, int nblk, hipStream_t s, int phase, int major) {
   set_stage(phase, major, 1);
   BTA_TRY(trinv_diag_tiles_launch(L, ldL, sL, W, ldW, sW, m, nblk, s));

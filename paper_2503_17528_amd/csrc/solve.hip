@@ -2,19 +2,29 @@
 // the log-determinant 2 * sum log diag(L).  Neither is in the paper; both are
 // needed for f(A) = log det A + y^T A^{-1} y and its gradient.
 //
-// The solve is memory bound (O(n b^2) reads of L per sweep).  Per block row
-// and right-hand side, the coupling to the block solved before it (L_{i,i-1}
-// z_{i-1} forward; L_{i+1,i}^T x_{i+1} and L_{n,i}^T x_n backward) is a
-// matrix-vector product spread over many workgroups (split along the
-// reduction, partial sums summed in a fixed order), and the substitution with
-// the diagonal block goes tile by tile in one workgroup per right-hand side,
-// with the 64 x 64 diagonal tiles applied through their precomputed inverses.
+// The solve is memory bound (O(n b^2) reads of L per sweep) and sequential in
+// the block index.  The diagonal blocks are inverted up front in batched MFMA
+// launches (W_i = L_ii^{-1}, the same inverse-factor form as the selected
+// inversion), so that every step of both sweeps is a pair of dense
+// matrix-vector products spread over many workgroups:
+//   forward   t = y_i - L_{i,i-1} z_{i-1},               z_i = W_i t
+//   backward  t = z_i - L_{i+1,i}^T x_{i+1} - L_{n,i}^T x_n,  x_i = W_i^T t
+// with L_{i+1,i}^T and W_i^T transposed once into the workspace, so that every
+// product reads its matrix by rows (lanes along the row, coalesced), and the
+// arrow terms, which do not depend on the chain, computed for all blocks at
+// once.  Every sum runs in a fixed order (deterministic).
 #include <algorithm>
 
 #include "bta_device.hpp"
 #include "bta_internal.hpp"
 
 namespace bta {
+
+#define BTA_TRY_E(x)                    \
+  do {                                  \
+    hipError_t e_ = (x);                \
+    if (e_ != hipSuccess) return e_;    \
+  } while (0)
 
 // ---------------------------------------------------------------- logdet
 __global__ __launch_bounds__(256) void logdet_partial_kernel(const double* LD, const double* LT, int64_t n, int64_t b,
@@ -180,142 +190,124 @@ hipError_t logdet_launch(int64_t n, int64_t b, int64_t a, const double* LD, cons
 
 // ---------------------------------------------------------------- solve
 
-// Compact 64 x 64 inverses of the diagonal tiles of nblk m x m lower-triangular
-// blocks: tile t of block blk goes to Wc + (blk*T + t) * 4096 (ld 64).
-__global__ __launch_bounds__(NT) void tile_inverses_kernel(const double* L, int64_t m, int64_t sL, int T, double* Wc) {
-  __shared__ double S[TS * LDS_LD];
-  const int tid = threadIdx.x;
-  const int64_t blk = blockIdx.x / T;
-  const int t = (int)(blockIdx.x - blk * T);
-  const int ext = (int)std::min<int64_t>(64, m - (int64_t)t * 64);
-  const double* Lt = L + blk * sL + (int64_t)t * 64 * m + (int64_t)t * 64;
-  for (int e = tid; e < 64 * 64; e += NT) {
-    const int rr = e >> 6, cc = e & 63;
-    double v;
-    if (rr < ext && cc < ext) v = (cc <= rr) ? Lt[(int64_t)rr * m + cc] : 0.0;
-    else v = (rr == cc) ? 1.0 : 0.0;
-    S[rr * LDS_LD + cc] = v;
-  }
-  __syncthreads();
-  double w[16];
-  trinv_tile(S, w, tid);
-  const int r = tid & 63, q = tid >> 6;
-  double* Wt = Wc + (blk * T + t) * 4096;
-#pragma unroll
-  for (int mm = 0; mm < 16; ++mm) {
-    const int c = 16 * q + mm;
-    Wt[r * 64 + c] = (c <= r) ? w[mm] : 0.0;
-  }
-}
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-// out[r] (r < R <= 64) += sign * sum_{k<K} M[r*ld + k] x[k]   (row access, lanes over k).
-// Wave w takes rows w, w+4, ..., w+60 together, so the loads of all its rows
-// are in flight at once; the per-lane partial sums are then reduced through
-// LDS (part: 64 x 65 doubles), four threads per row, instead of one chain of
-// cross-lane shuffles per row.  Ends with a barrier.
-__device__ void rowdot_acc(const double* M, int64_t ld, int R, int64_t K, const double* x, double* out, double sign,
-                           double* part, int tid) {
-  const int w = tid >> 6, lane = tid & 63;
-  double s[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) s[j] = 0.0;
-  // branchless: rows past R read row R-1 and columns past K column 0, and
-  // contribute zero (a per-row branch would make the compiler wait for each
-  // load before the next); two 64-wide k chunks per trip, so that 32 loads per
-  // lane are in flight
-  for (int64_t k0 = 0; k0 < K; k0 += 128) {
-    const int64_t k1 = k0 + lane, k2 = k0 + 64 + lane;
-    const bool in1 = k1 < K, in2 = k2 < K;
-    const int64_t ka = in1 ? k1 : 0, kb = in2 ? k2 : 0;
-    const double xa = in1 ? x[ka] : 0.0, xb = in2 ? x[kb] : 0.0;
-    double ma[16], mb[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int64_t row = (int64_t)((w + 4 * j) < R ? (w + 4 * j) : R - 1) * ld;
-      ma[j] = M[row + ka];
-      mb[j] = M[row + kb];
-    }
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const double t = ma[j] * xa + mb[j] * xb;
-      s[j] += (w + 4 * j < R) ? t : 0.0;
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < 16; ++j) part[(w + 4 * j) * 65 + lane] = s[j];
-  __syncthreads();
-  const int r = tid >> 2, q = tid & 3;
-  double t = 0.0;
-#pragma unroll
-  for (int l = 0; l < 16; ++l) t += part[r * 65 + 16 * q + l];
-  t += __shfl_xor(t, 1, 64);
-  t += __shfl_xor(t, 2, 64);
-  if (q == 0 && r < R) out[r] += sign * t;
-  __syncthreads();
-}
-
-// out[k] (k < Kc <= 64) += sign * sum_{r<R} M[r*ld + k] x[r]   (column access).
-// Sixteen independent partial sums per thread keep sixteen rows' loads in flight.
-__device__ void coldot_acc(const double* M, int64_t ld, int64_t R, int Kc, const double* x, double* out, double* red,
-                           double sign, int tid) {
-  const int k = tid & 63, ph = tid >> 6;
-  double s[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) s[u] = 0.0;
-  if (k < Kc) {
-    int64_t r = ph;
-    for (; r + 60 < R; r += 64) {
-#pragma unroll
-      for (int u = 0; u < 16; ++u) s[u] += M[(r + 4 * u) * ld + k] * x[r + 4 * u];
-    }
-    for (; r < R; r += 4) s[0] += M[r * ld + k] * x[r];
-  }
-#pragma unroll
-  for (int u = 0; u < 8; ++u) s[u] += s[u + 8];
-  red[ph * 64 + k] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-  __syncthreads();
-  if (tid < 64 && tid < Kc) out[tid] += sign * (red[tid] + red[64 + tid] + red[128 + tid] + red[192 + tid]);
-  __syncthreads();
-}
-
-// rowdot_acc over one 64 x 64 tile M (row stride 64) whose elements were
-// loaded before: m[j] = M[(w + 4j) * 64 + lane] (wave w, rows w + 4j).
-// Rows >= R and columns >= K contribute zero.  Ends with a barrier.
-__device__ void rowdot_tile_regs(const double (&m)[16], int R, int K, const double* x, double* out, double sign,
-                                 double* part, int tid) {
-  const int w = tid >> 6, lane = tid & 63;
-  const double xk = lane < K ? x[lane] : 0.0;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) part[(w + 4 * j) * 65 + lane] = (w + 4 * j < R) ? m[j] * xk : 0.0;
-  __syncthreads();
-  const int r = tid >> 2, q = tid & 3;
-  double t = 0.0;
-#pragma unroll
-  for (int l = 0; l < 16; ++l) t += part[r * 65 + 16 * q + l];
-  t += __shfl_xor(t, 1, 64);
-  t += __shfl_xor(t, 2, 64);
-  if (q == 0 && r < R) out[r] += sign * t;
-  __syncthreads();
-}
-
-struct SolveParams {
-  int64_t n, b, a, nrhs, N;
-  int T, TA;
-  const double* LD; const double* LB; const double* LR; const double* LT;
-  const double* Wd;  // [n*T] tile inverses
-  const double* Wt;  // [TA] tip tile inverses
-  double* vec;       // [nrhs][N] contiguous working copies
-  double* part;      // [nrhs][SP][b] partial sums of the coupling products
-  double* ptip;      // [nrhs][n][a] partial sums of the arrow coupling
-  int SF, SB, SR;    // splits: forward (along b), backward L_{i+1,i} and L_{n,i} (64 rows each)
-  int64_t SP;        // split capacity per right-hand side
+// out[r] = base[r] + sign * sum_k M[r*ld + k] x[k] for the rows of this
+// workgroup, batched over blockIdx.y (right-hand sides) and blockIdx.z
+// (independent blocks).  tri = 0: k < K; tri = 1 (lower triangular M): only
+// k < r0 + rows of the workgroup are read; tri = 2 (upper): only k >= r0.
+// Elements of a triangular M outside its triangle must be zero.  base may be
+// null (out = sign * sum) and M may be null (K = 0: out = base).
+struct MvArgs {
+  const double* M; int64_t ld, sMz;
+  const double* x; int64_t sxy, sxz;
+  const double* base; int64_t sby, sbz;
+  double* out; int64_t soy, soz;
+  int64_t rows, K;
+  int tri;
+  double sign;
 };
+
+// Wave w takes RPW consecutive rows; its lanes run along k in 64-wide chunks,
+// CH chunks per trip, so RPW * CH loads per lane are in flight at once.  Rows
+// past the end read the last row and columns past the end read column 0 (both
+// inside the matrix) and contribute zero: no per-load branch.
+template <int RPW, int CH>
+__global__ __launch_bounds__(256) void matvec_rows_kernel(MvArgs p) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t y = blockIdx.y, z = blockIdx.z;
+  const int64_t r0 = (int64_t)blockIdx.x * (4 * RPW);
+  const int64_t rw = r0 + (int64_t)w * RPW;
+  int64_t k0 = 0, k1 = p.K;
+  if (p.tri == 1) k1 = std::min<int64_t>(p.K, r0 + 4 * RPW);
+  if (p.tri == 2) k0 = r0;
+  double s[RPW];
+#pragma unroll
+  for (int j = 0; j < RPW; ++j) s[j] = 0.0;
+  if (p.M != nullptr && k1 > k0) {
+    const double* M = p.M + z * p.sMz;
+    const double* x = p.x + y * p.sxy + z * p.sxz;
+    int64_t roff[RPW];
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) roff[j] = std::min<int64_t>(rw + j, p.rows - 1) * p.ld;
+    for (int64_t kb = k0; kb < k1; kb += 64 * CH) {
+      double xv[CH];
+      int64_t kk[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int64_t k = kb + 64 * c + lane;
+        const bool in = k < k1;
+        kk[c] = in ? k : 0;
+        xv[c] = in ? x[kk[c]] : 0.0;
+      }
+      double mv[RPW][CH];
+#pragma unroll
+      for (int j = 0; j < RPW; ++j)
+#pragma unroll
+        for (int c = 0; c < CH; ++c) mv[j][c] = M[roff[j] + kk[c]];
+#pragma unroll
+      for (int j = 0; j < RPW; ++j)
+#pragma unroll
+        for (int c = 0; c < CH; ++c) s[j] = __builtin_fma(mv[j][c], xv[c], s[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RPW; ++j) {
+    const double t = wave_sum(s[j]);
+    const int64_t r = rw + j;
+    if (lane == 0 && r < p.rows) {
+      const double b0 = p.base ? p.base[y * p.sby + z * p.sbz + r] : 0.0;
+      p.out[y * p.soy + z * p.soz + r] = b0 + p.sign * t;
+    }
+  }
+}
+
+static hipError_t matvec_rows(const MvArgs& a, int nrhs, int nz, hipStream_t s) {
+  if (a.rows <= 0 || nrhs <= 0 || nz <= 0) return hipSuccess;
+  // short rows: one row per wave and many workgroups; long rows: two per wave
+  if (a.K <= 1024) {
+    const unsigned gx = (unsigned)((a.rows + 3) / 4);
+    hipLaunchKernelGGL((matvec_rows_kernel<1, 8>), dim3(gx, (unsigned)nrhs, (unsigned)nz), dim3(256), 0, s, a);
+  } else {
+    const unsigned gx = (unsigned)((a.rows + 7) / 8);
+    hipLaunchKernelGGL((matvec_rows_kernel<2, 8>), dim3(gx, (unsigned)nrhs, (unsigned)nz), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+// dst[z](c, r) = src[z](r, c) for rows x cols matrices (64 x 64 tiles through
+// LDS; grid (tiles, 1, nz)).
+__global__ __launch_bounds__(256) void transpose_kernel(const double* src, int64_t lds, int64_t ss, double* dst,
+                                                        int64_t ldd, int64_t sd, int64_t rows, int64_t cols) {
+  __shared__ double tile[64][65];
+  const int64_t tc = (cols + 63) / 64;
+  const int64_t tr = blockIdx.x / tc, tcol = blockIdx.x - tr * tc;
+  const double* S = src + (int64_t)blockIdx.z * ss;
+  double* Dm = dst + (int64_t)blockIdx.z * sd;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int rr = w; rr < 64; rr += 4) {
+    const int64_t r = tr * 64 + rr, c = tcol * 64 + lane;
+    if (r < rows && c < cols) tile[rr][lane] = S[r * lds + c];
+  }
+  __syncthreads();
+  for (int cc = w; cc < 64; cc += 4) {
+    const int64_t c = tcol * 64 + cc, r = tr * 64 + lane;
+    if (r < rows && c < cols) Dm[c * ldd + r] = tile[lane][cc];
+  }
+}
+
+static hipError_t transpose_launch(const double* src, int64_t lds, int64_t ss, double* dst, int64_t ldd, int64_t sd,
+                                   int64_t rows, int64_t cols, int nz, hipStream_t s) {
+  if (rows <= 0 || cols <= 0 || nz <= 0) return hipSuccess;
+  const unsigned g = (unsigned)(((rows + 63) / 64) * ((cols + 63) / 64));
+  hipLaunchKernelGGL(transpose_kernel, dim3(g, 1, (unsigned)nz), dim3(256), 0, s, src, lds, ss, dst, ldd, sd, rows,
+                     cols);
+  return hipGetLastError();
+}
 
 __global__ __launch_bounds__(256) void solve_gather_kernel(const double* rhs, int64_t nrhs, int64_t N, double* vec) {
   const int64_t j = blockIdx.y;
@@ -326,276 +318,172 @@ __global__ __launch_bounds__(256) void solve_scatter_kernel(double* rhs, int64_t
   for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += (int64_t)gridDim.x * 256) rhs[r * nrhs + j] = vec[j * N + r];
 }
 
-// part[j][s][r] = sum over k in split s of L_{i,i-1}[r][k] z_{i-1}[k]; a
-// workgroup covers 16 rows (4 per wave, lanes along k), grid (b/16, SF, nrhs).
-__global__ __launch_bounds__(256) void solve_fwd_couple_kernel(SolveParams p, int64_t i) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t j = blockIdx.z, s = blockIdx.y, b = p.b;
-  const int64_t kc = (b + p.SF - 1) / p.SF, k0 = s * kc, k1 = std::min<int64_t>(b, k0 + kc);
-  const double* M = p.LB + (i - 1) * b * b;
-  const double* x = p.vec + j * p.N + (i - 1) * b;
-  const int64_t rbase = (int64_t)blockIdx.x * 16 + 4 * w;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t k = k0 + lane; k < k1; k += 64) {
-    const double xk = x[k];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (rbase + u < b) acc[u] += M[(rbase + u) * b + k] * xk;
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const double t = wave_sum(acc[u]);
-    if (lane == 0 && rbase + u < b) p.part[(j * p.SP + s) * b + rbase + u] = t;
-  }
-}
-
-// ptip[j][i][r] = L_{n,i}[r] . z_i for every block i (grid (n, 1, nrhs)).
-__global__ __launch_bounds__(256) void solve_tip_couple_kernel(SolveParams p) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t j = blockIdx.z, i = blockIdx.x, b = p.b, a = p.a;
-  const double* M = p.LR + i * a * b;
-  const double* x = p.vec + j * p.N + i * b;
-  for (int64_t r = w; r < a; r += 4) {
+// t[j][r] = vec[j][n*b + r] - sum_i ptip[j][i][r], the blocks summed in order.
+__global__ __launch_bounds__(256) void solve_tip_rhs_kernel(const double* vec, int64_t N, int64_t nb, const double* ptip,
+                                                            int64_t n, int64_t a, double* t) {
+  const int64_t j = blockIdx.y;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < a; r += (int64_t)gridDim.x * 256) {
     double acc = 0.0;
-    for (int64_t k = lane; k < b; k += 64) acc += M[r * b + k] * x[k];
-    acc = wave_sum(acc);
-    if (lane == 0) p.ptip[(j * p.n + i) * a + r] = acc;
+    for (int64_t i = 0; i < n; ++i) acc += ptip[(j * n + i) * a + r];
+    t[j * a + r] = vec[j * N + nb + r] - acc;
   }
 }
 
-// part[j][s][k] = sum over the 64 rows r of split s of M[r][k] x[r], with
-// M = L_{i+1,i} and x = x_{i+1} for s < nb, M = L_{n,i} and x = x_n after;
-// lanes along k, the four waves over the rows; grid (b/64, splits, nrhs).
-__global__ __launch_bounds__(256) void solve_bwd_couple_kernel(SolveParams p, int64_t i, int nb) {
-  __shared__ double red[256];
-  const int ph = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t j = blockIdx.z, s = blockIdx.y, b = p.b, a = p.a;
-  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
-  const bool sub = s < nb;
-  const double* M = sub ? p.LB + i * b * b : p.LR + i * a * b;
-  const double* x = sub ? p.vec + j * p.N + (i + 1) * b : p.vec + j * p.N + p.n * b;
-  const int64_t R = sub ? b : a;
-  const int64_t r0 = (sub ? s : s - nb) * 64, r1 = std::min<int64_t>(R, r0 + 64);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (k < b) {
-    int64_t r = r0 + ph;
-    for (; r + 12 < r1; r += 16) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += M[(r + 4 * u) * b + k] * x[r + 4 * u];
-    }
-    for (; r < r1; r += 4) acc[0] += M[r * b + k] * x[r];
-  }
-  red[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-  __syncthreads();
-  if (ph == 0 && k < b) p.part[(j * p.SP + s) * b + k] = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
-}
-
-// Block i forward: z_i = L_ii^{-1} (z_i - sum_s part[s]) (nsplit partials), tile by tile.
-// The block's vector is kept in LDS (dynamic, b doubles, b <= 4096), so the
-// tile chain does not round-trip through global memory.
-__global__ __launch_bounds__(NT, 1) void solve_fwd_diag_kernel(SolveParams p, int64_t i, int nsplit, int in_lds) {
-  extern __shared__ double zsh[];
-  __shared__ double v[64];
-  __shared__ double red[256];
-  __shared__ double rpart[64 * 65];
-  const int tid = threadIdx.x;
-  const int64_t j = blockIdx.x, b = p.b, bb = b * b;
-  double* zg = p.vec + j * p.N + i * b;
-  double* z = in_lds ? zsh : zg;
-  const double* pt = p.part + j * p.SP * b;
-  for (int64_t r = tid; r < b; r += NT) {
-    double t = 0.0;
-    for (int s2 = 0; s2 < nsplit; ++s2) t += pt[s2 * b + r];
-    z[r] = zg[r] - t;
-  }
-  __syncthreads();
-  const double* Ld = p.LD + i * bb;
-  for (int c = 0; c < p.T; ++c) {
-    const int ext = (int)std::min<int64_t>(64, b - (int64_t)c * 64);
-    const int64_t r0 = (int64_t)c * 64;
-    // the tile's inverse does not depend on z: its loads go out first
-    double wr[16];
-    const double* Wc = p.Wd + (i * p.T + c) * 4096;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) wr[j] = Wc[((tid >> 6) + 4 * j) * 64 + (tid & 63)];
-    if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
-    __syncthreads();
-    if (c > 0) rowdot_acc(Ld + r0 * b, b, ext, r0, z, v, -1.0, rpart, tid);
-    if (tid < 64) red[tid] = 0.0;
-    __syncthreads();
-    rowdot_tile_regs(wr, ext, ext, v, red, 1.0, rpart, tid);
-    if (tid < ext) z[r0 + tid] = red[tid];
-    __syncthreads();
-  }
-  if (in_lds)
-    for (int64_t r = tid; r < b; r += NT) zg[r] = z[r];
-}
-
-// Tip forward: z_n = L_nn^{-1} (z_n - sum_i ptip[i]) (blocks summed in order), then
-// the tip backward x_n = L_nn^{-T} z_n.
-__global__ __launch_bounds__(NT, 1) void solve_tip_kernel(SolveParams p) {
-  __shared__ double v[64];
-  __shared__ double red[256];
-  __shared__ double red2[256];
-  __shared__ double rpart[64 * 65];
-  const int tid = threadIdx.x;
-  const int64_t j = blockIdx.x, a = p.a, n = p.n;
-  double* z = p.vec + j * p.N + n * p.b;
-  for (int64_t r = tid; r < a; r += NT) {
-    double t = 0.0;
-    for (int64_t i = 0; i < n; ++i) t += p.ptip[(j * n + i) * a + r];
-    z[r] -= t;
-  }
-  __syncthreads();
-  for (int c = 0; c < p.TA; ++c) {
-    const int ext = (int)std::min<int64_t>(64, a - (int64_t)c * 64);
-    const int64_t r0 = (int64_t)c * 64;
-    if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
-    __syncthreads();
-    if (c > 0) rowdot_acc(p.LT + r0 * a, a, ext, r0, z, v, -1.0, rpart, tid);
-    __syncthreads();
-    if (tid < 64) red[tid] = 0.0;
-    __syncthreads();
-    rowdot_acc(p.Wt + (int64_t)c * 4096, 64, ext, ext, v, red, 1.0, rpart, tid);
-    __syncthreads();
-    if (tid < ext) z[r0 + tid] = red[tid];
-    __syncthreads();
-  }
-  for (int c = p.TA - 1; c >= 0; --c) {
-    const int ext = (int)std::min<int64_t>(64, a - (int64_t)c * 64);
-    const int64_t r0 = (int64_t)c * 64;
-    if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
-    __syncthreads();
-    const int64_t below = a - (r0 + ext);
-    if (below > 0) coldot_acc(p.LT + (r0 + ext) * a + r0, a, below, ext, z + r0 + ext, v, red, -1.0, tid);
-    if (tid < 64) red2[tid] = 0.0;
-    __syncthreads();
-    coldot_acc(p.Wt + (int64_t)c * 4096, 64, ext, ext, v, red2, red, 1.0, tid);
-    if (tid < ext) z[r0 + tid] = red2[tid];
-    __syncthreads();
+// vec[j][i*b + c] -= sum_{r<a} L_{n,i}[r][c] x_n[r] for every block i < n
+// (the arrow terms of the backward sweep: x_n is final before it starts).
+__global__ __launch_bounds__(256) void solve_arrow_terms_kernel(const double* LR, int64_t n, int64_t b, int64_t a,
+                                                                const double* xn, int64_t N, double* vec) {
+  const int64_t j = blockIdx.y;
+  const int64_t total = n * b;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / b, c = e - i * b;
+    const double* M = LR + i * a * b + c;
+    const double* x = xn + j * N;
+    double acc = 0.0;
+    for (int64_t r = 0; r < a; ++r) acc = __builtin_fma(M[r * b], x[r], acc);
+    vec[j * N + e] -= acc;
   }
 }
 
-// Block i backward: x_i = L_ii^{-T} (z_i - sum_s part[s]), tile by tile from the
-// last, the block's vector in LDS when it fits (as in the forward).
-__global__ __launch_bounds__(NT) void solve_bwd_diag_kernel(SolveParams p, int64_t i, int nsplit, int in_lds) {
-  extern __shared__ double zsh[];
-  __shared__ double v[64];
-  __shared__ double red[256];
-  __shared__ double red2[256];
-  const int tid = threadIdx.x;
-  const int64_t j = blockIdx.x, b = p.b, bb = b * b;
-  double* zg = p.vec + j * p.N + i * b;
-  double* z = in_lds ? zsh : zg;
-  const double* pt = p.part + j * p.SP * b;
-  for (int64_t r = tid; r < b; r += NT) {
-    double t = 0.0;
-    for (int s2 = 0; s2 < nsplit; ++s2) t += pt[s2 * b + r];
-    z[r] = zg[r] - t;
-  }
-  __syncthreads();
-  const double* Ld = p.LD + i * bb;
-  for (int c = p.T - 1; c >= 0; --c) {
-    const int ext = (int)std::min<int64_t>(64, b - (int64_t)c * 64);
-    const int64_t r0 = (int64_t)c * 64;
-    if (tid < 64) v[tid] = tid < ext ? z[r0 + tid] : 0.0;
-    __syncthreads();
-    const int64_t below = b - (r0 + ext);
-    if (below > 0) coldot_acc(Ld + (r0 + ext) * b + r0, b, below, ext, z + r0 + ext, v, red, -1.0, tid);
-    if (tid < 64) red2[tid] = 0.0;
-    __syncthreads();
-    coldot_acc(p.Wd + (i * p.T + c) * 4096, 64, ext, ext, v, red2, red, 1.0, tid);
-    if (tid < ext) z[r0 + tid] = red2[tid];
-    __syncthreads();
-  }
-  if (in_lds)
-    for (int64_t r = tid; r < b; r += NT) zg[r] = z[r];
-}
+// Workspace layout of one solve.  C blocks per chunk of inverses: the whole
+// matrix when the inverses, their transposes and the transposed coupling
+// blocks fit in the budget (then each inverse is formed once for both
+// sweeps), else chunks that are formed again for the backward sweep.
+struct SolvePlan {
+  int64_t C, nchunks;
+  size_t off_W, off_T1, off_LBt, off_WT, off_WTt, off_vec, off_t, off_t2, off_ptip, bytes;
+};
 
-static void solve_splits(int64_t b, int64_t a, int& SF, int& SB, int& SR, int64_t& SP) {
-  SF = (int)std::max<int64_t>(1, (b + 255) / 256);
-  SB = (int)((b + 63) / 64);
-  SR = (int)((a + 63) / 64);
-  SP = std::max<int64_t>(SF, (int64_t)SB + SR);
-}
-
-size_t solve_work_bytes(int64_t n, int64_t b, int64_t a, int64_t nrhs) {
-  const int64_t T = (b + 63) / 64, TA = (a + 63) / 64;
+static SolvePlan solve_plan(int64_t n, int64_t b, int64_t a, int64_t nrhs) {
+  SolvePlan sp{};
+  const size_t per_block = 3 * 8 * (size_t)b * (size_t)b;
+  const size_t budget = size_t(2) << 30;
+  sp.C = std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(budget / per_block)));
+  sp.nchunks = (n + sp.C - 1) / sp.C;
   const int64_t N = n * b + a;
-  int SF, SB, SR;
-  int64_t SP;
-  solve_splits(b, a, SF, SB, SR, SP);
-  size_t bytes = 0;
-  auto take = [&](size_t x) { bytes += (x + 255) & ~size_t(255); };
-  take(8 * 4096 * (size_t)(n * T));
-  take(8 * 4096 * (size_t)std::max<int64_t>(TA, 1));
-  take(8 * (size_t)(N * nrhs));
-  take(8 * (size_t)(SP * b * nrhs));
-  take(8 * (size_t)std::max<int64_t>(1, n * a * nrhs));
-  return bytes;
+  size_t off = 0;
+  auto take = [&](size_t x) { size_t o = off; off += (std::max<size_t>(x, 8) + 255) & ~size_t(255); return o; };
+  const size_t cbb = 8 * (size_t)sp.C * (size_t)b * (size_t)b;
+  sp.off_W = take(cbb);
+  sp.off_T1 = take(cbb);
+  sp.off_LBt = take(cbb);
+  sp.off_WT = take(8 * (size_t)(a * a));
+  sp.off_WTt = take(8 * (size_t)(a * a));
+  sp.off_vec = take(8 * (size_t)(N * nrhs));
+  sp.off_t = take(8 * (size_t)(std::max(b, a) * nrhs));
+  sp.off_t2 = take(8 * (size_t)(a * nrhs));
+  sp.off_ptip = take(8 * (size_t)(n * a * nrhs));
+  sp.bytes = off;
+  return sp;
 }
+
+size_t solve_work_bytes(int64_t n, int64_t b, int64_t a, int64_t nrhs) { return solve_plan(n, b, a, nrhs).bytes; }
 
 hipError_t solve_launch(int64_t n, int64_t b, int64_t a, const double* LD, const double* LB, const double* LR,
                         const double* LT, double* rhs, int64_t nrhs, void* work, hipStream_t stream) {
-  const int64_t T = (b + 63) / 64, TA = (a + 63) / 64;
+  const SolvePlan sp = solve_plan(n, b, a, nrhs);
   char* w = static_cast<char*>(work);
-  size_t off = 0;
-  auto take = [&](size_t x) { size_t o = off; off += (x + 255) & ~size_t(255); return o; };
-  SolveParams p;
-  p.n = n; p.b = b; p.a = a; p.nrhs = nrhs; p.N = n * b + a;
-  p.T = (int)T; p.TA = (int)TA;
-  p.LD = LD; p.LB = LB; p.LR = LR; p.LT = LT;
-  solve_splits(b, a, p.SF, p.SB, p.SR, p.SP);
-  double* Wd = reinterpret_cast<double*>(w + take(8 * 4096 * (size_t)(n * T)));
-  double* Wt = reinterpret_cast<double*>(w + take(8 * 4096 * (size_t)std::max<int64_t>(TA, 1)));
-  p.vec = reinterpret_cast<double*>(w + take(8 * (size_t)(p.N * nrhs)));
-  p.part = reinterpret_cast<double*>(w + take(8 * (size_t)(p.SP * b * nrhs)));
-  p.ptip = reinterpret_cast<double*>(w + take(8 * (size_t)std::max<int64_t>(1, n * a * nrhs)));
-  p.Wd = Wd; p.Wt = Wt;
+  double* W = reinterpret_cast<double*>(w + sp.off_W);
+  double* T1 = reinterpret_cast<double*>(w + sp.off_T1);   // TRTRI scratch, then W_i^T
+  double* LBt = reinterpret_cast<double*>(w + sp.off_LBt);
+  double* WT = reinterpret_cast<double*>(w + sp.off_WT);
+  double* WTt = reinterpret_cast<double*>(w + sp.off_WTt);
+  double* vec = reinterpret_cast<double*>(w + sp.off_vec);
+  double* tb = reinterpret_cast<double*>(w + sp.off_t);
+  double* t2 = reinterpret_cast<double*>(w + sp.off_t2);
+  double* ptip = reinterpret_cast<double*>(w + sp.off_ptip);
+  const int64_t N = n * b + a, bb = b * b, ab = a * b;
+  const int nr = (int)nrhs;
+  const int64_t tstride = std::max(b, a);
   auto ok = [&]() { return hipGetLastError(); };
-  hipLaunchKernelGGL(tile_inverses_kernel, dim3((unsigned)(n * T)), dim3(NT), 0, stream, LD, b, b * b, (int)T, Wd);
+
+  const unsigned gN = (unsigned)std::min<int64_t>(1024, (N + 255) / 256);
+  hipLaunchKernelGGL(solve_gather_kernel, dim3(gN, (unsigned)nrhs), dim3(256), 0, stream, rhs, nrhs, N, vec);
   if (hipError_t e = ok()) return e;
-  if (a > 0) {
-    hipLaunchKernelGGL(tile_inverses_kernel, dim3((unsigned)TA), dim3(NT), 0, stream, LT, a, (int64_t)0, (int)TA, Wt);
-    if (hipError_t e = ok()) return e;
-  }
-  const unsigned gN = (unsigned)std::min<int64_t>(1024, (p.N + 255) / 256);
-  // the diagonal-block kernels keep the block's vector in LDS up to b = 4096
-  // (32 KB of dynamic LDS, within the default limit)
-  const int in_lds = b <= 4096 ? 1 : 0;
-  const size_t zbytes = in_lds ? 8 * (size_t)b : 0;
-  hipLaunchKernelGGL(solve_gather_kernel, dim3(gN, (unsigned)nrhs), dim3(256), 0, stream, rhs, nrhs, p.N, p.vec);
-  if (hipError_t e = ok()) return e;
-  // forward over the blocks
-  for (int64_t i = 0; i < n; ++i) {
-    if (i > 0) {
-      hipLaunchKernelGGL(solve_fwd_couple_kernel, dim3((unsigned)((b + 15) / 16), (unsigned)p.SF, (unsigned)nrhs), dim3(256),
-                         0, stream, p, i);
-      if (hipError_t e = ok()) return e;
+
+  auto invert_chunk = [&](int64_t i0, int64_t cnt) -> hipError_t {
+    BTA_TRY_E(fill_zero_launch(W, (size_t)(cnt * bb), stream));
+    return trtri_batched(LD + i0 * bb, b, bb, W, T1, b, bb, (int)b, (int)cnt, stream, 0, 0);
+  };
+
+  // ---- forward: z_i = W_i (y_i - L_{i,i-1} z_{i-1})
+  for (int64_t c = 0; c < sp.nchunks; ++c) {
+    const int64_t i0 = c * sp.C, cnt = std::min<int64_t>(sp.C, n - i0);
+    BTA_TRY_E(invert_chunk(i0, cnt));
+    for (int64_t i = i0; i < i0 + cnt; ++i) {
+      MvArgs cp{};
+      cp.M = i > 0 ? LB + (i - 1) * bb : nullptr; cp.ld = b;
+      cp.x = vec + (i - 1) * b; cp.sxy = N;
+      cp.base = vec + i * b; cp.sby = N;
+      cp.out = tb; cp.soy = tstride;
+      cp.rows = b; cp.K = i > 0 ? b : 0; cp.tri = 0; cp.sign = -1.0;
+      BTA_TRY_E(matvec_rows(cp, nr, 1, stream));
+      MvArgs ap{};
+      ap.M = W + (i - i0) * bb; ap.ld = b;
+      ap.x = tb; ap.sxy = tstride;
+      ap.out = vec + i * b; ap.soy = N;
+      ap.rows = b; ap.K = b; ap.tri = 1; ap.sign = 1.0;
+      BTA_TRY_E(matvec_rows(ap, nr, 1, stream));
     }
-    hipLaunchKernelGGL(solve_fwd_diag_kernel, dim3((unsigned)nrhs), dim3(NT), zbytes, stream, p, i, i > 0 ? p.SF : 0, in_lds);
-    if (hipError_t e = ok()) return e;
   }
-  // the tip, forward then backward
+
+  // ---- the tip: z_n = W_T (y_n - sum_i L_{n,i} z_i), x_n = W_T^T z_n, then
+  // the arrow terms of every block's backward right-hand side
   if (a > 0) {
-    hipLaunchKernelGGL(solve_tip_couple_kernel, dim3((unsigned)n, 1, (unsigned)nrhs), dim3(256), 0, stream, p);
+    MvArgs pp{};
+    pp.M = LR; pp.ld = b; pp.sMz = ab;
+    pp.x = vec; pp.sxy = N; pp.sxz = b;
+    pp.out = ptip; pp.soy = n * a; pp.soz = a;
+    pp.rows = a; pp.K = b; pp.tri = 0; pp.sign = 1.0;
+    BTA_TRY_E(matvec_rows(pp, nr, (int)n, stream));
+    hipLaunchKernelGGL(solve_tip_rhs_kernel, dim3((unsigned)((a + 255) / 256), (unsigned)nrhs), dim3(256), 0, stream, vec,
+                       N, n * b, ptip, n, a, t2);
     if (hipError_t e = ok()) return e;
-    hipLaunchKernelGGL(solve_tip_kernel, dim3((unsigned)nrhs), dim3(NT), 0, stream, p);
+    BTA_TRY_E(fill_zero_launch(WT, (size_t)(a * a), stream));
+    BTA_TRY_E(trtri_batched(LT, a, 0, WT, WTt, a, 0, (int)a, 1, stream, 0, 0));
+    BTA_TRY_E(transpose_launch(WT, a, 0, WTt, a, 0, a, a, 1, stream));
+    MvArgs fz{};
+    fz.M = WT; fz.ld = a;
+    fz.x = t2; fz.sxy = a;
+    fz.out = tb; fz.soy = tstride;
+    fz.rows = a; fz.K = a; fz.tri = 1; fz.sign = 1.0;
+    BTA_TRY_E(matvec_rows(fz, nr, 1, stream));
+    MvArgs bx{};
+    bx.M = WTt; bx.ld = a;
+    bx.x = tb; bx.sxy = tstride;
+    bx.out = vec + n * b; bx.soy = N;
+    bx.rows = a; bx.K = a; bx.tri = 2; bx.sign = 1.0;
+    BTA_TRY_E(matvec_rows(bx, nr, 1, stream));
+    const unsigned g = (unsigned)std::min<int64_t>(4096, (n * b + 255) / 256);
+    hipLaunchKernelGGL(solve_arrow_terms_kernel, dim3(g, (unsigned)nrhs), dim3(256), 0, stream, LR, n, b, a, vec + n * b, N,
+                       vec);
     if (hipError_t e = ok()) return e;
   }
-  // backward over the blocks
-  for (int64_t i = n - 1; i >= 0; --i) {
-    const int nb = i < n - 1 ? p.SB : 0;
-    const int ns = nb + (a > 0 ? p.SR : 0);
-    if (ns > 0) {
-      hipLaunchKernelGGL(solve_bwd_couple_kernel, dim3((unsigned)((b + 63) / 64), (unsigned)ns, (unsigned)nrhs), dim3(256), 0,
-                         stream, p, i, nb);
-      if (hipError_t e = ok()) return e;
+
+  // ---- backward: x_i = W_i^T (z_i - L_{n,i}^T x_n - L_{i+1,i}^T x_{i+1})
+  for (int64_t c = sp.nchunks - 1; c >= 0; --c) {
+    const int64_t i0 = c * sp.C, cnt = std::min<int64_t>(sp.C, n - i0);
+    if (sp.nchunks > 1) BTA_TRY_E(invert_chunk(i0, cnt));
+    BTA_TRY_E(transpose_launch(W, b, bb, T1, b, bb, b, b, (int)cnt, stream));
+    const int64_t nsub = std::min<int64_t>(cnt, (n - 1) - i0);
+    if (nsub > 0) BTA_TRY_E(transpose_launch(LB + i0 * bb, b, bb, LBt, b, bb, b, b, (int)nsub, stream));
+    for (int64_t i = i0 + cnt - 1; i >= i0; --i) {
+      MvArgs cp{};
+      cp.M = i < n - 1 ? LBt + (i - i0) * bb : nullptr; cp.ld = b;
+      cp.x = vec + (i + 1) * b; cp.sxy = N;
+      cp.base = vec + i * b; cp.sby = N;
+      cp.out = tb; cp.soy = tstride;
+      cp.rows = b; cp.K = i < n - 1 ? b : 0; cp.tri = 0; cp.sign = -1.0;
+      BTA_TRY_E(matvec_rows(cp, nr, 1, stream));
+      MvArgs ap{};
+      ap.M = T1 + (i - i0) * bb; ap.ld = b;
+      ap.x = tb; ap.sxy = tstride;
+      ap.out = vec + i * b; ap.soy = N;
+      ap.rows = b; ap.K = b; ap.tri = 2; ap.sign = 1.0;
+      BTA_TRY_E(matvec_rows(ap, nr, 1, stream));
     }
-    hipLaunchKernelGGL(solve_bwd_diag_kernel, dim3((unsigned)nrhs), dim3(NT), zbytes, stream, p, i, ns, in_lds);
-    if (hipError_t e = ok()) return e;
   }
-  hipLaunchKernelGGL(solve_scatter_kernel, dim3(gN, (unsigned)nrhs), dim3(256), 0, stream, rhs, nrhs, p.N, p.vec);
+  hipLaunchKernelGGL(solve_scatter_kernel, dim3(gN, (unsigned)nrhs), dim3(256), 0, stream, rhs, nrhs, N, vec);
   return ok();
 }
 
