@@ -93,6 +93,29 @@ BTA_API bta_status bta_factor(int64_t n, int64_t b, int64_t a,
                void* work, size_t work_bytes, int64_t* d_info, bta_stream_t stream);
 
 /*
+ * bta_factor without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the factorization's scratch (the progress flags,
+ * the diagonal-tile inverses and the tip partial sums) lives in a fixed,
+ * library-owned device array of BTA_NOALLOC_SCRATCH_BYTES (64 MiB) per
+ * device, held from the library's load on that device until the process ends.
+ * The call allocates nothing (no hipMalloc, no allocating library routine).
+ *  - Problems whose scratch (bta_workspace_bytes(BTA_OP_FACTOR, n, b, a, 0))
+ *    exceeds the limit are rejected with BTA_EINVAL before any HIP work;
+ *    they need bta_factor and a workspace.
+ *  - Arguments, outputs, d_info and the results are exactly those of
+ *    bta_factor (the same kernels run).
+ *  - Every call on a device shares that device's array, and each call resets
+ *    the parts that must start cleared: calls that may overlap on one device
+ *    (different streams, or different host threads) race on it and must be
+ *    serialized by the caller.
+ */
+#define BTA_NOALLOC_SCRATCH_BYTES (64u << 20)
+BTA_API bta_status bta_factor_noalloc(int64_t n, int64_t b, int64_t a,
+               const double* D, const double* B, const double* R, const double* T,
+               double* LD, double* LB, double* LR, double* LT, int64_t* d_info, bta_stream_t stream);
+
+/*
  * POBTASI (Algorithm 2): selected inversion from the factor of bta_factor.
  *  in : LD, LB, LR, LT   blocks of L
  *  out: XD, XB, XR, XT   blocks of Sigma = A^{-1} at the BTA pattern:

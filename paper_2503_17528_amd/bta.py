@@ -25,7 +25,7 @@ BTA_OK, BTA_EINVAL, BTA_EHIP, BTA_ENOTSUP = 0, 1, 3, 4
 NOT_POSITIVE_DEFINITE = 2
 BTA_OP_FACTOR, BTA_OP_SELINV, BTA_OP_SOLVE, BTA_OP_LOGDET = 0, 1, 2, 3
 
-EXPORTED = ("bta_workspace_bytes", "bta_factor", "bta_selinv", "bta_solve", "bta_logdet",
+EXPORTED = ("bta_workspace_bytes", "bta_factor", "bta_factor_noalloc", "bta_selinv", "bta_solve", "bta_logdet",
             "bta_logdet_quad", "bta_grad_logdet_quad", "bta_batched_workspace_bytes", "bta_factor_batched",
             "bta_selinv_batched", "bta_status_string", "bta_last_error")
 
@@ -63,6 +63,8 @@ def lib() -> ctypes.CDLL:
     L.bta_workspace_bytes.restype = sz
     L.bta_factor.argtypes = [i64, i64, i64] + [vp] * 8 + [vp, sz, vp, vp]
     L.bta_factor.restype = ctypes.c_int
+    L.bta_factor_noalloc.argtypes = [i64, i64, i64] + [vp] * 8 + [vp, vp]
+    L.bta_factor_noalloc.restype = ctypes.c_int
     L.bta_selinv.argtypes = [i64, i64, i64] + [vp] * 8 + [vp, sz, vp]
     L.bta_selinv.restype = ctypes.c_int
     L.bta_solve.argtypes = [i64, i64, i64] + [vp] * 4 + [vp, i64, vp, sz, vp]
@@ -106,6 +108,10 @@ def bta_workspace_bytes(op: int, n: int, b: int, a: int, nrhs: int = 0) -> int:
 
 def bta_factor(n, b, a, D, B, R, T, LD, LB, LR, LT, work, work_bytes, d_info, stream) -> int:
     return int(lib().bta_factor(n, b, a, D, B, R, T, LD, LB, LR, LT, work, work_bytes, d_info, stream))
+
+
+def bta_factor_noalloc(n, b, a, D, B, R, T, LD, LB, LR, LT, d_info, stream) -> int:
+    return int(lib().bta_factor_noalloc(n, b, a, D, B, R, T, LD, LB, LR, LT, d_info, stream))
 
 
 def bta_selinv(n, b, a, LD, LB, LR, LT, XD, XB, XR, XT, work, work_bytes, stream) -> int:
@@ -220,6 +226,26 @@ def factor(D, B, R, T, out=None, work=None, stream=None, check: bool = True):
             raise NotPositiveDefinite(v)
         if v < 0:
             raise BTAError(BTA_EHIP, "bta_factor: progress watchdog fired")
+    return LD, LB, LR, LT, info
+
+
+def factor_noalloc(D, B, R, T, out=None, stream=None):
+    """bta_factor_noalloc: L = POBTAF(A) with the library's fixed device
+    scratch instead of a workspace (no allocation inside the call; problems
+    above the scratch limit raise BTAError with BTA_EINVAL).  Returns
+    (LD, LB, LR, LT, info) without synchronizing."""
+    import torch
+
+    n, b, a = _dims(D, R, T)
+    _validate(D, (n, b, b), "D"); _validate(B, (max(n - 1, 0), b, b), "B")
+    _validate(R, (n, a, b), "R"); _validate(T, (a, a), "T")
+    if out is None:
+        out = (torch.empty_like(D), torch.empty_like(B), torch.empty_like(R), torch.empty_like(T))
+    LD, LB, LR, LT = out
+    info = torch.zeros((), dtype=torch.int64, device=D.device)
+    st = bta_factor_noalloc(n, b, a, _ptr(D), _ptr(B), _ptr(R), _ptr(T), _ptr(LD), _ptr(LB), _ptr(LR), _ptr(LT),
+                            info.data_ptr(), _stream(stream))
+    _check(st, "bta_factor_noalloc")
     return LD, LB, LR, LT, info
 
 

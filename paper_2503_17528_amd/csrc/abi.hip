@@ -2,6 +2,8 @@
 // dispatch to the launchers.  Validation happens before any HIP call, so the
 // argument checks work on a host without a GPU.
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <utility>
 #include <vector>
 #include <cstdarg>
@@ -91,6 +93,53 @@ bta_status check_work(void* work, size_t work_bytes, size_t need) {
 
 }  // namespace
 
+// Fixed device scratch of bta_factor_noalloc: one copy per device, created
+// when the library's code object is loaded on that device and kept until the
+// process ends.  Host code never passes `scratch` itself to a kernel (its
+// host-side name is not a device address): it takes the device address from
+// hipGetSymbolAddress, once per device, and passes that.
+static __device__ __align__(256) unsigned char scratch[BTA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;  // device ordinal -> address of that device's `scratch`
+
+// The current device's address of `scratch` (looked up on first use, with
+// that device current).
+bta_status scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return BTA_OK;
+  }
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255)) return fail(BTA_EHIP, "scratch address %p is not 256-byte aligned", ptr);
+  g_scratch_addr[dev] = ptr;
+  *out = ptr;
+  return BTA_OK;
+}
+
+// Argument checks shared by bta_factor and bta_factor_noalloc.
+bta_status factor_args(int64_t n, int64_t b, int64_t a, const double* D, const double* B, const double* R, const double* T,
+                       double* LD, double* LB, double* LR, double* LT, int64_t* d_info) {
+  if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
+  const Arr arr[9] = {
+      {D, blk_bytes(n, b, b), "D"},        {B, blk_bytes(n - 1, b, b), "B"}, {R, blk_bytes(n, a, b), "R"},
+      {T, blk_bytes(1, a, a), "T"},        {LD, blk_bytes(n, b, b), "LD"},   {LB, blk_bytes(n - 1, b, b), "LB"},
+      {LR, blk_bytes(n, a, b), "LR"},      {LT, blk_bytes(1, a, a), "LT"},   {d_info, 8, "d_info"}};
+  const int pair[9] = {4, 5, 6, 7, 0, 1, 2, 3, -1};
+  return check_arrays(arr, 9, pair);
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t bta_workspace_bytes(int op, int64_t n, int64_t b, int64_t a, int64_t nrhs) {
@@ -107,13 +156,7 @@ size_t bta_workspace_bytes(int op, int64_t n, int64_t b, int64_t a, int64_t nrhs
 bta_status bta_factor(int64_t n, int64_t b, int64_t a, const double* D, const double* B, const double* R, const double* T,
                double* LD, double* LB, double* LR, double* LT, void* work, size_t work_bytes, int64_t* d_info,
                bta_stream_t stream) {
-  if (!dims_ok(n, b, a)) return fail(BTA_EINVAL, "invalid sizes n=%lld b=%lld a=%lld", (long long)n, (long long)b, (long long)a);
-  const Arr arr[9] = {
-      {D, blk_bytes(n, b, b), "D"},        {B, blk_bytes(n - 1, b, b), "B"}, {R, blk_bytes(n, a, b), "R"},
-      {T, blk_bytes(1, a, a), "T"},        {LD, blk_bytes(n, b, b), "LD"},   {LB, blk_bytes(n - 1, b, b), "LB"},
-      {LR, blk_bytes(n, a, b), "LR"},      {LT, blk_bytes(1, a, a), "LT"},   {d_info, 8, "d_info"}};
-  const int pair[9] = {4, 5, 6, 7, 0, 1, 2, 3, -1};
-  bta_status st = check_arrays(arr, 9, pair);
+  bta_status st = factor_args(n, b, a, D, B, R, T, LD, LB, LR, LT, d_info);
   if (st) return st;
   const bta::FactorPlan fp = bta::factor_plan(n, b, a);
   st = check_work(work, work_bytes, fp.bytes);
@@ -123,6 +166,26 @@ bta_status bta_factor(int64_t n, int64_t b, int64_t a, const double* D, const do
   hipError_t e = bta::factor_launch(fp, n, b, a, D, B, R, T, LD, LB, LR, LT, work, d_info,
                                     reinterpret_cast<hipStream_t>(stream), bta::device_cu_count());
   return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_factor launch");
+}
+
+bta_status bta_factor_noalloc(int64_t n, int64_t b, int64_t a, const double* D, const double* B, const double* R,
+                              const double* T, double* LD, double* LB, double* LR, double* LT, int64_t* d_info,
+                              bta_stream_t stream) {
+  bta_status st = factor_args(n, b, a, D, B, R, T, LD, LB, LR, LT, d_info);
+  if (st) return st;
+  const bta::FactorPlan fp = bta::factor_plan(n, b, a);
+  if (fp.bytes > (size_t)BTA_NOALLOC_SCRATCH_BYTES)
+    return fail(BTA_EINVAL, "bta_factor_noalloc: n=%lld b=%lld a=%lld needs %zu bytes of scratch, above the fixed %zu "
+                "(use bta_factor with a workspace)", (long long)n, (long long)b, (long long)a, fp.bytes,
+                (size_t)BTA_NOALLOC_SCRATCH_BYTES);
+  st = device_ok();
+  if (st) return st;
+  void* ptr = nullptr;
+  st = scratch_address(&ptr);
+  if (st) return st;
+  hipError_t e = bta::factor_launch(fp, n, b, a, D, B, R, T, LD, LB, LR, LT, ptr, d_info,
+                                    reinterpret_cast<hipStream_t>(stream), bta::device_cu_count());
+  return e == hipSuccess ? BTA_OK : hip_fail(e, "bta_factor_noalloc launch");
 }
 
 bta_status bta_selinv(int64_t n, int64_t b, int64_t a, const double* LD, const double* LB, const double* LR, const double* LT,

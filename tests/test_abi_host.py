@@ -148,3 +148,21 @@ def test_build_rejects_scratch_kernels():
     ]
     assert build.scratch_kernels(lines) == [("_Zk2", 352)]
     assert build.scratch_kernels(lines[:3]) == []
+
+
+def test_factor_noalloc_rejects_problems_above_its_scratch(bta):
+    """The fixed-scratch factorization refuses problems whose scratch exceeds
+    its limit before any HIP work (host-only: fake, aligned, disjoint device
+    addresses)."""
+    import ctypes as ct
+
+    n, b, a = 64, 2048, 8
+    assert bta.bta_workspace_bytes(bta.BTA_OP_FACTOR, n, b, a, 0) > (64 << 20)
+    base = 1 << 44
+    span = 1 << 36
+    p = [base + k * span for k in range(9)]
+    st = bta.bta_factor_noalloc(n, b, a, *p[:8], p[8], None)
+    assert st == bta.BTA_EINVAL
+    assert "scratch" in bta.bta_last_error()
+    # a small problem passes the size check (and then needs a device)
+    assert bta.bta_workspace_bytes(bta.BTA_OP_FACTOR, 4, 64, 2, 0) <= (64 << 20)
