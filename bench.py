@@ -239,6 +239,8 @@ def parity_gate(torch, synth, wl, seed, Q, L, X):
             if j < n - 1:
                 acc += XR[j + 1] @ B[j]
             ident["arrow"] = max(ident["arrow"], acc.abs().max().item())
+        if j % 64 == 63:
+            print(f"[bench] parity gate: {j + 1}/{n} blocks", file=sys.stderr, flush=True)
     if a:
         eL["T"] = rel(LT, synth.factor_block_torch(wl, seed, synth.KIND_TIP, 0, D.device), True)
         acc = XT @ T
@@ -366,7 +368,8 @@ def main():
         wl = synth.workload(args.n, args.b, args.a, reading, name=f"bta_n{args.n}_b{args.b}_a{args.a}")
     n, b, a, reading = wl.n, wl.b, wl.a, wl.reading
     print(f"[bench] drawing {wl.name} ({wl.block_bytes() / 1e9:.2f} GB of blocks) on {dev}", file=sys.stderr, flush=True)
-    Q = synth.make_torch(wl, args.seed, dev)
+    Q = synth.make_torch(wl, args.seed, dev,
+                         progress=lambda i, m: print(f"[bench] drawn {i}/{m} blocks", file=sys.stderr, flush=True))
     D, B, R, T = Q["D"], Q["B"], Q["R"], Q["T"]
     outL = tuple(torch.empty_like(x) for x in (D, B, R, T))
     outX = tuple(torch.empty_like(x) for x in (D, B, R, T))

@@ -1,0 +1,168 @@
+"""Autotuner of the factorization's tunables, and access to the library's
+tuning table.
+
+The library keeps its tuned decisions in a table keyed by
+``<arch>|<op>|b=<b>|a=<a>|<knob>`` (``tune.hip``): the factorization's DIAG
+lookahead (``look``: how many band columns ahead of the diagonal-tile chain a
+diagonal task starts its accumulation) and its k-loop load path (``cached``:
+1 reads published operand tiles through the L2), and the batched selected
+inversion's tile shape per merged stage class (``tile128``, measured by the
+library itself on first use).  ``BTA_TUNE_CACHE=<file.json>`` makes the
+library load the table from that file on first use and write measured
+entries back; ``BTA_FACTOR_LOOKAHEAD`` and ``BTA_FACTOR_CACHED`` override the
+table for every shape.
+
+``tune_factor`` times candidate settings on a seeded synthetic matrix of the
+given block shape (the median of ``reps`` factorizations each, HIP events on
+the current stream) and records the fastest in the table.  Command line::
+
+    python -m paper_2503_17528_amd.autotune --n 32 --b 2048 --a 8 --out tune.json
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import statistics
+import sys
+from typing import Dict, Iterable, Optional
+
+from . import bta, synth
+
+
+def _lib():
+    L = bta.lib()
+    L.bta_internal_tune_set.argtypes = [ctypes.c_char_p, ctypes.c_longlong]
+    L.bta_internal_tune_set.restype = ctypes.c_int
+    L.bta_internal_tune_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_longlong)]
+    L.bta_internal_tune_get.restype = ctypes.c_int
+    L.bta_internal_tune_key.argtypes = [ctypes.c_char_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_char_p,
+                                        ctypes.c_char_p, ctypes.c_int]
+    L.bta_internal_tune_key.restype = ctypes.c_int
+    L.bta_internal_tune_save.argtypes = [ctypes.c_char_p]
+    L.bta_internal_tune_save.restype = ctypes.c_int
+    L.bta_internal_tune_load.argtypes = [ctypes.c_char_p]
+    L.bta_internal_tune_load.restype = ctypes.c_int
+    L.bta_internal_tune_clear.argtypes = []
+    L.bta_internal_tune_clear.restype = ctypes.c_int
+    L.bta_internal_autotune_dump.argtypes = [ctypes.c_char_p, ctypes.c_int]
+    L.bta_internal_autotune_dump.restype = ctypes.c_int
+    L.bta_internal_factor_lookahead.argtypes = [ctypes.c_int]
+    L.bta_internal_factor_lookahead.restype = ctypes.c_int
+    L.bta_internal_factor_cached_loads.argtypes = [ctypes.c_int]
+    L.bta_internal_factor_cached_loads.restype = ctypes.c_int
+    return L
+
+
+def key(op: str, b: int, a: int, knob: str) -> str:
+    buf = ctypes.create_string_buffer(256)
+    if _lib().bta_internal_tune_key(op.encode(), b, a, knob.encode(), buf, 256) != 0:
+        raise ValueError("tuning key too long")
+    return buf.value.decode()
+
+
+def set_entry(k: str, value: int) -> None:
+    if _lib().bta_internal_tune_set(k.encode(), int(value)) != 0:
+        raise ValueError(f"invalid tuning key {k!r}")
+
+
+def get_entry(k: str) -> Optional[int]:
+    v = ctypes.c_longlong(0)
+    return int(v.value) if _lib().bta_internal_tune_get(k.encode(), ctypes.byref(v)) == 0 else None
+
+
+def table() -> Dict[str, int]:
+    buf = ctypes.create_string_buffer(1 << 20)
+    _lib().bta_internal_autotune_dump(buf, len(buf))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        k, _, v = line.rpartition("=")
+        out[k] = int(v)
+    return out
+
+
+def save(path: str) -> None:
+    if _lib().bta_internal_tune_save(path.encode()) != 0:
+        raise OSError(f"could not write {path}")
+
+
+def load(path: str) -> None:
+    if _lib().bta_internal_tune_load(path.encode()) != 0:
+        raise OSError(f"could not read a tuning table from {path}")
+
+
+def clear() -> None:
+    _lib().bta_internal_tune_clear()
+
+
+def tune_factor(n: int, b: int, a: int, looks: Iterable[int] = (2, 4, 6, 8, 12, 16), cached: Iterable[int] = (0, 1),
+                reps: int = 3, seed: int = 0, log=None) -> Dict[str, float]:
+    """Time bta_factor on a seeded n x (b, a) matrix for every (lookahead,
+    load path) candidate, the median of ``reps`` runs each, and record the
+    fastest as the table's ``look`` and ``cached`` entries for (b, a).
+    Returns {"look=<L>,cached=<c>": median ms}."""
+    import torch
+
+    if reps < 3:
+        raise ValueError("reps >= 3 (the median of at least three runs)")
+    L = _lib()
+    reading = "scaled" if b >= 2048 else "literal"
+    wl = synth.workload(n, b, a, reading)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    Q = synth.make_torch(wl, seed, dev)
+    out = tuple(torch.empty_like(Q[k]) for k in "DBRT")
+    work, _ = bta.workspace(bta.BTA_OP_FACTOR, n, b, a, dev)
+    T = (b + 63) // 64
+    times: Dict[str, float] = {}
+    prev_look = L.bta_internal_factor_lookahead(-1)
+    prev_cached = L.bta_internal_factor_cached_loads(-2)
+    try:
+        for look in sorted(set(min(max(1, int(x)), max(1, T - 1)) for x in looks)):
+            for c in cached:
+                L.bta_internal_factor_lookahead(look)
+                L.bta_internal_factor_cached_loads(int(c))
+                ms = []
+                for _ in range(reps + 1):  # the first run warms up
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    info = bta.factor(Q["D"], Q["B"], Q["R"], Q["T"], out=out, work=work, check=False)[4]
+                    e1.record()
+                    torch.cuda.synchronize()
+                    if int(info.item()) != 0:
+                        raise bta.BTAError(bta.BTA_EHIP, f"factorization failed during tuning (info {int(info.item())})")
+                    ms.append(e0.elapsed_time(e1))
+                med = statistics.median(ms[1:])
+                times[f"look={look},cached={int(c)}"] = med
+                if log:
+                    log(f"factor n={n} b={b} a={a} look={look} cached={int(c)}: {med:.3f} ms")
+    finally:
+        L.bta_internal_factor_lookahead(prev_look)
+        L.bta_internal_factor_cached_loads(prev_cached)
+    best = min(times, key=times.get)
+    look_s, cached_s = best.split(",")
+    set_entry(key("factor", b, a, "look"), int(look_s.split("=")[1]))
+    set_entry(key("factor", b, a, "cached"), int(cached_s.split("=")[1]))
+    return times
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description="tune the BTA factorization for one block shape")
+    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--b", type=int, required=True)
+    ap.add_argument("--a", type=int, default=0)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--out", required=True, help="JSON tuning table to update (read first if it exists)")
+    args = ap.parse_args(argv)
+    import os
+
+    if os.path.exists(args.out):
+        load(args.out)
+    times = tune_factor(args.n, args.b, args.a, reps=args.reps, log=lambda m: print(m, file=sys.stderr, flush=True))
+    save(args.out)
+    print(json.dumps({"times_ms": times, "table": table()}))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbta.so")
-SOURCES = ["abi.hip", "batched.hip", "factor.hip", "gemm.hip", "selinv.hip", "solve.hip"]
+SOURCES = ["abi.hip", "batched.hip", "factor.hip", "gemm.hip", "selinv.hip", "solve.hip", "tune.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

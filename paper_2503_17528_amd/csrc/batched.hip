@@ -10,6 +10,7 @@
 // per process.
 #include <algorithm>
 #include <cstring>
+#include <list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -210,9 +211,11 @@ MergedPlan build_plan(const StageRecorder& rec) {
 
 // ---------------------------------------------------------------- autotuner / graph cache
 
+// Captured graphs of recent descriptor sets, most recently used first; at
+// most kGraphCache of them are kept, the oldest destroyed on insertion.
+constexpr size_t kGraphCache = 8;
 std::mutex g_mu;
-std::map<std::string, int> g_tuned;           // shape class -> 0 (64 tiles) / 1 (128 tiles)
-std::map<std::string, hipGraphExec_t> g_graphs;  // descriptor set -> graph
+std::list<std::pair<std::string, hipGraphExec_t>> g_graphs;
 
 int heuristic_big(const StageExec& ex) { return ex.work2 >= 200 ? 1 : 0; }
 
@@ -240,7 +243,9 @@ hipError_t launch_stage(const StageExec& ex, char* dtab, int big, hipStream_t s)
   return hipSuccess;
 }
 
-std::string tune_key(const StageExec& ex) { return ex.shape; }
+// The tuning-table key of a merged GEMM stage's shape class (every matrix's
+// b and a are in the shape string, so the op's b and a fields stay 0).
+std::string stage_key(const StageExec& ex) { return tune_key(("selinv_batched[" + ex.shape + "]").c_str(), 0, 0, "tile128"); }
 
 }  // namespace
 
@@ -255,7 +260,7 @@ static BatchLayout batch_layout(int count, const int64_t* n, const int64_t* b, c
   size_t off = 0;
   for (int m = 0; m < count; ++m) {
     L.slice.push_back(off);
-    off += align256(selinv_plan(n[m], b[m], a[m]).bytes);
+    off += align256(selinv_plan(n[m], b[m], a[m], false).bytes);
   }
   L.table_off = off;
   L.bytes = off + table_bytes;
@@ -267,7 +272,7 @@ static hipError_t record_batch(int count, const BatchMatrix* mats, char* work, c
   hipError_t e = hipSuccess;
   for (int m = 0; m < count && e == hipSuccess; ++m) {
     const BatchMatrix& x = mats[m];
-    e = selinv_launch(selinv_plan(x.n, x.b, x.a), x.n, x.b, x.a, x.LD, x.LB, x.LR, x.LT, x.XD, x.XB, x.XR, x.XT,
+    e = selinv_launch(selinv_plan(x.n, x.b, x.a, false), x.n, x.b, x.a, x.LD, x.LB, x.LR, x.LT, x.XD, x.XB, x.XR, x.XT,
                       work + L.slice[m], nullptr);
   }
   g_rec = nullptr;
@@ -305,11 +310,18 @@ hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, h
   sig += std::to_string(reinterpret_cast<uintptr_t>(work));
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_graphs.find(sig);
-    if (it != g_graphs.end()) return hipGraphLaunch(it->second, stream);
+    for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+      if (it->first == sig) {
+        g_graphs.splice(g_graphs.begin(), g_graphs, it);  // most recently used
+        return hipGraphLaunch(g_graphs.front().second, stream);
+      }
   }
 
-  // first use: run eagerly, timing both tilings of untuned pure GEMM stages
+  // first use: run eagerly; a pure GEMM stage whose shape class is not in the
+  // tuning table is timed with both tilings (median of three runs each; the
+  // stage's outputs do not feed its inputs, so repeating it is harmless) and
+  // the faster one recorded.  This first call waits for those timings on the
+  // host (hipEventSynchronize on the caller's stream); later calls only enqueue.
   std::vector<int> choice(mp.stages.size(), 0);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   for (size_t k = 0; k < mp.stages.size(); ++k) {
@@ -318,33 +330,33 @@ hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, h
       BTA_TRY_E(launch_stage(ex, dtab, 0, stream));
       continue;
     }
-    int tuned = -1;
-    {
-      std::lock_guard<std::mutex> lk(g_mu);
-      auto it = g_tuned.find(tune_key(ex));
-      if (it != g_tuned.end()) tuned = it->second;
-    }
+    long long tuned = -1;
+    if (!tune_get(stage_key(ex), &tuned) || (tuned != 0 && tuned != 1)) tuned = -1;
     if (tuned < 0 && ex.pure && ex.work2 > 0) {
       if (!e0) {
         BTA_TRY_E(hipEventCreate(&e0));
         BTA_TRY_E(hipEventCreate(&e1));
       }
-      float t[2] = {0.f, 0.f};
+      float med[2] = {0.f, 0.f};
       for (int big = 0; big < 2; ++big) {
-        BTA_TRY_E(hipEventRecord(e0, stream));
-        BTA_TRY_E(launch_stage(ex, dtab, big, stream));
-        BTA_TRY_E(hipEventRecord(e1, stream));
-        BTA_TRY_E(hipEventSynchronize(e1));
-        BTA_TRY_E(hipEventElapsedTime(&t[big], e0, e1));
+        float t[3];
+        for (int rep = 0; rep < 3; ++rep) {
+          BTA_TRY_E(hipEventRecord(e0, stream));
+          BTA_TRY_E(launch_stage(ex, dtab, big, stream));
+          BTA_TRY_E(hipEventRecord(e1, stream));
+          BTA_TRY_E(hipEventSynchronize(e1));
+          BTA_TRY_E(hipEventElapsedTime(&t[rep], e0, e1));
+        }
+        std::sort(t, t + 3);
+        med[big] = t[1];
       }
-      tuned = t[1] < t[0] ? 1 : 0;
-      std::lock_guard<std::mutex> lk(g_mu);
-      g_tuned[tune_key(ex)] = tuned;
+      tuned = med[1] < med[0] ? 1 : 0;
+      tune_set(stage_key(ex), tuned, true);
     } else {
       if (tuned < 0) tuned = heuristic_big(ex);
-      BTA_TRY_E(launch_stage(ex, dtab, tuned, stream));
+      BTA_TRY_E(launch_stage(ex, dtab, (int)tuned, stream));
     }
-    choice[k] = tuned;
+    choice[k] = (int)tuned;
   }
   if (e0) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); }
 
@@ -364,7 +376,11 @@ hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, h
   (void)hipGraphDestroy(graph);
   if (ie != hipSuccess) return ie;
   std::lock_guard<std::mutex> lk(g_mu);
-  g_graphs[sig] = exec;
+  g_graphs.emplace_front(sig, exec);
+  while (g_graphs.size() > kGraphCache) {
+    (void)hipGraphExecDestroy(g_graphs.back().second);
+    g_graphs.pop_back();
+  }
   return hipSuccess;
 }
 
@@ -438,20 +454,6 @@ BTA_TESTING_API int bta_internal_selinv_batch_check(int count, const int64_t* n,
         if (spans[i].op != spans[j].op && (spans[i].w || spans[j].w)) return 3;
   }
   return 0;
-}
-
-// Autotuner decisions recorded so far (for inspection): writes up to `cap`
-// bytes of "shape class=choice" lines.
-BTA_TESTING_API int bta_internal_autotune_dump(char* out, int cap) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  std::string s;
-  for (auto& kv : g_tuned) s += kv.first + "=" + (kv.second ? "128" : "64") + "\n";
-  const int n = (int)std::min<size_t>(s.size(), cap > 0 ? (size_t)cap - 1 : 0);
-  if (cap > 0) {
-    std::memcpy(out, s.data(), n);
-    out[n] = 0;
-  }
-  return (int)g_tuned.size();
 }
 
 }  // namespace bta

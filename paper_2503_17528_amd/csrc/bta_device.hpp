@@ -389,18 +389,26 @@ __device__ __forceinline__ void blk_store(const d4& c, double* X, int ld, int la
 // column, reusing the pivots' reciprocal square roots), then the 2 x 2 block
 // recursion W21 = -W22 L21 W11, at 16 and at 32, on MFMA.
 // Scratch: rinv[64], tmp[4 * 16 * 17].
-__device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double* rinv, double* tmp, int* fail_sh, int tid) {
+// VAR 0: the pivot of column k+1 is broadcast from its updated column entry;
+// VAR 1: lane k+1 forms the next pivot from its own L(k+1,k) (one FMA), so
+// the cross-lane read of L(k+1,k) leaves the pivot chain.  TIMED: thread 0
+// writes s_memrealtime stamps of the phase ends into ts[0..7].
+template <int VAR, bool TIMED>
+__device__ __forceinline__ int chol_inv_tile_mfma_t(double* S, double* Wl, double* rinv, double* tmp, int* fail_sh, int tid,
+                                                    long long* ts) {
   const int r = tid & 63, q = tid >> 6;
+  if (TIMED && tid == 0) ts[0] = __builtin_amdgcn_s_memrealtime();
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
     if (q == p) {
       double s[16];
 #pragma unroll
       for (int m = 0; m < 16; ++m) s[m] = S[r * LDS_LD + 16 * p + m];
+      double dn = s[0];
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
         const int k = 16 * p + m;
-        const double d = rd_lane(s[m], k);
+        const double d = rd_lane(VAR == 1 ? dn : s[m], k);
         // (pivots are checked once after the panels, from rinv)
         const double ri = rsqrt_refined(d);
         if (r == 0) rinv[k] = ri;
@@ -410,6 +418,7 @@ __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double*
         // are written back as zeros
         const double lv = s[m] * ri;
         s[m] = lv;
+        if (VAR == 1 && m + 1 < 16) dn = __builtin_fma(-lv, lv, s[m + 1]);
         // column m+1 (the next pivot) by a cross-lane read; the other columns
         // through a double-buffered LDS copy of the column (results in VGPRs,
         // off the next pivot's critical path)
@@ -427,6 +436,7 @@ __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double*
       for (int m = 0; m < 16; ++m) S[r * LDS_LD + 16 * p + m] = s[m];
     }
     __syncthreads();
+    if (TIMED && tid == 0) ts[1 + 2 * p] = __builtin_amdgcn_s_memrealtime();
     if (p < 3) {
       // rank-16 update of the trailing lower blocks (I, J), p < J <= I
       const int nb = (3 - p) * (4 - p) / 2;
@@ -440,6 +450,7 @@ __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double*
         blk_store(c, S + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
       }
       __syncthreads();
+      if (TIMED && tid == 0) ts[2 + 2 * p] = __builtin_amdgcn_s_memrealtime();
     }
   }
   // first pivot that is not a positive finite number: its reciprocal square
@@ -475,6 +486,7 @@ __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double*
     }
   }
   __syncthreads();
+  if (TIMED && tid == 0) ts[8] = __builtin_amdgcn_s_memrealtime();
   // ---- level 16: W(1,0) = -W(1,1) L(1,0) W(0,0) (wave 0), W(3,2) = -W(3,3) L(3,2) W(2,2) (wave 1)
   if (q < 2) {
     const int I = 2 * q + 1, J = 2 * q;
@@ -489,6 +501,7 @@ __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double*
     blk_store(o, Wl + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
   }
   __syncthreads();
+  if (TIMED && tid == 0) ts[9] = __builtin_amdgcn_s_memrealtime();
   // ---- level 32: U = L21 W11 (one 16 x 16 block per wave), then W21 = -W22 U
   {
     const int I = 2 + (q >> 1), J = q & 1;
@@ -507,8 +520,13 @@ __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double*
     blk_store(o, Wl + 16 * I * LDS_LD + 16 * J, LDS_LD, r);
   }
   __syncthreads();
+  if (TIMED && tid == 0) ts[10] = __builtin_amdgcn_s_memrealtime();
   const int f = *fail_sh;
   return f == 0x7fffffff ? 0 : f;
+}
+
+__device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double* rinv, double* tmp, int* fail_sh, int tid) {
+  return chol_inv_tile_mfma_t<0, false>(S, Wl, rinv, tmp, fail_sh, tid, nullptr);
 }
 
 // In-LDS inverse of a lower-triangular 64 x 64 tile by forward substitution on

@@ -6,6 +6,7 @@
 
 #include <array>
 #include <map>
+#include <string>
 #include <vector>
 
 namespace bta {
@@ -90,13 +91,24 @@ struct GemmArgs {
 
 // Launch the problems (at most GEMM_MAX_PROBS) as one grid; empty problems are skipped.
 hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream);
+// One problem whose 64 x 64 tiles fill less than half of the CUs, with plain
+// (not triangular) operands: its k range is split into S <= GEMM_MAX_PROBS
+// parts computed as one launch into ws (S*M*N doubles), then summed in split
+// order by a second launch with the problem's alpha, beta and store mode.
+// Anything else (or ws == nullptr) goes to gemm_launch.
+hipError_t gemm_launch_split(GProb* probs, int nprob, hipStream_t stream, double* ws, size_t ws_doubles);
+// The split count gemm_launch_split would use for p (1 = no split).
+int splitk_factor(const GProb& p, size_t ws_doubles);
 
 // ---------------------------------------------------------------- selinv
 struct SelinvPlan {
   int64_t chunk;  // blocks per preprocessing chunk
-  size_t off_W, off_T1, off_PR, off_Xp, off_WT, bytes;
+  size_t split_doubles;  // split-k partials of the sweep products (0: no split)
+  size_t off_W, off_T1, off_PR, off_Xp, off_WT, off_split, bytes;
 };
-SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a);
+// split: reserve the split-k partials of the sweep products (single-matrix
+// calls; the batched selected inversion has parallelism across matrices).
+SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a, bool split = true);
 hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
                          const double* LD, const double* LB, const double* LR, const double* LT,
                          double* XD, double* XB, double* XR, double* XT,
@@ -140,6 +152,14 @@ hipError_t copy2d_launch(const double* src, int64_t lds, int64_t ss, double* dst
                          int rows, int cols, int nb, hipStream_t stream);
 
 int device_cu_count();
+// ---------------------------------------------------------------- tuning table (tune.hip)
+// Key of a tuned decision: "<arch>|<op>|b=<b>|a=<a>|<knob>".
+std::string tune_key(const char* op, int64_t b, int64_t a, const char* knob);
+bool tune_get(const std::string& key, long long* out);
+// persist: rewrite the BTA_TUNE_CACHE file (when set) with the whole table.
+void tune_set(const std::string& key, long long val, bool persist);
+// Integer environment override in [lo, hi] (false when unset or invalid).
+bool env_int(const char* name, long long lo, long long hi, long long* out);
 
 // Library-owned streams and events for one call.  Every call that needs more
 // than the caller's stream leases a context for its whole enqueue sequence

@@ -16,9 +16,13 @@
 #define BTA_TESTING_API extern "C" __attribute__((visibility("default")))
 
 /* ---- factorization (factor.hip) */
-/* DIAG lookahead in band columns for later factorizations (1..64); returns the
- * previous value (any other argument only queries). */
+/* Override of the DIAG lookahead in band columns for later factorizations
+ * (1..64; 0 removes the override); returns the previous override (0 = none;
+ * any other argument only queries). */
 BTA_TESTING_API int bta_internal_factor_lookahead(int look);
+/* The DIAG lookahead (after the T-1 clamp) and the k-loop load path (1 = L2)
+ * a factorization of (n, b, a) would use now. */
+BTA_TESTING_API int bta_internal_factor_plan_knobs(int64_t n, int64_t b, int64_t a, int* look, int* cached);
 /* Cap on the single-matrix factor kernel's workgroups (0 = one per CU);
  * returns the previous value (a negative argument only queries). */
 BTA_TESTING_API int bta_internal_factor_max_grid(int g);
@@ -28,14 +32,34 @@ BTA_TESTING_API int bta_internal_factor_traced(int64_t n, int64_t b, int64_t a, 
                                                const double* R, const double* T, double* LD, double* LB, double* LR,
                                                double* LT, void* work, int64_t* info, unsigned long long* trace,
                                                long long* ntasks, hipStream_t stream);
-/* 1: the factor kernels read their k-loop operand tiles through the L2 where
- * the tiles are cache-line aligned; 0: device-coherent loads.  Returns the
- * previous value (any other argument only queries). */
+/* Override: 1 the factor kernels read their k-loop operand tiles through the
+ * L2 where the tiles are cache-line aligned, 0 device-coherent loads, -1 no
+ * override.  Returns the previous override (any other argument only queries). */
 BTA_TESTING_API int bta_internal_factor_cached_loads(int on);
 /* The pivot reciprocal square root of the diagonal-tile Cholesky
  * (hardware estimate + one third-order refinement) applied to count device
  * doubles: d_out[k] = rsqrt_refined(d_in[k]).  Returns 0 on launch success. */
 BTA_TESTING_API int bta_internal_rsqrt(const double* d_in, double* d_out, int64_t count, hipStream_t s);
+/* Latency probe of the diagonal-tile Cholesky + inverse: one workgroup
+ * factors the 64 x 64 SPD tile d_A (row-major) `iters` times with panel
+ * variant `var`; d_ticks[0] gets the summed 100 MHz ticks, d_ticks[1] the
+ * failure column (0 = none), d_ticks[2..11] the summed phase ticks, d_L and
+ * d_W (64 x 64 each) the factor and its inverse. */
+BTA_TESTING_API int bta_internal_diag_link_probe(const double* d_A, double* d_L, double* d_W, long long* d_ticks,
+                                                 int iters, int var, hipStream_t s);
+/* Round-trip latency of the cross-workgroup flag hand-off between the first
+ * and last workgroup of a grid of `grid` (d_flags: 128 zeroed ints); mode 0
+ * release/acquire, mode 1 relaxed after a store wait.  d_ticks[0] = summed
+ * 100 MHz ticks of `iters` round trips.  Every poll is bounded. */
+BTA_TESTING_API int bta_internal_flag_pingpong(int* d_flags, long long* d_ticks, int iters, int mode, int grid,
+                                               hipStream_t s);
+/* Throughput probe of the factor's k loop: `grid` workgroups each run
+ * `steps` double-buffered k steps on 64 x 64 tiles at pseudo-random positions
+ * of the first span_rows rows of the row-major matrix d_M (leading dimension
+ * ld, a multiple of 64); mode 0 device-coherent loads, 1 no loads, 2 loads
+ * through the L2.  d_ticks[g]: workgroup g's 100 MHz ticks; d_out: grid*256. */
+BTA_TESTING_API int bta_internal_kloop_probe(const double* d_M, int64_t ld, int64_t span_rows, int steps, int mode,
+                                             int grid, long long* d_ticks, double* d_out, hipStream_t s);
 /* Host replay of the single-matrix task schedule (0 = valid); counts[7]
  * receives the number of tiles of each task type. */
 BTA_TESTING_API int bta_internal_factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts);
@@ -50,9 +74,21 @@ BTA_TESTING_API int bta_internal_factor_batch_check(int count, const int64_t* n,
 BTA_TESTING_API int bta_internal_selinv_dry_check(int64_t n, int64_t b, int64_t a);
 /* Host check of the merged batched plan (0 = valid). */
 BTA_TESTING_API int bta_internal_selinv_batch_check(int count, const int64_t* n, const int64_t* b, const int64_t* a);
-/* Autotuner decisions of this process as "key=choice" lines (up to cap bytes);
- * returns the number of decisions. */
+/* The tuning table (tune.hip) as "key=value" lines (up to cap bytes); returns
+ * the number of entries.  Keys: "<arch>|<op>|b=<b>|a=<a>|<knob>", e.g. the
+ * factor's "look" (DIAG lookahead) and "cached" (L2 loads), the batched
+ * selected inversion's per-stage-class "tile128". */
 BTA_TESTING_API int bta_internal_autotune_dump(char* out, int cap);
+/* Tuning table access: set (in memory), get (0 = found), the key of
+ * (op, b, a, knob) for this device, save / load the JSON file at path, clear.
+ * The file named by BTA_TUNE_CACHE is loaded on first use and rewritten when
+ * a first-use measurement adds an entry. */
+BTA_TESTING_API int bta_internal_tune_set(const char* key, long long value);
+BTA_TESTING_API int bta_internal_tune_get(const char* key, long long* value);
+BTA_TESTING_API int bta_internal_tune_key(const char* op, int64_t b, int64_t a, const char* knob, char* out, int cap);
+BTA_TESTING_API int bta_internal_tune_save(const char* path);
+BTA_TESTING_API int bta_internal_tune_load(const char* path);
+BTA_TESTING_API int bta_internal_tune_clear(void);
 
 /* ---- GEMM engine and measurement (gemm.hip) */
 /* GEMM kernel family of the selected inversion (0 automatic, 1 register-staged,
@@ -63,6 +99,12 @@ BTA_TESTING_API int bta_internal_gemm_mode(int mode);
 BTA_TESTING_API int bta_internal_gemm(int M, int N, int K, const double* A, int64_t lda, int at, const double* B,
                                       int64_t ldb, int bt, int tri, const double* Cin, double* C, int64_t ldc,
                                       double alpha, double beta, int store, int lower_tiles, hipStream_t s);
+/* The same product through the split-k path of the selected inversion's sweep
+ * (ws: device partials of ws_doubles; *splits receives the split count used). */
+BTA_TESTING_API int bta_internal_gemm_split(int M, int N, int K, const double* A, int64_t lda, int at, const double* B,
+                                            int64_t ldb, int bt, const double* Cin, double* C, int64_t ldc,
+                                            double alpha, double beta, int store, int lower_tiles, double* ws,
+                                            size_t ws_doubles, int* splits, hipStream_t s);
 /* Per-kernel HIP-event timing of the main kernels (on with a pool of
  * 2*max_launches events, off with on = 0); not thread safe. */
 BTA_TESTING_API int bta_internal_timing(int on, int max_launches);

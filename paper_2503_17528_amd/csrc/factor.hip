@@ -871,16 +871,36 @@ __global__ void factor_finish_kernel(const int* ctl, int64_t* info) {
 }
 
 // ---------------------------------------------------------------------------
-// DIAG lookahead in columns (internal override for measurements).
-static int g_factor_look = FACTOR_LOOKAHEAD;
+// DIAG lookahead in columns: internal override for measurements (0 = none).
+static int g_factor_look = 0;
 // DIAG lookahead of the batched kernel: with many matrices in flight a longer
 // lookahead only holds more workgroups on waiting tiles (measured on the 64-matrix
 // workload: 23.2, 22.5, 23.2, 23.6 and 23.9 ms for 1, 2, 3, 4 and 8 columns).
 constexpr int BATCH_LOOKAHEAD = 2;
 // Upper bound on the factor kernel's workgroups (internal, for measurements; 0: one per CU).
 static int g_factor_max_grid = 0;
-// k-loop operands through the L2 where the tiles are line-aligned (internal switch).
-static int g_factor_cached = 0;
+// k-loop operands through the L2 where the tiles are line-aligned: internal
+// override for measurements (-1 = none).
+static int g_factor_cached = -1;
+
+// The DIAG lookahead for blocks of b with an arrow of a: the internal
+// override, else BTA_FACTOR_LOOKAHEAD, else the tuning table, else the default.
+static int factor_lookahead(int64_t b, int64_t a) {
+  if (g_factor_look > 0) return g_factor_look;
+  long long v = 0;
+  if (env_int("BTA_FACTOR_LOOKAHEAD", 1, 64, &v)) return (int)v;
+  if (tune_get(tune_key("factor", b, a, "look"), &v) && v >= 1 && v <= 64) return (int)v;
+  return FACTOR_LOOKAHEAD;
+}
+
+// Whether the k loops read through the L2 (same order of sources; default off).
+static bool factor_cached_loads(int64_t b, int64_t a) {
+  if (g_factor_cached >= 0) return g_factor_cached != 0;
+  long long v = 0;
+  if (env_int("BTA_FACTOR_CACHED", 0, 1, &v)) return v != 0;
+  if (tune_get(tune_key("factor", b, a, "cached"), &v)) return v != 0;
+  return false;
+}
 
 // Whether every operand tile of a factorization starts its rows on 128-byte
 // cache lines: the L arrays 128-byte aligned and their leading dimensions
@@ -902,7 +922,7 @@ FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   fp.step_full = T * (T - 1) / 2 + 1 + T * T - 1 + T * TA + TA * (TA + 1) / 2;
   fp.step_last = T * (T - 1) / 2 + 1 + T * TA + TA * (TA + 1) / 2;
   fp.ntasks = (n - 1) * fp.step_full + fp.step_last + TA * (TA + 1) / 2;
-  fp.look = (int)std::min<int64_t>(g_factor_look, T - 1);
+  fp.look = (int)std::min<int64_t>(factor_lookahead(b, a), T - 1);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
   fp.off_ctl = take(64);
@@ -933,7 +953,7 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
   p.step_full = fp.step_full;
   p.step_last = fp.step_last;
   p.look = fp.look;
-  p.cached = (g_factor_cached && factor_lines_aligned(b, a, LD, LB, LR, LT)) ? 1 : 0;
+  p.cached = (factor_cached_loads(b, a) && factor_lines_aligned(b, a, LD, LB, LR, LT)) ? 1 : 0;
   p.trace = trace;
   p.spin_limit = 1LL << 22;  // a few seconds of polling without progress before the watchdog fires
   const int rgrid = (int)std::min<long long>(1024, (fp.nflags + 255) / 256 + 1);
@@ -1092,7 +1112,7 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
     p.step_last = fp.step_last;
     p.look = fp.look;
     p.spin_limit = 1LL << 22;
-    p.cached = (g_factor_cached && factor_lines_aligned(p.b, p.a, p.LD, p.LB, p.LR, p.LT)) ? 1 : 0;
+    p.cached = (factor_cached_loads(p.b, p.a) && factor_lines_aligned(p.b, p.a, p.LD, p.LB, p.LR, p.LT)) ? 1 : 0;
     p.trace = nullptr;
   }
   std::vector<int64_t> ns(bp.count);
@@ -1277,15 +1297,25 @@ int factor_schedule_check(int64_t n, int64_t b, int64_t a, long long* counts /* 
 BTA_TESTING_API int bta_internal_factor_lookahead(int look) {
   const int prev = bta::g_factor_look;
   if (look >= 1 && look <= 64) bta::g_factor_look = look;
+  else if (look == 0) bta::g_factor_look = 0;
   return prev;
 }
 
+// Internal: the DIAG lookahead and the k-loop load path a factorization of
+// (n, b, a) would use now (overrides, environment, tuning table, default).
+BTA_TESTING_API int bta_internal_factor_plan_knobs(int64_t n, int64_t b, int64_t a, int* look, int* cached) {
+  if (look) *look = bta::factor_plan(n, b, a).look;
+  if (cached) *cached = bta::factor_cached_loads(b, a) ? 1 : 0;
+  return 0;
+}
+
 // Internal: 1 reads the k-loop operand tiles through the L2 where they are
-// line-aligned, 0 with device-coherent loads; returns the previous value (any
-// other argument only queries).
+// line-aligned, 0 with device-coherent loads, -1 removes the override (the
+// environment, the tuning table or the default decide); returns the previous
+// override (any other argument only queries).
 BTA_TESTING_API int bta_internal_factor_cached_loads(int on) {
   const int prev = bta::g_factor_cached;
-  if (on == 0 || on == 1) bta::g_factor_cached = on;
+  if (on >= -1 && on <= 1) bta::g_factor_cached = on;
   return prev;
 }
 
@@ -1416,5 +1446,234 @@ BTA_TESTING_API int bta_internal_rsqrt(const double* d_in, double* d_out, int64_
   if (!d_in || !d_out || count < 1) return (int)hipErrorInvalidValue;
   const unsigned grid = (unsigned)std::min<int64_t>(4096, (count + 255) / 256);
   hipLaunchKernelGGL(bta::rsqrt_probe_kernel, dim3(grid), dim3(256), 0, s, d_in, d_out, count);
+  return (int)hipGetLastError();
+}
+
+namespace bta {
+// Latency of the diagonal-tile Cholesky + inverse (the link of the factor's
+// critical path) in isolation: one workgroup factors the same 64 x 64 SPD tile
+// `iters` times from LDS; ticks[0] receives the summed s_memrealtime ticks
+// (100 MHz) of the calls, ticks[1] the failure column, ticks[2..11] the summed
+// phase durations (panels and trailing updates, W, levels), L and W the last
+// call's factor and inverse.  var selects the panel variant.
+template <int VAR>
+__device__ void diag_link_probe_body(const double* A, double* Lout, double* Wout, long long* ticks, int iters) {
+  __shared__ Shared sh;
+  __shared__ long long ts[12];
+  const int tid = threadIdx.x;
+  double v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int idx = tid + 256 * e;
+    v[e] = A[idx];
+  }
+  long long total = 0, ph[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int f = 0;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int idx = tid + 256 * e;
+      sh.u.f.As[(idx >> 6) * LDS_LD + (idx & 63)] = v[e];
+    }
+    __syncthreads();
+    const long long t0 = __builtin_amdgcn_s_memrealtime();
+    f = chol_inv_tile_mfma_t<VAR, true>(sh.u.f.As, sh.u.f.Bs, sh.rinv, sh.pan, &sh.fail, tid, ts);
+    __syncthreads();
+    const long long t1 = __builtin_amdgcn_s_memrealtime();
+    total += t1 - t0;
+    if (tid == 0)
+      for (int k = 0; k < 10; ++k) ph[k] += ts[k + 1] - ts[k];
+  }
+  for (int e = tid; e < 4096; e += NT) {
+    const int rr = e >> 6, cc = e & 63;
+    Lout[e] = cc <= rr ? sh.u.f.As[rr * LDS_LD + cc] : 0.0;
+    Wout[e] = sh.u.f.Bs[rr * LDS_LD + cc];
+  }
+  if (tid == 0) {
+    ticks[0] = total;
+    ticks[1] = f;
+    for (int k = 0; k < 10; ++k) ticks[2 + k] = ph[k];
+  }
+}
+__global__ __launch_bounds__(NT, 1) void diag_link_probe_kernel0(const double* A, double* L, double* W, long long* t, int it) {
+  diag_link_probe_body<0>(A, L, W, t, it);
+}
+__global__ __launch_bounds__(NT, 1) void diag_link_probe_kernel1(const double* A, double* L, double* W, long long* t, int it) {
+  diag_link_probe_body<1>(A, L, W, t, it);
+}
+}  // namespace bta
+
+BTA_TESTING_API int bta_internal_diag_link_probe(const double* d_A, double* d_L, double* d_W, long long* d_ticks,
+                                                 int iters, int var, hipStream_t s) {
+  if (!d_A || !d_L || !d_W || !d_ticks || iters < 1) return (int)hipErrorInvalidValue;
+  if (var == 0)
+    hipLaunchKernelGGL(bta::diag_link_probe_kernel0, dim3(1), dim3(bta::NT), 0, s, d_A, d_L, d_W, d_ticks, iters);
+  else if (var == 1)
+    hipLaunchKernelGGL(bta::diag_link_probe_kernel1, dim3(1), dim3(bta::NT), 0, s, d_A, d_L, d_W, d_ticks, iters);
+  else
+    return (int)hipErrorInvalidValue;
+  return (int)hipGetLastError();
+}
+
+namespace bta {
+// Round-trip latency of the cross-workgroup flag hand-off: workgroup 0 and the
+// last workgroup of the grid (another XCD) pass a token `iters` times.  mode 0:
+// release store / relaxed polls + acquire fence (the factor's protocol);
+// mode 1: relaxed device-coherent store after a wait for the wave's stores,
+// relaxed polls, no fences.  ticks[0]: summed 100 MHz ticks of the round
+// trips measured by workgroup 0.
+__global__ __launch_bounds__(64) void flag_pingpong_kernel(int* flags, long long* ticks, int iters, int mode) {
+  const bool a = blockIdx.x == 0, b = blockIdx.x == gridDim.x - 1;
+  if (!(a || b) || threadIdx.x != 0) return;
+  int* mine = flags + (a ? 0 : 64);
+  int* other = flags + (a ? 64 : 0);
+  const long long t0 = __builtin_amdgcn_s_memrealtime();
+  for (int it = 1; it <= iters; ++it) {
+    if (b) {
+      long long polls = 0;
+      while (__hip_atomic_load(other, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it && ++polls < (1LL << 22)) {
+      }
+      if (mode == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    if (mode == 0) {
+      __hip_atomic_store(mine, it, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __builtin_amdgcn_s_waitcnt(0);
+      __hip_atomic_store(mine, it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (a) {
+      long long polls = 0;
+      while (__hip_atomic_load(other, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it && ++polls < (1LL << 22)) {
+      }
+      if (mode == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+  }
+  if (a) ticks[0] = __builtin_amdgcn_s_memrealtime() - t0;
+}
+}  // namespace bta
+
+BTA_TESTING_API int bta_internal_flag_pingpong(int* d_flags, long long* d_ticks, int iters, int mode, int grid,
+                                               hipStream_t s) {
+  if (!d_flags || !d_ticks || iters < 1 || grid < 2) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(bta::flag_pingpong_kernel, dim3((unsigned)grid), dim3(64), 0, s, d_flags, d_ticks, iters, mode);
+  return (int)hipGetLastError();
+}
+
+namespace bta {
+// Throughput of the factor's k loop in isolation: every workgroup runs `steps`
+// k steps (two 64 x 64 operand tiles into the double-buffered pieced LDS
+// stages, then the MFMA product of the previous stage), the tiles taken from a
+// row-major matrix of `rows` x `ld` doubles at pseudo-random tile positions
+// inside the first `span_rows` rows (a small span stays in the caches).  mode 0:
+// device-coherent direct loads (the factor's), 1: no loads (MFMA + barriers
+// only), 2: direct loads through the L2, 3: loads into registers two steps
+// ahead (plain loads), written to the pieced LDS stage after the MFMAs, 4: as
+// 3 with device-coherent buffer loads.  ticks[blockIdx.x]: the workgroup's ticks.
+__device__ __forceinline__ void tile_load_regs(d2v (&r)[8], const OpTile& t, int tid, bool coherent) {
+  const int w = tid >> 6, lane = tid & 63;
+  __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(t.p), (short)0, 0x7fffffff, 0x00020000);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int slot = (w * 8 + j) * 64 + lane;
+    const int m = slot >> 5, pc = (slot & 31) ^ (m & 15);
+    const int off = (int)(((int64_t)m * t.ld + 2 * pc) * 8);
+    if (coherent) {
+      r[j] = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 16));
+    } else {
+      r[j] = *reinterpret_cast<const d2v*>(t.p + (int64_t)m * t.ld + 2 * pc);
+    }
+  }
+}
+__device__ __forceinline__ void tile_regs_to_lds(double* dst, const d2v (&r)[8], int tid) {
+  const int w = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) *reinterpret_cast<d2v*>(dst + 2 * ((w * 8 + j) * 64 + lane)) = r[j];
+}
+
+__global__ __launch_bounds__(NT, 1) void kloop_probe_kernel(const double* M, int64_t ld, int64_t span_rows, int steps,
+                                                            int mode, long long* ticks, double* out) {
+  __shared__ Shared sh;
+  const int tid = threadIdx.x;
+  Acc acc;
+  acc_zero(acc);
+  // tile rows and columns as powers of two (masks instead of divisions, so the
+  // index arithmetic per step is a few instructions, as in the factor)
+  unsigned trm = 1, tcm = 1;
+  while (2 * trm <= (unsigned)(span_rows / 64)) trm *= 2;
+  while (2 * tcm <= (unsigned)(ld / 64)) tcm *= 2;
+  auto tile_at = [&](int kk, int which) {
+    const unsigned h = blockIdx.x * 2654435761u + (unsigned)kk * 40503u + (unsigned)which * 977u;
+    const int64_t tr = (int64_t)(h & (trm - 1)), tc = (int64_t)((h >> 11) & (tcm - 1));
+    return OpTile{M + tr * 64 * ld + tc * 64, ld, 64, 64, false};
+  };
+  long long t0 = 0;
+  if (mode >= 3) {
+    const bool coh = mode == 4;
+    d2v ra[2][8], rb[2][8];
+    tile_load_regs(ra[0], tile_at(0, 0), tid, coh);
+    tile_load_regs(rb[0], tile_at(0, 1), tid, coh);
+    tile_load_regs(ra[1], tile_at(1, 0), tid, coh);
+    tile_load_regs(rb[1], tile_at(1, 1), tid, coh);
+    __builtin_amdgcn_s_waitcnt(0);
+    tile_regs_to_lds(sh.u.stage[0][0], ra[0], tid);
+    tile_regs_to_lds(sh.u.stage[0][1], rb[0], tid);
+    __syncthreads();
+    t0 = __builtin_amdgcn_s_memrealtime();
+    // two steps per trip: the register buffers are indexed by constants
+#define BTA_KSTEP(C, KK)                                                  \
+  do {                                                                    \
+    if ((KK) + 2 < steps) {                                               \
+      tile_load_regs(ra[C], tile_at((KK) + 2, 0), tid, coh);              \
+      tile_load_regs(rb[C], tile_at((KK) + 2, 1), tid, coh);              \
+    }                                                                     \
+    mma_ptile(acc, sh.u.stage[C][0], sh.u.stage[C][1], tid);              \
+    if ((KK) + 1 < steps) {                                               \
+      tile_regs_to_lds(sh.u.stage[1 - (C)][0], ra[1 - (C)], tid);         \
+      tile_regs_to_lds(sh.u.stage[1 - (C)][1], rb[1 - (C)], tid);         \
+    }                                                                     \
+    __syncthreads();                                                      \
+  } while (0)
+    for (int kk = 0; kk < steps; kk += 2) {
+      BTA_KSTEP(0, kk);
+      if (kk + 1 < steps) BTA_KSTEP(1, kk + 1);
+    }
+#undef BTA_KSTEP
+  } else {
+    if (mode != 1) {
+      tile_load_lds_dev(sh.u.stage[0][0], tile_at(0, 0), tid, mode == 2);
+      tile_load_lds_dev(sh.u.stage[0][1], tile_at(0, 1), tid, mode == 2);
+    } else {
+      for (int e = tid; e < 2 * PT; e += NT) sh.u.stage[0][0][e] = 1e-3 * (e & 7);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    t0 = __builtin_amdgcn_s_memrealtime();
+    for (int kk = 0; kk < steps; ++kk) {
+      const int cur = mode == 1 ? 0 : (kk & 1);
+      if (mode != 1 && kk + 1 < steps) {
+        tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][0], tile_at(kk + 1, 0), tid, mode == 2);
+        tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][1], tile_at(kk + 1, 1), tid, mode == 2);
+      }
+      mma_ptile(acc, sh.u.stage[cur][0], sh.u.stage[cur][1], tid);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+  }
+  const long long t1 = __builtin_amdgcn_s_memrealtime();
+  if (tid == 0) ticks[blockIdx.x] = t1 - t0;
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) s += acc.v[i][j][0] + acc.v[i][j][1] + acc.v[i][j][2] + acc.v[i][j][3];
+  out[(int64_t)blockIdx.x * NT + tid] = s;
+}
+}  // namespace bta
+
+BTA_TESTING_API int bta_internal_kloop_probe(const double* d_M, int64_t ld, int64_t span_rows, int steps, int mode,
+                                             int grid, long long* d_ticks, double* d_out, hipStream_t s) {
+  if (!d_M || !d_ticks || !d_out || steps < 1 || grid < 1 || ld < 64 || ld % 64 || span_rows < 64) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(bta::kloop_probe_kernel, dim3((unsigned)grid), dim3(bta::NT), 0, s, d_M, ld, span_rows, steps, mode,
+                     d_ticks, d_out);
   return (int)hipGetLastError();
 }

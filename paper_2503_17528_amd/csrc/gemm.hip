@@ -987,6 +987,88 @@ hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- split-k
+// C = beta*Cin + alpha*sum_s P_s over the partial products of a split launch
+// (summed in split order: deterministic), with the problem's store mode.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const double* P, int S, int M, int N, const double* Cin,
+                                                            double* C, int64_t ldc, double alpha, double beta, int store) {
+  const int64_t MN = (int64_t)M * N;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < MN; e += (int64_t)gridDim.x * 256) {
+    const int r = (int)(e / N), c = (int)(e - (int64_t)r * N);
+    if (store != ST_FULL && c > r) continue;
+    double v = 0.0;
+    for (int q = 0; q < S; ++q) v += P[q * MN + e];
+    v *= alpha;
+    if (beta != 0.0) v += beta * Cin[(int64_t)r * ldc + c];
+    C[(int64_t)r * ldc + c] = v;
+    if (store == ST_LOWER_MIRROR && c < r) C[(int64_t)c * ldc + r] = v;
+  }
+}
+
+int splitk_factor(const GProb& p, size_t ws_doubles) {
+  if (p.nb0 != 1 || p.nb1 != 1 || p.nseg < 1 || p.M <= 0 || p.N <= 0) return 1;
+  for (int q = 0; q < p.nseg; ++q)
+    if (p.seg[q].tri != TRI_NONE) return 1;
+  const int K0 = p.seg[0].K;
+  GemmArgs tmp{};
+  GProb c = p;
+  const long long t64 = plan_tiles(tmp, &c, 1, 64, 64);
+  int cus = device_cu_count();
+  if (cus <= 0 && g_dry) cus = 256;  // host dry run: plan for the full chip
+  cus = std::max(1, cus);
+  if (t64 <= 0 || 2 * t64 > cus) return 1;
+  int S = (int)std::min<long long>(GEMM_MAX_PROBS, cus / t64);
+  S = std::min(S, K0 / 128);  // at least 128 of k per split
+  while (S > 1 && (size_t)S * p.M * p.N > ws_doubles) --S;
+  return S >= 2 ? S : 1;
+}
+
+hipError_t gemm_launch_split(GProb* probs, int nprob, hipStream_t stream, double* ws, size_t ws_doubles) {
+  if (g_rec || nprob != 1 || ws == nullptr) return gemm_launch(probs, nprob, stream);
+  const GProb& p = probs[0];
+  const int S = splitk_factor(p, ws_doubles);
+  if (S < 2) return gemm_launch(probs, nprob, stream);
+  const int K0 = p.seg[0].K;
+  // split boundaries on multiples of 64 (16-byte aligned operand rows stay aligned)
+  const int chunk = ((K0 + S - 1) / S + 63) / 64 * 64;
+  GProb sub[GEMM_MAX_PROBS];
+  int ns = 0;
+  for (int q = 0; q < S; ++q) {
+    const int k0 = q * chunk, k1 = std::min(K0, k0 + chunk);
+    if (k1 <= k0 && q > 0) break;
+    GProb t = p;
+    GSeg g = p.seg[0];
+    g.A = g.at ? g.A + (int64_t)k0 * g.lda : g.A + k0;
+    g.B = g.bt ? g.B + (int64_t)k0 * g.ldb : g.B + k0;
+    g.K = k1 - k0;
+    t.seg[0] = g;
+    t.nseg = q == 0 ? p.nseg : 1;  // the short second segment goes with the first split
+    t.Cin = nullptr;
+    t.Cout = ws + (int64_t)q * p.M * p.N;
+    t.ldc = p.N; t.sC0 = 0; t.sC1 = 0;
+    t.alpha = 1.0; t.beta = 0.0;
+    t.store = p.store == ST_FULL ? ST_FULL : ST_LOWER;
+    sub[ns++] = t;
+  }
+  hipError_t e = gemm_launch(sub, ns, stream);
+  if (e != hipSuccess) return e;
+  if (g_dry) {
+    ++g_dry->op;
+    for (int q = 0; q < ns; ++q) g_dry->add(ws + (int64_t)q * p.M * p.N, p.M, p.N, p.N, false);
+    if (p.beta != 0.0) g_dry->add(p.Cin, p.M, p.N, p.ldc, false);
+    g_dry->add(p.Cout, p.M, p.N, p.ldc, true);
+    if (p.store == ST_LOWER_MIRROR) g_dry->add(p.Cout, p.N, p.M, p.ldc, true);
+    return hipSuccess;
+  }
+  const int64_t MN = (int64_t)p.M * p.N;
+  const unsigned grid = (unsigned)std::min<int64_t>(2048, (MN + 255) / 256);
+  timing_mark(KT_GEMM, true, stream);
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid), dim3(256), 0, stream, ws, ns, p.M, p.N, p.Cin, p.Cout, p.ldc,
+                     p.alpha, p.beta, p.store);
+  timing_mark(KT_GEMM, false, stream);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- small kernels
 
 __global__ __launch_bounds__(NT) void trinv_diag_tiles_kernel(const double* L, int64_t ldL, int64_t sL, double* W,
@@ -1151,6 +1233,23 @@ BTA_TESTING_API int bta_internal_gemm(
   p.M = M; p.N = N; p.nb0 = 1; p.nb1 = 1;
   p.alpha = alpha; p.beta = beta; p.store = store; p.lower_tiles = lower_tiles;
   return (int)bta::gemm_launch(&p, 1, s);
+}
+
+// The same product through the split-k path (ws: S*M*N doubles of partials;
+// *splits receives the split count used, 1 = none).
+BTA_TESTING_API int bta_internal_gemm_split(
+    int M, int N, int K, const double* A, int64_t lda, int at, const double* B, int64_t ldb, int bt, const double* Cin,
+    double* C, int64_t ldc, double alpha, double beta, int store, int lower_tiles, double* ws, size_t ws_doubles,
+    int* splits, hipStream_t s) {
+  bta::GProb p{};
+  p.seg[0].A = A; p.seg[0].B = B; p.seg[0].lda = lda; p.seg[0].ldb = ldb; p.seg[0].K = K;
+  p.seg[0].at = at; p.seg[0].bt = bt; p.seg[0].tri = bta::TRI_NONE;
+  p.nseg = 1;
+  p.Cin = Cin; p.Cout = C; p.ldc = ldc;
+  p.M = M; p.N = N; p.nb0 = 1; p.nb1 = 1;
+  p.alpha = alpha; p.beta = beta; p.store = store; p.lower_tiles = lower_tiles;
+  if (splits) *splits = bta::splitk_factor(p, ws_doubles);
+  return (int)bta::gemm_launch_split(&p, 1, s, ws, ws_doubles);
 }
 
 namespace bta {

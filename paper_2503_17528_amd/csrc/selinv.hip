@@ -168,7 +168,7 @@ SyncLease::~SyncLease() {
   g_sync_free[ctx_->dev].push_back(ctx_);
 }
 
-SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a) {
+SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a, bool split) {
   SelinvPlan sp{};
   const int64_t T = (b + 63) / 64;
   // enough blocks per chunk to give the 64-tile inverses ~512 workgroups,
@@ -187,6 +187,9 @@ SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a) {
   sp.off_PR = take(8 * (size_t)std::max<int64_t>(1, a * b * n));
   sp.off_Xp = take(8 * 2 * bb);  // X_{i+1,i} of two consecutive steps
   sp.off_WT = take(8 * (size_t)std::max<int64_t>(1, 2 * a * a));
+  // split-k partial products of the sweep at small b (few output tiles)
+  sp.split_doubles = (split && b <= 1024) ? (size_t)GEMM_MAX_PROBS * bb : 0;
+  sp.off_split = take(8 * std::max<size_t>(1, sp.split_doubles));
   sp.bytes = off;
   return sp;
 }
@@ -215,6 +218,7 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
   double* Xp = reinterpret_cast<double*>(w + sp.off_Xp);
   double* PR = reinterpret_cast<double*>(w + sp.off_PR);  // P_R of every block (a x b each)
   double* WT = reinterpret_cast<double*>(w + sp.off_WT);
+  double* SK = sp.split_doubles ? reinterpret_cast<double*>(w + sp.off_split) : nullptr;
   const int64_t bb = b * b, ab = a * b;
   const int ib = (int)b, ia = (int)a;
   // outputs may alias the inputs exactly: P_B = L_{i+1,i} W_i then goes to
@@ -342,7 +346,7 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       p.Cout = Xb; p.ldc = b;
       p.M = ib; p.N = ib;
       p.alpha = -1.0;
-      BTA_TRY(gemm_launch(&p, 1, s));
+      BTA_TRY(gemm_launch_split(&p, 1, s, SK, sp.split_doubles));
     }
     set_stage(2, step, 1);
     {  // X_ii = V_i - X_{i+1,i}^T P_B - X_{n,i}^T P_R  (lower, mirrored; no
@@ -356,7 +360,7 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       p.alpha = -1.0; p.beta = 1.0;
       p.lower_tiles = 1;
       p.store = ST_LOWER_MIRROR;
-      BTA_TRY(gemm_launch(&p, 1, s));
+      BTA_TRY(gemm_launch_split(&p, 1, s, SK, sp.split_doubles));
     }
     set_stage(2, step, 3);
     if (has_sub) {

@@ -234,10 +234,12 @@ def factor_block_torch(wl: Workload, seed: int, kind: int, i: int, device):
     raise ValueError(kind)
 
 
-def make_torch(wl: Workload, seed: int, device, with_factor: bool = False, out: Optional[dict] = None):
+def make_torch(wl: Workload, seed: int, device, with_factor: bool = False, out: Optional[dict] = None,
+               progress=None):
     """Draw the factor on ``device`` block by block and assemble ``Q = L L^T``
     there.  Only two factor block-columns are alive at a time unless
-    ``with_factor`` is set.  ``out`` may pass preallocated D, B, R, T."""
+    ``with_factor`` is set.  ``out`` may pass preallocated D, B, R, T;
+    ``progress(done, n)`` (optional) is called every 32 blocks."""
     import torch
 
     n, b, a = wl.n, wl.b, wl.a
@@ -279,6 +281,8 @@ def make_torch(wl: Workload, seed: int, device, with_factor: bool = False, out: 
             if Ls is not None:
                 out["LB"][i].copy_(Ls)
         prev_sub, prev_arrow = Ls, Lr
+        if progress is not None and (i % 32 == 31 or i == n - 1):
+            progress(i + 1, n)
     T.copy_(0.5 * (T + T.T))
     if with_factor:
         out["LT"] = LT

@@ -1,0 +1,64 @@
+"""The autotuners on the GPU: the factor tuner times every candidate (median
+of three runs) and records the fastest lookahead and load path, which the
+next factorization then uses (checked against the oracle); the batched
+selected inversion records its per-stage tile choices on first use; both
+appear in the table dump and survive a save / load round trip."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_17528_amd import synth
+from tests.gpu_util import TOL, errs, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def test_factor_tuner_and_batched_tuner(tmp_path):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2503_17528_amd import autotune, bta
+
+    bta.lib()
+    try:
+        _run(torch, autotune, bta, tmp_path)
+    finally:
+        autotune.clear()  # later tests run with the built-in defaults
+
+
+def _run(torch, autotune, bta, tmp_path):
+    n, b, a = 6, 256, 4
+    say(f"case autotune factor n={n} b={b} a={a}")
+    times = autotune.tune_factor(n, b, a, looks=(1, 2, 3), cached=(0, 1), reps=3, log=say)
+    assert len(times) == 6 and all(t > 0 for t in times.values())
+    look = autotune.get_entry(autotune.key("factor", b, a, "look"))
+    cached = autotune.get_entry(autotune.key("factor", b, a, "cached"))
+    best = min(times, key=times.get)
+    assert best == f"look={look},cached={cached}", (best, look, cached)
+
+    # the tuned settings are the ones the next factorization runs with
+    Q = synth.make_np(synth.workload(n, b, a), 3)
+    F = oracle.pobtaf(Q["D"], Q["B"], Q["R"], Q["T"])
+    D, B, R, T = (torch.from_numpy(Q[k]).to("cuda") for k in "DBRT")
+    L = bta.factor(D, B, R, T)
+    torch.cuda.synchronize()
+    e = errs(dict(zip("DBRT", to_np(L[:4]))), {"D": F["LD"], "B": F["LB"], "R": F["LR"], "T": F["LT"]})
+    say(f"   tuned factor vs oracle: {e}")
+    assert max(e.values()) < TOL
+
+    # batched selected inversion: first use measures and records its stage choices
+    mats = [synth.make_torch(synth.workload(4, 128, 2), 70 + k, "cuda") for k in range(3)]
+    batch = bta.Batch(mats)
+    batch.factor()
+    batch.selinv()
+    torch.cuda.synchronize()
+    tab = autotune.table()
+    stage_keys = [k for k in tab if "|selinv_batched[" in k and k.endswith("|tile128")]
+    say(f"   table: {len(tab)} entries, {len(stage_keys)} batched stage classes")
+    assert any(k.endswith(f"|factor|b={b}|a={a}|look") for k in tab)
+    assert stage_keys and all(tab[k] in (0, 1) for k in stage_keys)
+    path = str(tmp_path / "tune.json")
+    autotune.save(path)
+    autotune.clear()
+    autotune.load(path)
+    assert autotune.table() == tab
