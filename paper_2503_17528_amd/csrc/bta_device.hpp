@@ -232,6 +232,17 @@ __device__ __forceinline__ void tile_store_dev(const double* lds, double* out, i
   }
 }
 
+// Rows r0 .. r0 + nrows - 1 (nrows a multiple of 8) of a 64-column LDS tile to
+// global memory (device-coherent stores).
+__device__ __forceinline__ void tile_store_rows_dev(const double* lds, double* out, int64_t ld, int r0, int nrows, int tid) {
+  const int c2 = (tid & 31) * 2, rr = tid >> 5;
+  for (int j = 0; 8 * j < nrows; ++j) {
+    const int row = r0 + 8 * j + rr;
+    st_dev(out + (int64_t)row * ld + c2, lds[row * LDS_LD + c2]);
+    st_dev(out + (int64_t)row * ld + c2 + 1, lds[row * LDS_LD + c2 + 1]);
+  }
+}
+
 // tile_store_dev of a lower-triangular tile whose LDS image holds stale values
 // above the diagonal: exact zeros are stored there instead.
 __device__ __forceinline__ void tile_store_lower_dev(const double* lds, double* out, int64_t ld, int rows, int tid) {
@@ -392,10 +403,16 @@ __device__ __forceinline__ void blk_store(const d4& c, double* X, int ld, int la
 // VAR 0: the pivot of column k+1 is broadcast from its updated column entry;
 // VAR 1: lane k+1 forms the next pivot from its own L(k+1,k) (one FMA), so
 // the cross-lane read of L(k+1,k) leaves the pivot chain.  TIMED: thread 0
-// writes s_memrealtime stamps of the phase ends into ts[0..7].
+// writes s_memrealtime stamps of the phase ends into ts[0..10].
+// early_flag (optional): a flag published (agent-scope release, value 1) once
+// panel 0 is done and every wave's earlier global stores are complete, so that
+// stores issued before the call are published off the critical path.
+// Wg (optional): W is also stored to global memory (device coherent, row
+// stride 64): rows 0..31 while the 32-level recursion runs, rows 32..63 at the
+// end; the caller waits for the stores before publishing W.
 template <int VAR, bool TIMED>
 __device__ __forceinline__ int chol_inv_tile_mfma_t(double* S, double* Wl, double* rinv, double* tmp, int* fail_sh, int tid,
-                                                    long long* ts) {
+                                                    long long* ts, int* early_flag = nullptr, double* Wg = nullptr) {
   const int r = tid & 63, q = tid >> 6;
   if (TIMED && tid == 0) ts[0] = __builtin_amdgcn_s_memrealtime();
 #pragma unroll
@@ -435,7 +452,10 @@ __device__ __forceinline__ int chol_inv_tile_mfma_t(double* S, double* Wl, doubl
 #pragma unroll
       for (int m = 0; m < 16; ++m) S[r * LDS_LD + 16 * p + m] = s[m];
     }
+    if (p == 0 && early_flag) __builtin_amdgcn_s_waitcnt(0);  // every wave's earlier stores complete
     __syncthreads();
+    if (p == 0 && early_flag && tid == 192)
+      __hip_atomic_store(early_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     if (TIMED && tid == 0) ts[1 + 2 * p] = __builtin_amdgcn_s_memrealtime();
     if (p < 3) {
       // rank-16 update of the trailing lower blocks (I, J), p < J <= I
@@ -502,6 +522,8 @@ __device__ __forceinline__ int chol_inv_tile_mfma_t(double* S, double* Wl, doubl
   }
   __syncthreads();
   if (TIMED && tid == 0) ts[9] = __builtin_amdgcn_s_memrealtime();
+  // rows 0..31 of W are final: their global stores overlap the 32-level recursion
+  if (Wg) tile_store_rows_dev(Wl, Wg, 64, 0, 32, tid);
   // ---- level 32: U = L21 W11 (one 16 x 16 block per wave), then W21 = -W22 U
   {
     const int I = 2 + (q >> 1), J = q & 1;
@@ -521,12 +543,19 @@ __device__ __forceinline__ int chol_inv_tile_mfma_t(double* S, double* Wl, doubl
   }
   __syncthreads();
   if (TIMED && tid == 0) ts[10] = __builtin_amdgcn_s_memrealtime();
+  if (Wg) tile_store_rows_dev(Wl, Wg, 64, 32, 32, tid);
   const int f = *fail_sh;
   return f == 0x7fffffff ? 0 : f;
 }
 
 __device__ __forceinline__ int chol_inv_tile_mfma(double* S, double* Wl, double* rinv, double* tmp, int* fail_sh, int tid) {
   return chol_inv_tile_mfma_t<0, false>(S, Wl, rinv, tmp, fail_sh, tid, nullptr);
+}
+
+// chol_inv_tile_mfma with the early publication and the global W stores above.
+__device__ __forceinline__ int chol_inv_tile_mfma_pub(double* S, double* Wl, double* rinv, double* tmp, int* fail_sh,
+                                                      int tid, int* early_flag, double* Wg) {
+  return chol_inv_tile_mfma_t<0, false>(S, Wl, rinv, tmp, fail_sh, tid, nullptr, early_flag, Wg);
 }
 
 // In-LDS inverse of a lower-triangular 64 x 64 tile by forward substitution on

@@ -541,12 +541,16 @@ __device__ __forceinline__ void diag_finish(const FactorParams& p, int i, int c,
     // minus L(g,g-1) L(g,g-1)^T = x x^T on the lower triangle, then publish L(g,g-1)
     // (its barrier also orders these LDS updates before the factorization)
     syrk_lower(sh.u.f.As, sh.u.f.Bs, tid);
-    publish(pflag, tid);
+    __syncthreads();  // the updates are in LDS before the factorization reads them
     if (rec && tid == 0) rec[1] = __builtin_amdgcn_s_memrealtime();
   }
 
-  // factor and invert A(g,g) - sum over all k < g
-  const int f = uni(chol_inv_tile_mfma(sh.u.f.As, sh.u.f.Bs, sh.rinv, sh.pan, &sh.fail, tid));
+  // factor and invert A(g,g) - sum over all k < g; L(g,g-1)'s flag is published
+  // after the first panel (its stores had that long to complete), and W goes
+  // to global memory as its rows become final
+  double* Wout = p.Wd + ((int64_t)i * T + c) * 4096;
+  const int f = uni(chol_inv_tile_mfma_pub(sh.u.f.As, sh.u.f.Bs, sh.rinv, sh.pan, &sh.fail, tid, has_pre ? pflag : nullptr,
+                                           Wout));
   if (rec && tid == 0) rec[2] = __builtin_amdgcn_s_memrealtime();
   if (f != 0 && f <= rows && tid == 0) {
     const long long row0 = (long long)i * b + (long long)c * 64;
@@ -554,8 +558,6 @@ __device__ __forceinline__ void diag_finish(const FactorParams& p, int i, int c,
   }
   // the flag covers W only: no task reads a diagonal tile of L (every solve
   // uses W), so L(g,g) is stored after the publication, off the chain
-  double* Wout = p.Wd + ((int64_t)i * T + c) * 4096;
-  tile_store_dev(sh.u.f.Bs, Wout, 64, 64, 64, tid);
   publish(p.flags + fl_D(p, i, c, c), tid);
   tile_store_lower_dev(sh.u.f.As, out, b, rows, tid);
   __builtin_amdgcn_s_setprio(0);

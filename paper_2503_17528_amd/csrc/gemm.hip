@@ -990,18 +990,39 @@ hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream) {
 // ---------------------------------------------------------------- split-k
 // C = beta*Cin + alpha*sum_s P_s over the partial products of a split launch
 // (summed in split order: deterministic), with the problem's store mode.
+// Block (x, r) covers columns 512x .. 512x + 511 of row r, two per thread
+// (16-byte loads when N is even); blocks entirely above the diagonal of a
+// lower store exit at once.
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(const double* P, int S, int M, int N, const double* Cin,
                                                             double* C, int64_t ldc, double alpha, double beta, int store) {
+  const int r = blockIdx.y;
+  const int c0 = blockIdx.x * 512;
+  if (store != ST_FULL && c0 > r) return;
   const int64_t MN = (int64_t)M * N;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < MN; e += (int64_t)gridDim.x * 256) {
-    const int r = (int)(e / N), c = (int)(e - (int64_t)r * N);
-    if (store != ST_FULL && c > r) continue;
-    double v = 0.0;
-    for (int q = 0; q < S; ++q) v += P[q * MN + e];
-    v *= alpha;
-    if (beta != 0.0) v += beta * Cin[(int64_t)r * ldc + c];
-    C[(int64_t)r * ldc + c] = v;
-    if (store == ST_LOWER_MIRROR && c < r) C[(int64_t)c * ldc + r] = v;
+  const int c = c0 + 2 * threadIdx.x;
+  if (c >= N) return;
+  const int64_t e = (int64_t)r * N + c;
+  const bool pair = (N % 2 == 0) && (c + 1 < N);
+  double v0 = 0.0, v1 = 0.0;
+  if (pair) {
+    for (int q = 0; q < S; ++q) {
+      const d2v x = *reinterpret_cast<const d2v*>(P + q * MN + e);
+      v0 += x[0];
+      v1 += x[1];
+    }
+  } else {
+    for (int q = 0; q < S; ++q) {
+      v0 += P[q * MN + e];
+      if (c + 1 < N) v1 += P[q * MN + e + 1];
+    }
+  }
+  for (int h = 0; h < 2; ++h) {
+    const int cc = c + h;
+    if (cc >= N || (store != ST_FULL && cc > r)) continue;
+    double v = alpha * (h ? v1 : v0);
+    if (beta != 0.0) v += beta * Cin[(int64_t)r * ldc + cc];
+    C[(int64_t)r * ldc + cc] = v;
+    if (store == ST_LOWER_MIRROR && cc < r) C[(int64_t)cc * ldc + r] = v;
   }
 }
 
@@ -1060,10 +1081,9 @@ hipError_t gemm_launch_split(GProb* probs, int nprob, hipStream_t stream, double
     if (p.store == ST_LOWER_MIRROR) g_dry->add(p.Cout, p.N, p.M, p.ldc, true);
     return hipSuccess;
   }
-  const int64_t MN = (int64_t)p.M * p.N;
-  const unsigned grid = (unsigned)std::min<int64_t>(2048, (MN + 255) / 256);
+  const dim3 grid((unsigned)((p.N + 511) / 512), (unsigned)p.M);
   timing_mark(KT_GEMM, true, stream);
-  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid), dim3(256), 0, stream, ws, ns, p.M, p.N, p.Cin, p.Cout, p.ldc,
+  hipLaunchKernelGGL(splitk_reduce_kernel, grid, dim3(256), 0, stream, ws, ns, p.M, p.N, p.Cin, p.Cout, p.ldc,
                      p.alpha, p.beta, p.store);
   timing_mark(KT_GEMM, false, stream);
   return hipGetLastError();
