@@ -352,6 +352,9 @@ hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, h
       }
       tuned = med[1] < med[0] ? 1 : 0;
       tune_set(stage_key(ex), tuned, true);
+      // the last timed run used the 128 tiling: leave the chosen tiling's
+      // result, so that this call's bits are those of the replays
+      if (tuned == 0) BTA_TRY_E(launch_stage(ex, dtab, 0, stream));
     } else {
       if (tuned < 0) tuned = heuristic_big(ex);
       BTA_TRY_E(launch_stage(ex, dtab, (int)tuned, stream));
