@@ -165,6 +165,20 @@ __device__ __forceinline__ void tile_load_lds_dev(double* dst, const OpTile& t, 
   }
 }
 
+// tile_load_lds_dev for a tile known to take the direct path (even leading
+// dimension and column count, 16-byte aligned start; device coherent): the
+// same loads without the test, so that a k loop over such tiles is straight code.
+__device__ __forceinline__ void tile_load_lds_fast(double* dst, const OpTile& t, int tid) {
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int slot = (w * 8 + j) * 64 + lane;
+    const int m = slot >> 5, pc = (slot & 31) ^ (m & 15);
+    const double* src = (m < t.rows && 2 * pc < t.cols) ? t.p + (int64_t)m * t.ld + 2 * pc : k_zero_pair;
+    lds_dma16_dev(src, dst + (w * 8 + j) * 128);
+  }
+}
+
 // The four consecutive k values 16*kg + 4*g .. +3 of row m of a pieced tile.
 __device__ __forceinline__ d4 ptile_row4(const double* T, int m, int kg, int g) {
   const int p0 = 8 * kg + 2 * g;

@@ -60,6 +60,8 @@ struct FactorParams {
   long long step_full, step_last;  // tasks per step (with / without SUB)
   int look;                        // DIAG lookahead: DIAG(i,c) is dispatched with column c - look of its step
   int cached;                      // 1: k-loop operand tiles are read through the L2 (line-aligned tiles only)
+  int fast;                        // 1: every k-loop operand tile takes the direct 16-byte path, device
+                                   // coherent (b and a even, L arrays 16-byte aligned, cached == 0)
   long long spin_limit;
   unsigned long long* trace;  // optional: 8 words per ticket (start, k loop done, end, type | workgroup << 8,
                               // W ready (DIAG: of g-1), L(g,g-1) published (DIAG), tile factored (DIAG),
@@ -280,6 +282,14 @@ __device__ __forceinline__ long long uni64(long long v) {
   return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+// One k-loop operand tile into LDS: the direct path without its test when the
+// launch's tiles all take it (F), else the general loader.
+template <bool F>
+__device__ __forceinline__ void load_k(const FactorParams& p, double* dst, const OpTile& t, int tid) {
+  if constexpr (F) tile_load_lds_fast(dst, t, tid);
+  else tile_load_lds_dev(dst, t, tid, p.cached != 0);
+}
+
 // Block until flags are set (thread 0 polls); returns false on abort.
 __device__ __forceinline__ bool wait_ready(const FactorParams& p, const int* f1, const int* f2, Shared& sh, int tid) {
   if (tid == 0) {
@@ -322,6 +332,7 @@ __device__ __forceinline__ void publish(int* flag, int tid) {
 // One k loop over the k < g-1 shared by both accumulates
 //   acc1 = -(A(g,g) - sum_k L(g,k) L(g,k)^T),  acc2 = -(A(g,g-1) - sum_k L(g,k) L(g-1,k)^T)
 // (a padded diagonal tile gets -1 on the padded diagonal).
+template <bool F>
 __device__ __forceinline__ void diag_partials(const FactorParams& p, const Task& t, Shared& sh, int tid, Acc& acc1,
                                               Acc& acc2, unsigned long long* rec) {
   const int T = p.T, b = p.b;
@@ -364,35 +375,35 @@ __device__ __forceinline__ void diag_partials(const FactorParams& p, const Task&
   const int nk = has_pre ? uni(ksources(p, pt, -1, nullptr)) : 0;
   bool aborted = false;
   if (nk > 0) {
-    int upto = 0;
-    KSrc s0;
-    ksources(p, pt, 0, &s0);
-    if (!wait_ready(p, s0.fa, s0.fb, sh, tid)) aborted = true;
-    upto = 1;
-    tile_load_lds_dev(sh.u.stage[0][0], s0.a, tid, p.cached != 0);
-    tile_load_lds_dev(sh.u.stage[0][1], s0.b, tid, p.cached != 0);
-    for (int kk = 0; kk < nk && !aborted; ++kk) {
-      if (tid < 64) {
-        const int u = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, pt, kk + 1, nk, tid) : upto;
-        if (tid == 0) sh.upto = u;
-      }
-      __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of k tile kk have landed
-      __syncthreads();                // everyone's; and stage (kk+1)&1 is no longer read
-      const int u = uni(sh.upto);
-      upto = u > upto ? u : upto;
-      if (kk + 1 < nk) {
-        KSrc sn;
-        ksources(p, pt, kk + 1, &sn);
-        if (kk + 1 >= upto) {
-          if (!wait_ready(p, sn.fa, sn.fb, sh, tid)) aborted = true;
-          if (rec && tid == 0) rec[7] = __builtin_amdgcn_s_memrealtime();
-          upto = kk + 2;
+      int upto = 0;
+      KSrc s0;
+      ksources(p, pt, 0, &s0);
+      if (!wait_ready(p, s0.fa, s0.fb, sh, tid)) aborted = true;
+      upto = 1;
+      load_k<F>(p, sh.u.stage[0][0], s0.a, tid);
+      load_k<F>(p, sh.u.stage[0][1], s0.b, tid);
+      for (int kk = 0; kk < nk && !aborted; ++kk) {
+        if (tid < 64) {
+          const int u = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, pt, kk + 1, nk, tid) : upto;
+          if (tid == 0) sh.upto = u;
         }
-        tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][0], sn.a, tid, p.cached != 0);
-        tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][1], sn.b, tid, p.cached != 0);
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of k tile kk have landed
+        __syncthreads();                // everyone's; and stage (kk+1)&1 is no longer read
+        const int u = uni(sh.upto);
+        upto = u > upto ? u : upto;
+        if (kk + 1 < nk) {
+          KSrc sn;
+          ksources(p, pt, kk + 1, &sn);
+          if (kk + 1 >= upto) {
+            if (!wait_ready(p, sn.fa, sn.fb, sh, tid)) aborted = true;
+            if (rec && tid == 0) rec[7] = __builtin_amdgcn_s_memrealtime();
+            upto = kk + 2;
+          }
+          load_k<F>(p, sh.u.stage[(kk + 1) & 1][0], sn.a, tid);
+          load_k<F>(p, sh.u.stage[(kk + 1) & 1][1], sn.b, tid);
+        }
+        mma_ptile2(acc1, acc2, sh.u.stage[kk & 1][0], sh.u.stage[kk & 1][1], tid);
       }
-      mma_ptile2(acc1, acc2, sh.u.stage[kk & 1][0], sh.u.stage[kk & 1][1], tid);
-    }
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -571,15 +582,17 @@ __device__ __forceinline__ void diag_finish(const FactorParams& p, int i, int c,
   }
 }
 
+template <bool F>
 __device__ __forceinline__ void run_diag(const FactorParams& p, const Task& t, Shared& sh, int tid,
                                          unsigned long long& tr1, unsigned long long* rec) {
   Acc acc1, acc2;
-  diag_partials(p, t, sh, tid, acc1, acc2, rec);
+  diag_partials<F>(p, t, sh, tid, acc1, acc2, rec);
   if (rec && tid == 0) tr1 = __builtin_amdgcn_s_memrealtime();
   diag_finish(p, t.i, t.c, sh, tid, acc1, acc2, rec ? rec + 4 : nullptr);
 }
 
 // One task of one matrix: accumulate, finish, publish.
+template <bool F>
 __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Shared& sh, int tid) {
   {
     Task t = decode(p, tk);
@@ -588,7 +601,7 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
     if (p.trace && tid == 0) tr0 = __builtin_amdgcn_s_memrealtime();
     if (t.type == T_DIAG) {
       unsigned long long* rec = p.trace ? p.trace + 8 * tk : nullptr;
-      run_diag(p, t, sh, tid, tr1, rec);
+      run_diag<F>(p, t, sh, tid, tr1, rec);
       if (rec && tid == 0) {
         rec[0] = tr0;
         rec[1] = tr1;
@@ -682,35 +695,35 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
     const int nk = uni(ksources(p, t, -1, nullptr));
     bool aborted = false;
     if (nk > 0) {
-      int upto = 0;
-      KSrc s0;
-      ksources(p, t, 0, &s0);
-      if (!wait_ready(p, s0.fa, s0.fb, sh, tid)) aborted = true;
-      upto = 1;
-      tile_load_lds_dev(sh.u.stage[0][0], s0.a, tid, p.cached != 0);
-      tile_load_lds_dev(sh.u.stage[0][1], s0.b, tid, p.cached != 0);
-      for (int kk = 0; kk < nk && !aborted; ++kk) {
-        if (tid < 64) {
-          const int u = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, t, kk + 1, nk, tid) : upto;
-          if (tid == 0) sh.upto = u;
-        }
-        __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of k tile kk have landed
-        __syncthreads();                // everyone's; and stage (kk+1)&1 is no longer read
-        const int u = uni(sh.upto);
-        upto = u > upto ? u : upto;
-        if (kk + 1 < nk) {
-          KSrc sn;
-          ksources(p, t, kk + 1, &sn);
-          if (kk + 1 >= upto) {  // not final yet: block (rare once the pipeline is primed)
-            if (!wait_ready(p, sn.fa, sn.fb, sh, tid)) { aborted = true; }
-            if (p.trace && tid == 0) p.trace[8 * tk + 7] = __builtin_amdgcn_s_memrealtime();
-            upto = kk + 2;
+        int upto = 0;
+        KSrc s0;
+        ksources(p, t, 0, &s0);
+        if (!wait_ready(p, s0.fa, s0.fb, sh, tid)) aborted = true;
+        upto = 1;
+        load_k<F>(p, sh.u.stage[0][0], s0.a, tid);
+        load_k<F>(p, sh.u.stage[0][1], s0.b, tid);
+        for (int kk = 0; kk < nk && !aborted; ++kk) {
+          if (tid < 64) {
+            const int u = (kk + 1 < nk && kk + 1 >= upto) ? extend_ready(p, t, kk + 1, nk, tid) : upto;
+            if (tid == 0) sh.upto = u;
           }
-          tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][0], sn.a, tid, p.cached != 0);
-          tile_load_lds_dev(sh.u.stage[(kk + 1) & 1][1], sn.b, tid, p.cached != 0);
+          __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of k tile kk have landed
+          __syncthreads();                // everyone's; and stage (kk+1)&1 is no longer read
+          const int u = uni(sh.upto);
+          upto = u > upto ? u : upto;
+          if (kk + 1 < nk) {
+            KSrc sn;
+            ksources(p, t, kk + 1, &sn);
+            if (kk + 1 >= upto) {  // not final yet: block (rare once the pipeline is primed)
+              if (!wait_ready(p, sn.fa, sn.fb, sh, tid)) { aborted = true; }
+              if (p.trace && tid == 0) p.trace[8 * tk + 7] = __builtin_amdgcn_s_memrealtime();
+              upto = kk + 2;
+            }
+            load_k<F>(p, sh.u.stage[(kk + 1) & 1][0], sn.a, tid);
+            load_k<F>(p, sh.u.stage[(kk + 1) & 1][1], sn.b, tid);
+          }
+          mma_ptile(acc, sh.u.stage[kk & 1][0], sh.u.stage[kk & 1][1], tid);
         }
-        mma_ptile(acc, sh.u.stage[kk & 1][0], sh.u.stage[kk & 1][1], tid);
-      }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -777,6 +790,7 @@ __device__ __forceinline__ void run_task(const FactorParams& p, long long tk, Sh
 }
 
 // Persistent workers: take tickets until the task list is exhausted.
+template <bool F>
 __device__ __forceinline__ void factor_worker(const FactorParams& p, Shared& sh) {
   const int tid = threadIdx.x;
   for (;;) {
@@ -784,7 +798,7 @@ __device__ __forceinline__ void factor_worker(const FactorParams& p, Shared& sh)
     __syncthreads();
     const long long tk = uni64(sh.ticket);
     if (tk >= p.ntasks) break;
-    run_task(p, tk, sh, tid);
+    run_task<F>(p, tk, sh, tid);
   }
 }
 
@@ -794,9 +808,12 @@ __device__ __forceinline__ void factor_worker(const FactorParams& p, Shared& sh)
 // of another task, and every task has the CU's full register file.
 constexpr size_t SOLO_LDS_PAD = 0;
 static_assert(sizeof(Shared) > 80 * 1024, "one workgroup per CU relies on the LDS footprint");
+// F: every k-loop operand tile of the launch takes the direct load path
+// (FactorParams::fast), so the k loops carry no per-tile path test.
+template <bool F>
 __global__ __launch_bounds__(NT, 1) void factor_kernel(FactorParams p) {
   __shared__ Shared sh;
-  factor_worker(p, sh);
+  factor_worker<F>(p, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -820,6 +837,7 @@ struct FactorBatchArgs {
   int* ctl;
 };
 
+template <bool F>
 __global__ __launch_bounds__(NT, 1) void factor_batched_kernel(FactorBatchArgs args) {
   __shared__ Shared sh;
   const int tid = threadIdx.x;
@@ -836,7 +854,7 @@ __global__ __launch_bounds__(NT, 1) void factor_batched_kernel(FactorBatchArgs a
     lo = uni(lo);
     const long long local = uni64(args.segs[lo].local0 + (tk - args.segs[lo].t0));
     const FactorParams p = args.mats[uni(args.segs[lo].mat)];
-    run_task(p, local, sh, tid);
+    run_task<F>(p, local, sh, tid);
   }
 }
 
@@ -913,6 +931,15 @@ static bool factor_lines_aligned(int64_t b, int64_t a, const double* LD, const d
   return b % 16 == 0 && (a == 0 || a % 16 == 0) && al(LD) && al(LB) && al(LR) && al(LT);
 }
 
+// Whether every k-loop operand tile of a factorization takes the direct
+// 16-byte load path: even b and a (even leading dimensions and column counts)
+// and 16-byte aligned L arrays.
+static bool factor_ops_direct(int64_t b, int64_t a, const double* LD, const double* LB, const double* LR,
+                              const double* LT) {
+  auto al = [](const void* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+  return b % 2 == 0 && a % 2 == 0 && al(LD) && al(LB) && al(LR) && al(LT);
+}
+
 FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   FactorPlan fp{};
   const int64_t T = (b + 63) / 64, TA = (a + 63) / 64;
@@ -956,6 +983,7 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
   p.step_last = fp.step_last;
   p.look = fp.look;
   p.cached = (factor_cached_loads(b, a) && factor_lines_aligned(b, a, LD, LB, LR, LT)) ? 1 : 0;
+  p.fast = (!p.cached && factor_ops_direct(b, a, LD, LB, LR, LT)) ? 1 : 0;
   p.trace = trace;
   p.spin_limit = 1LL << 22;  // a few seconds of polling without progress before the watchdog fires
   const int rgrid = (int)std::min<long long>(1024, (fp.nflags + 255) / 256 + 1);
@@ -967,7 +995,10 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
   const long long grid = std::min<long long>(fp.ntasks, cap);
   if (grid < fp.ntasks && grid <= fp.look + 1) return hipErrorInvalidConfiguration;  // lookahead needs more workers
   timing_mark(KT_FACTOR, true, stream);
-  hipLaunchKernelGGL(factor_kernel, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, p);
+  if (p.fast)
+    hipLaunchKernelGGL(factor_kernel<true>, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, p);
+  else
+    hipLaunchKernelGGL(factor_kernel<false>, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, p);
   timing_mark(KT_FACTOR, false, stream);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1115,6 +1146,7 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
     p.look = fp.look;
     p.spin_limit = 1LL << 22;
     p.cached = (factor_cached_loads(p.b, p.a) && factor_lines_aligned(p.b, p.a, p.LD, p.LB, p.LR, p.LT)) ? 1 : 0;
+    p.fast = (!p.cached && factor_ops_direct(p.b, p.a, p.LD, p.LB, p.LR, p.LT)) ? 1 : 0;
     p.trace = nullptr;
   }
   std::vector<int64_t> ns(bp.count);
@@ -1139,7 +1171,12 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
   const long long grid = std::min<long long>(t, (long long)num_cus);
   if (grid < t && grid <= batch_ahead_bound(bp)) return hipErrorInvalidConfiguration;  // lookahead needs more workers
   timing_mark(KT_FACTOR, true, stream);
-  hipLaunchKernelGGL(factor_batched_kernel, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, args);
+  bool all_fast = true;
+  for (const FactorParams& q : hp) all_fast = all_fast && q.fast != 0;
+  if (all_fast)
+    hipLaunchKernelGGL(factor_batched_kernel<true>, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, args);
+  else
+    hipLaunchKernelGGL(factor_batched_kernel<false>, dim3((unsigned)grid), dim3(NT), SOLO_LDS_PAD, stream, args);
   timing_mark(KT_FACTOR, false, stream);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
