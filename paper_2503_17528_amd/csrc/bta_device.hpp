@@ -167,15 +167,27 @@ __device__ __forceinline__ void tile_load_lds_dev(double* dst, const OpTile& t, 
 
 // tile_load_lds_dev for a tile known to take the direct path (even leading
 // dimension and column count, 16-byte aligned start; device coherent): the
-// same loads without the test, so that a k loop over such tiles is straight code.
+// same loads without the test, written so that the compiler emits straight
+// code.  Instruction j of wave w fills rows m = 16w + 2j + lane/32, piece
+// pc = (lane%32) ^ (m%16); every address is formed with plain adds from one
+// per-lane row base, and pieces outside rows x cols take the zero pair by a
+// select (no branch, no per-load multiply).
 __device__ __forceinline__ void tile_load_lds_fast(double* dst, const OpTile& t, int tid) {
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int lane = tid & 63;
+  // the lane terms are recomputed at every call instead of being kept live
+  // across the caller's k loop (the factor kernel has no registers to spare)
+  asm volatile("" : "+v"(lane));
+  const int m0 = 16 * w + (lane >> 5);
+  const double* rowbase = t.p + (int64_t)m0 * t.ld;
+  const int64_t step = 2 * t.ld;  // two rows per instruction
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int slot = (w * 8 + j) * 64 + lane;
-    const int m = slot >> 5, pc = (slot & 31) ^ (m & 15);
-    const double* src = (m < t.rows && 2 * pc < t.cols) ? t.p + (int64_t)m * t.ld + 2 * pc : k_zero_pair;
-    lds_dma16_dev(src, dst + (w * 8 + j) * 128);
+    const int m = m0 + 2 * j;
+    const int pc = (lane & 31) ^ (m & 15);
+    const double* q = rowbase + j * step + 2 * pc;
+    const bool ok = (m < t.rows) & (2 * pc < t.cols);
+    lds_dma16_dev(ok ? q : k_zero_pair, dst + (w * 8 + j) * 128);
   }
 }
 
