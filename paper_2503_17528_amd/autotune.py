@@ -1,20 +1,27 @@
-"""Autotuner of the factorization's tunables, and access to the library's
-tuning table.
+"""Autotuner of the factorization's and the selected inversion's tunables,
+and access to the library's tuning table.
 
 The library keeps its tuned decisions in a table keyed by
-``<arch>|<op>|b=<b>|a=<a>|<knob>`` (``tune.hip``): the factorization's DIAG
-lookahead (``look``: how many band columns ahead of the diagonal-tile chain a
-diagonal task starts its accumulation) and its k-loop load path (``cached``:
-1 reads published operand tiles through the L2), and the batched selected
-inversion's tile shape per merged stage class (``tile128``, measured by the
-library itself on first use).  ``BTA_TUNE_CACHE=<file.json>`` makes the
-library load the table from that file on first use and write measured
-entries back; ``BTA_FACTOR_LOOKAHEAD`` and ``BTA_FACTOR_CACHED`` override the
-table for every shape.
+``<arch>|<op>|b=<b>|a=<a>|<knob>`` (``tune.hip``):
 
-``tune_factor`` times candidate settings on a seeded synthetic matrix of the
-given block shape (the median of ``reps`` factorizations each, HIP events on
-the current stream) and records the fastest in the table.  Command line::
+- the factorization's DIAG lookahead (``look``: how many band columns ahead of
+  the diagonal-tile chain a diagonal task starts its accumulation);
+- its k-loop load path (``cached``: 1 reads published operand tiles through
+  the L2);
+- the largest split count of the selected inversion's sweep products at
+  small b (op ``selinv``, knob ``split``);
+- the batched selected inversion's tile shape per merged stage class
+  (``tile128``, measured by the library itself on first use).
+
+``BTA_TUNE_CACHE=<file.json>`` makes the library load the table from that file
+on first use and write measured entries back; ``BTA_FACTOR_LOOKAHEAD``,
+``BTA_FACTOR_CACHED`` and ``BTA_SELINV_SPLIT`` override the table for every
+shape.
+
+``tune_factor`` and ``tune_selinv_split`` time candidate settings on a seeded
+synthetic matrix of the given block shape (the median of ``reps`` runs each,
+HIP events on the current stream) and record the fastest in the table.
+Command line::
 
     python -m paper_2503_17528_amd.autotune --n 32 --b 2048 --a 8 --out tune.json
 """
@@ -146,8 +153,55 @@ def tune_factor(n: int, b: int, a: int, looks: Iterable[int] = (2, 4, 6, 8, 12, 
     return times
 
 
+def tune_selinv_split(n: int, b: int, a: int, splits: Iterable[int] = (1, 2, 3, 4), reps: int = 3, seed: int = 0,
+                      log=None) -> Dict[str, float]:
+    """Time bta_selinv on the factor of a seeded n x (b, a) matrix for every
+    largest split count of the sweep products (``split``: 1 = no split; the
+    library splits only where a product's 64 x 64 tiles fill under half the
+    CUs), the median of ``reps`` runs each, and record the fastest as the
+    table's ``split`` entry for (b, a).  ``BTA_SELINV_SPLIT``, when set,
+    overrides the table and makes the candidates equal.
+    Returns {"split=<s>": median ms}."""
+    import torch
+
+    if reps < 3:
+        raise ValueError("reps >= 3 (the median of at least three runs)")
+    reading = "scaled" if b >= 2048 else "literal"
+    wl = synth.workload(n, b, a, reading)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    Q = synth.make_torch(wl, seed, dev)
+    L = bta.factor(Q["D"], Q["B"], Q["R"], Q["T"])[:4]
+    out = tuple(torch.empty_like(t) for t in L)
+    work, _ = bta.workspace(bta.BTA_OP_SELINV, n, b, a, dev)
+    k = key("selinv", b, a, "split")
+    prev = get_entry(k)
+    times: Dict[str, float] = {}
+    try:
+        for sp in sorted(set(int(x) for x in splits)):
+            set_entry(k, sp)
+            ms = []
+            for _ in range(reps + 1):  # the first run warms up
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                bta.selinv(*L, out=out, work=work)
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            med = statistics.median(ms[1:])
+            times[f"split={sp}"] = med
+            if log:
+                log(f"selinv n={n} b={b} a={a} split={sp}: {med:.3f} ms")
+    finally:
+        if prev is not None:
+            set_entry(k, prev)
+    best = min(times, key=times.get)
+    set_entry(k, int(best.split("=")[1]))
+    return times
+
+
 def main(argv=None) -> int:
-    ap = argparse.ArgumentParser(description="tune the BTA factorization for one block shape")
+    ap = argparse.ArgumentParser(description="tune the BTA factorization and selected inversion for one block shape")
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--b", type=int, required=True)
     ap.add_argument("--a", type=int, default=0)
@@ -158,7 +212,9 @@ def main(argv=None) -> int:
 
     if os.path.exists(args.out):
         load(args.out)
-    times = tune_factor(args.n, args.b, args.a, reps=args.reps, log=lambda m: print(m, file=sys.stderr, flush=True))
+    say = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    times = tune_factor(args.n, args.b, args.a, reps=args.reps, log=say)
+    times.update(tune_selinv_split(args.n, args.b, args.a, reps=args.reps, log=say))
     save(args.out)
     print(json.dumps({"times_ms": times, "table": table()}))
     return 0

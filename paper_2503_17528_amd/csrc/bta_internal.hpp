@@ -96,14 +96,16 @@ hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream);
 // parts computed as one launch into ws (S*M*N doubles), then summed in split
 // order by a second launch with the problem's alpha, beta and store mode.
 // Anything else (or ws == nullptr) goes to gemm_launch.
-hipError_t gemm_launch_split(GProb* probs, int nprob, hipStream_t stream, double* ws, size_t ws_doubles);
-// The split count gemm_launch_split would use for p (1 = no split).
-int splitk_factor(const GProb& p, size_t ws_doubles);
+hipError_t gemm_launch_split(GProb* probs, int nprob, hipStream_t stream, double* ws, size_t ws_doubles,
+                             int smax = GEMM_MAX_PROBS);
+// The split count gemm_launch_split would use for p (1 = no split; at most smax).
+int splitk_factor(const GProb& p, size_t ws_doubles, int smax = GEMM_MAX_PROBS);
 
 // ---------------------------------------------------------------- selinv
 struct SelinvPlan {
   int64_t chunk;  // blocks per preprocessing chunk
   size_t split_doubles;  // split-k partials of the sweep products (0: no split)
+  int split_max;         // largest split count of a sweep product (tuning knob "split")
   size_t off_W, off_T1, off_PR, off_Xp, off_WT, off_split, bytes;
 };
 // split: reserve the split-k partials of the sweep products (single-matrix

@@ -1026,7 +1026,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const double* P, int
   }
 }
 
-int splitk_factor(const GProb& p, size_t ws_doubles) {
+int splitk_factor(const GProb& p, size_t ws_doubles, int smax) {
   if (p.nb0 != 1 || p.nb1 != 1 || p.nseg < 1 || p.M <= 0 || p.N <= 0) return 1;
   for (int q = 0; q < p.nseg; ++q)
     if (p.seg[q].tri != TRI_NONE) return 1;
@@ -1038,16 +1038,16 @@ int splitk_factor(const GProb& p, size_t ws_doubles) {
   if (cus <= 0 && g_dry) cus = 256;  // host dry run: plan for the full chip
   cus = std::max(1, cus);
   if (t64 <= 0 || 2 * t64 > cus) return 1;
-  int S = (int)std::min<long long>(GEMM_MAX_PROBS, cus / t64);
+  int S = (int)std::min<long long>(std::min(smax, GEMM_MAX_PROBS), cus / t64);
   S = std::min(S, K0 / 128);  // at least 128 of k per split
   while (S > 1 && (size_t)S * p.M * p.N > ws_doubles) --S;
   return S >= 2 ? S : 1;
 }
 
-hipError_t gemm_launch_split(GProb* probs, int nprob, hipStream_t stream, double* ws, size_t ws_doubles) {
+hipError_t gemm_launch_split(GProb* probs, int nprob, hipStream_t stream, double* ws, size_t ws_doubles, int smax) {
   if (g_rec || nprob != 1 || ws == nullptr) return gemm_launch(probs, nprob, stream);
   const GProb& p = probs[0];
-  const int S = splitk_factor(p, ws_doubles);
+  const int S = splitk_factor(p, ws_doubles, smax);
   if (S < 2) return gemm_launch(probs, nprob, stream);
   const int K0 = p.seg[0].K;
   // split boundaries on multiples of 64 (16-byte aligned operand rows stay aligned)

@@ -168,6 +168,15 @@ SyncLease::~SyncLease() {
   g_sync_free[ctx_->dev].push_back(ctx_);
 }
 
+// Largest split count of a sweep product: BTA_SELINV_SPLIT (1..GEMM_MAX_PROBS),
+// else the tuning table's "split" entry for (b, a), else GEMM_MAX_PROBS.
+static int selinv_split_max(int64_t b, int64_t a) {
+  long long v = 0;
+  if (env_int("BTA_SELINV_SPLIT", 1, GEMM_MAX_PROBS, &v)) return (int)v;
+  if (tune_get(tune_key("selinv", b, a, "split"), &v) && v >= 1 && v <= GEMM_MAX_PROBS) return (int)v;
+  return GEMM_MAX_PROBS;
+}
+
 SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a, bool split) {
   SelinvPlan sp{};
   const int64_t T = (b + 63) / 64;
@@ -189,6 +198,7 @@ SelinvPlan selinv_plan(int64_t n, int64_t b, int64_t a, bool split) {
   sp.off_WT = take(8 * (size_t)std::max<int64_t>(1, 2 * a * a));
   // split-k partial products of the sweep at small b (few output tiles)
   sp.split_doubles = (split && b <= 1024) ? (size_t)GEMM_MAX_PROBS * bb : 0;
+  sp.split_max = selinv_split_max(b, a);
   sp.off_split = take(8 * std::max<size_t>(1, sp.split_doubles));
   sp.bytes = off;
   return sp;
@@ -346,7 +356,7 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       p.Cout = Xb; p.ldc = b;
       p.M = ib; p.N = ib;
       p.alpha = -1.0;
-      BTA_TRY(gemm_launch_split(&p, 1, s, SK, sp.split_doubles));
+      BTA_TRY(gemm_launch_split(&p, 1, s, SK, sp.split_doubles, sp.split_max));
     }
     set_stage(2, step, 1);
     {  // X_ii = V_i - X_{i+1,i}^T P_B - X_{n,i}^T P_R  (lower, mirrored; no
@@ -360,7 +370,7 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       p.alpha = -1.0; p.beta = 1.0;
       p.lower_tiles = 1;
       p.store = ST_LOWER_MIRROR;
-      BTA_TRY(gemm_launch_split(&p, 1, s, SK, sp.split_doubles));
+      BTA_TRY(gemm_launch_split(&p, 1, s, SK, sp.split_doubles, sp.split_max));
     }
     set_stage(2, step, 3);
     if (has_sub) {
