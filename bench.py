@@ -173,19 +173,20 @@ def kernel_line(L, steps):
 
 def mfma_probe(torch, L, dev):
     """Sustained FP64 MFMA rate of this device: a register-only MFMA loop
-    (bta_internal_mfma_probe) at 2, 4 and 8 workgroups per CU with 8 and 16
-    independent chains per wave, timed with events on the current stream; the
-    best configuration's rate."""
+    (bta_internal_mfma_probe) at 1, 2, 4 and 8 workgroups of 4 waves per CU
+    with 4, 8 and 16 independent chains per wave (the same number of MFMAs per
+    launch in every configuration), timed with events on the current stream;
+    the best configuration's rate."""
     L.bta_internal_mfma_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
     L.bta_internal_mfma_probe.restype = ctypes.c_int
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
-    iters = 4000
     out = torch.empty(8 * cus * 256, dtype=torch.float64, device=dev)
     s = torch.cuda.current_stream().cuda_stream
     best = 0.0
-    for per_cu in (2, 4, 8):
-        for chains in (8, 16):
+    for per_cu in (1, 2, 4, 8):
+        for chains in (4, 8, 16):
             grid = per_cu * cus
+            iters = 4000 * 128 // (per_cu * chains)
             for _ in range(2):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)

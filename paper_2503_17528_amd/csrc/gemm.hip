@@ -1297,11 +1297,13 @@ __global__ __launch_bounds__(256) void mfma_probe_kernel(double* out, int iters)
 }  // namespace bta
 
 // Internal: launch the MFMA rate probe with `grid` workgroups of 256 threads
-// on `s` (chains: 8 or 16 independent MFMA chains per wave); d_out holds
+// on `s` (chains: 4, 8 or 16 independent MFMA chains per wave); d_out holds
 // grid * 256 doubles.  Flops = grid * 4 * iters * chains * 2048.
 BTA_TESTING_API int bta_internal_mfma_probe(double* d_out, int grid, int iters, int chains, hipStream_t s) {
-  if (!d_out || grid < 1 || iters < 1 || (chains != 8 && chains != 16)) return (int)hipErrorInvalidValue;
-  if (chains == 8)
+  if (!d_out || grid < 1 || iters < 1 || (chains != 4 && chains != 8 && chains != 16)) return (int)hipErrorInvalidValue;
+  if (chains == 4)
+    hipLaunchKernelGGL(bta::mfma_probe_kernel<4>, dim3((unsigned)grid), dim3(256), 0, s, d_out, iters);
+  else if (chains == 8)
     hipLaunchKernelGGL(bta::mfma_probe_kernel<8>, dim3((unsigned)grid), dim3(256), 0, s, d_out, iters);
   else
     hipLaunchKernelGGL(bta::mfma_probe_kernel<16>, dim3((unsigned)grid), dim3(256), 0, s, d_out, iters);
