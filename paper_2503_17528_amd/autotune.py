@@ -6,6 +6,8 @@ The library keeps its tuned decisions in a table keyed by
 
 - the factorization's DIAG lookahead (``look``: how many band columns ahead of
   the diagonal-tile chain a diagonal task starts its accumulation);
+- its SUB dispatch delay (``sub_delay``: how many band columns after their own
+  the tasks of the coupling block's tiles are dispatched);
 - its k-loop load path (``cached``: 1 reads published operand tiles through
   the L2);
 - the largest split count of the selected inversion's sweep products at
@@ -15,8 +17,8 @@ The library keeps its tuned decisions in a table keyed by
 
 ``BTA_TUNE_CACHE=<file.json>`` makes the library load the table from that file
 on first use and write measured entries back; ``BTA_FACTOR_LOOKAHEAD``,
-``BTA_FACTOR_CACHED`` and ``BTA_SELINV_SPLIT`` override the table for every
-shape.
+``BTA_FACTOR_CACHED``, ``BTA_FACTOR_SUB_DELAY`` and ``BTA_SELINV_SPLIT``
+override the table for every shape.
 
 ``tune_factor`` and ``tune_selinv_split`` time candidate settings on a seeded
 synthetic matrix of the given block shape (the median of ``reps`` runs each,
@@ -103,11 +105,14 @@ def clear() -> None:
 
 
 def tune_factor(n: int, b: int, a: int, looks: Iterable[int] = (2, 4, 6, 8, 12, 16), cached: Iterable[int] = (0, 1),
-                reps: int = 3, seed: int = 0, log=None) -> Dict[str, float]:
+                reps: int = 3, seed: int = 0, log=None, sub_delays: Iterable[int] = (0, 2, 4, 8, 16)) -> Dict[str, float]:
     """Time bta_factor on a seeded n x (b, a) matrix for every (lookahead,
     load path) candidate, the median of ``reps`` runs each, and record the
-    fastest as the table's ``look`` and ``cached`` entries for (b, a).
-    Returns {"look=<L>,cached=<c>": median ms}."""
+    fastest as the table's ``look`` and ``cached`` entries for (b, a); then,
+    with those, every SUB dispatch delay (``sub_delay``: columns by which the
+    tasks of the coupling block's tiles follow their own column), recording
+    the fastest.  ``BTA_FACTOR_SUB_DELAY``, when set, overrides the table.
+    Returns {"look=<L>,cached=<c>": median ms, "sub_delay=<d>": median ms}."""
     import torch
 
     if reps < 3:
@@ -120,6 +125,21 @@ def tune_factor(n: int, b: int, a: int, looks: Iterable[int] = (2, 4, 6, 8, 12, 
     out = tuple(torch.empty_like(Q[k]) for k in "DBRT")
     work, _ = bta.workspace(bta.BTA_OP_FACTOR, n, b, a, dev)
     T = (b + 63) // 64
+
+    def median_ms() -> float:
+        ms = []
+        for _ in range(reps + 1):  # the first run warms up
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            info = bta.factor(Q["D"], Q["B"], Q["R"], Q["T"], out=out, work=work, check=False)[4]
+            e1.record()
+            torch.cuda.synchronize()
+            if int(info.item()) != 0:
+                raise bta.BTAError(bta.BTA_EHIP, f"factorization failed during tuning (info {int(info.item())})")
+            ms.append(e0.elapsed_time(e1))
+        return statistics.median(ms[1:])
+
     times: Dict[str, float] = {}
     prev_look = L.bta_internal_factor_lookahead(-1)
     prev_cached = L.bta_internal_factor_cached_loads(-2)
@@ -128,18 +148,7 @@ def tune_factor(n: int, b: int, a: int, looks: Iterable[int] = (2, 4, 6, 8, 12, 
             for c in cached:
                 L.bta_internal_factor_lookahead(look)
                 L.bta_internal_factor_cached_loads(int(c))
-                ms = []
-                for _ in range(reps + 1):  # the first run warms up
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    e0.record()
-                    info = bta.factor(Q["D"], Q["B"], Q["R"], Q["T"], out=out, work=work, check=False)[4]
-                    e1.record()
-                    torch.cuda.synchronize()
-                    if int(info.item()) != 0:
-                        raise bta.BTAError(bta.BTA_EHIP, f"factorization failed during tuning (info {int(info.item())})")
-                    ms.append(e0.elapsed_time(e1))
-                med = statistics.median(ms[1:])
+                med = median_ms()
                 times[f"look={look},cached={int(c)}"] = med
                 if log:
                     log(f"factor n={n} b={b} a={a} look={look} cached={int(c)}: {med:.3f} ms")
@@ -150,6 +159,16 @@ def tune_factor(n: int, b: int, a: int, looks: Iterable[int] = (2, 4, 6, 8, 12, 
     look_s, cached_s = best.split(",")
     set_entry(key("factor", b, a, "look"), int(look_s.split("=")[1]))
     set_entry(key("factor", b, a, "cached"), int(cached_s.split("=")[1]))
+    # the SUB dispatch delay, with the lookahead and load path just recorded
+    kd = key("factor", b, a, "sub_delay")
+    delays: Dict[str, float] = {}
+    for d in sorted(set(min(max(0, int(x)), T) for x in sub_delays)):
+        set_entry(kd, d)
+        delays[f"sub_delay={d}"] = median_ms()
+        if log:
+            log(f"factor n={n} b={b} a={a} sub_delay={d}: {delays[f'sub_delay={d}']:.3f} ms")
+    set_entry(kd, int(min(delays, key=delays.get).split("=")[1]))
+    times.update(delays)
     return times
 
 

@@ -19,6 +19,7 @@ constexpr int FACTOR_LOOKAHEAD = 8;
 
 struct FactorPlan {
   int T, TA, look;
+  int sub_delay;  // SUB tasks of column c are dispatched with column c + sub_delay of their step
   long long nflags, step_full, step_last, ntasks;
   size_t off_ctl, off_flags, off_Wd, off_Wt, off_P, bytes;
 };

@@ -59,6 +59,8 @@ struct FactorParams {
   long long ntasks;
   long long step_full, step_last;  // tasks per step (with / without SUB)
   int look;                        // DIAG lookahead: DIAG(i,c) is dispatched with column c - look of its step
+  int sub_delay;                   // SUB(i,r,c) is dispatched with column c + sub_delay of its step (after
+                                   // the last column for c + sub_delay >= T)
   int cached;                      // 1: k-loop operand tiles are read through the L2 (line-aligned tiles only)
   int fast;                        // 1: every k-loop operand tile takes the direct 16-byte path, device
                                    // coherent (b and a even, L arrays 16-byte aligned, cached == 0)
@@ -118,15 +120,21 @@ __host__ __device__ __forceinline__ Task decode(const FactorParams& p, long long
   }
   // column c: DIAG tasks (DIAG(0 .. L) at c = 0, DIAG(c + L) after, L = look:
   // a diagonal task starts its long k loop L columns ahead of the chain), OFFD
-  // rows c+2 .. T-1 (row c+1 is fused into the next DIAG), SUB rows 0 .. T-1
-  // (not row 0 of the last column: fused into the next step's first DIAG),
-  // ARW rows 0 .. TA-1
-  const int L = p.look;
-  for (int c = 0; c < T; ++c) {
-    const int ndg = (c == 0) ? L + 1 : ((c + L <= T - 1) ? 1 : 0);
-    const int no = (c <= T - 2) ? T - c - 2 : 0;
-    const int ns = has_sub ? (c == T - 1 ? T - 1 : T) : 0;
-    const int g = ndg + no + ns + TA;
+  // rows c+2 .. T-1 (row c+1 is fused into the next DIAG), the SUB tasks of
+  // column c - S (S = sub_delay; rows 0 .. T-1, not row 0 of the last column:
+  // fused into the next step's first DIAG), ARW rows 0 .. TA-1; then the SUB
+  // tasks of the last S columns.  Every task still waits only on smaller
+  // tickets (a SUB tile's sources are SUB tiles of earlier columns and D-block
+  // tiles), apart from the DIAG lookahead.
+  const int L = p.look, S = has_sub ? p.sub_delay : 0;
+  for (int c = 0; c < T + S; ++c) {
+    const bool col = c < T;
+    const int cs = c - S;
+    const int ndg = !col ? 0 : (c == 0) ? L + 1 : ((c + L <= T - 1) ? 1 : 0);
+    const int no = (col && c <= T - 2) ? T - c - 2 : 0;
+    const int ns = (has_sub && cs >= 0) ? (cs == T - 1 ? T - 1 : T) : 0;
+    const int na = col ? TA : 0;
+    const int g = ndg + no + ns + na;
     if (rem < g) {
       if (rem < ndg) {
         k.type = T_DIAG;
@@ -138,8 +146,8 @@ __host__ __device__ __forceinline__ Task decode(const FactorParams& p, long long
         k.r = c + 2 + (int)(rem - ndg);
       } else if (rem - ndg - no < ns) {
         k.type = T_SUB;
-        k.c = c;
-        k.r = (int)(rem - ndg - no) + (c == T - 1 ? 1 : 0);
+        k.c = cs;
+        k.r = (int)(rem - ndg - no) + (cs == T - 1 ? 1 : 0);
       } else {
         k.type = T_ARW;
         k.c = c;
@@ -913,6 +921,22 @@ static int factor_lookahead(int64_t b, int64_t a) {
   return FACTOR_LOOKAHEAD;
 }
 
+// SUB dispatch delay in columns for blocks of b with an arrow of a:
+// BTA_FACTOR_SUB_DELAY, else the tuning table ("factor", "sub_delay"), else
+// min(8, T/4).  A SUB tile's last source is the SUB tile to its left, which
+// is final only once the diagonal chain has passed its column; dispatched with
+// its own column, a SUB task holds its workgroup waiting for it.  Measured
+// (factor ms for delays 0, 1, 2, 4, 8, 16): n=128, b=2048, a=8: 105.6, 98.6,
+// 95.0, 86.6, 84.3, 87.9; n=48, b=4096, a=16: 218.4, 194.9, 189.1, 187.4,
+// 187.5, 188.2; no change at b=512 (n=256) and b=1024 (n=512, a=256).
+static int factor_sub_delay(int64_t b, int64_t a) {
+  long long v = 0;
+  if (env_int("BTA_FACTOR_SUB_DELAY", 0, 64, &v)) return (int)v;
+  if (tune_get(tune_key("factor", b, a, "sub_delay"), &v) && v >= 0 && v <= 64) return (int)v;
+  const int64_t T = (b + 63) / 64;
+  return (int)std::min<int64_t>(8, T / 4);
+}
+
 // Whether the k loops read through the L2 (same order of sources; default off).
 static bool factor_cached_loads(int64_t b, int64_t a) {
   if (g_factor_cached >= 0) return g_factor_cached != 0;
@@ -952,6 +976,7 @@ FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   fp.step_last = T * (T - 1) / 2 + 1 + T * TA + TA * (TA + 1) / 2;
   fp.ntasks = (n - 1) * fp.step_full + fp.step_last + TA * (TA + 1) / 2;
   fp.look = (int)std::min<int64_t>(factor_lookahead(b, a), T - 1);
+  fp.sub_delay = (int)std::min<int64_t>(factor_sub_delay(b, a), T);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
   fp.off_ctl = take(64);
@@ -982,6 +1007,7 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
   p.step_full = fp.step_full;
   p.step_last = fp.step_last;
   p.look = fp.look;
+  p.sub_delay = fp.sub_delay;
   p.cached = (factor_cached_loads(b, a) && factor_lines_aligned(b, a, LD, LB, LR, LT)) ? 1 : 0;
   p.fast = (!p.cached && factor_ops_direct(b, a, LD, LB, LR, LT)) ? 1 : 0;
   p.trace = trace;
@@ -1097,6 +1123,7 @@ FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b,
   for (int m = 0; m < count; ++m) {
     bp.plans[m] = factor_plan(n[m], b[m], a[m]);
     bp.plans[m].look = std::min(bp.plans[m].look, BATCH_LOOKAHEAD);
+    bp.plans[m].sub_delay = 0;  // the batch segments follow decode()'s undelayed column groups
     bp.flag_off[m] = nflags;
     nflags += bp.plans[m].nflags;
   }
@@ -1191,12 +1218,14 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
 // inside its array.  counts[] receives the number of tiles of each kind (a
 // DIAG task also produces the tile left of its diagonal tile, counted under
 // OFFD or SUB).  Returns 0 when the schedule is valid, else an error code.
-// `look` is the DIAG lookahead to replay (the plan's own when negative);
-// maxdep_out (optional) receives, per ticket, the largest ticket it waits on.
+// `look` and `sub_delay` are the DIAG lookahead and SUB delay to replay (the
+// plan's own when negative); maxdep_out (optional) receives, per ticket, the
+// largest ticket it waits on.
 int factor_schedule_replay(int64_t n, int64_t b, int64_t a, int look, long long* counts /* [7] or null */,
-                           std::vector<long long>* maxdep_out) {
+                           std::vector<long long>* maxdep_out, int sub_delay = -1) {
   FactorPlan fp = factor_plan(n, b, a);
   if (look >= 0) fp.look = std::min<int>(look, fp.T - 1);
+  if (sub_delay >= 0) fp.sub_delay = std::min<int>(sub_delay, fp.T);
   FactorParams p{};
   p.n = (int)n; p.b = (int)b; p.a = (int)a; p.T = fp.T; p.TA = fp.TA;
   const uintptr_t G = uintptr_t(1) << 40;
@@ -1206,6 +1235,7 @@ int factor_schedule_replay(int64_t n, int64_t b, int64_t a, int look, long long*
   p.LT = reinterpret_cast<double*>(4 * G);
   p.flags = reinterpret_cast<int*>(5 * G);
   p.ntasks = fp.ntasks; p.step_full = fp.step_full; p.step_last = fp.step_last; p.look = fp.look;
+  p.sub_delay = fp.sub_delay;
   const size_t lim[4] = {(size_t)(n * b * b), (size_t)((n - 1) * b * b), (size_t)(n * a * b), (size_t)(a * a)};
   auto inside = [&](const OpTile& o) -> bool {
     if (o.rows <= 0 || o.cols <= 0) return false;
@@ -1400,7 +1430,7 @@ BTA_TESTING_API int bta_internal_factor_batch_check(int count, const int64_t* n,
   std::vector<std::vector<long long>> maxdep(count), global(count);
   std::vector<bta::FactorParams> ps(count);
   for (int m = 0; m < count; ++m) {
-    if (bta::factor_schedule_replay(n[m], b[m], a[m], bp.plans[m].look, nullptr, &maxdep[m]) != 0) return 5;
+    if (bta::factor_schedule_replay(n[m], b[m], a[m], bp.plans[m].look, nullptr, &maxdep[m], 0) != 0) return 5;
     global[m].assign((size_t)bp.plans[m].ntasks, -1);
     bta::FactorParams& p = ps[m];
     p.n = (int)n[m]; p.b = (int)b[m]; p.a = (int)a[m]; p.T = bp.plans[m].T; p.TA = bp.plans[m].TA;

@@ -1,5 +1,5 @@
 """The autotuners on the GPU: the factor tuner times every candidate (median
-of three runs) and records the fastest lookahead and load path, which the
+of three runs) and records the fastest lookahead, load path and SUB delay, which the
 next factorization then uses (checked against the oracle); the selected
 inversion's split tuner likewise (the next selected inversion checked against
 the oracle); the batched
@@ -31,12 +31,17 @@ def test_factor_tuner_and_batched_tuner(tmp_path):
 def _run(torch, autotune, bta, tmp_path):
     n, b, a = 6, 256, 4
     say(f"case autotune factor n={n} b={b} a={a}")
-    times = autotune.tune_factor(n, b, a, looks=(1, 2, 3), cached=(0, 1), reps=3, log=say)
-    assert len(times) == 6 and all(t > 0 for t in times.values())
+    times = autotune.tune_factor(n, b, a, looks=(1, 2, 3), cached=(0, 1), reps=3, log=say, sub_delays=(0, 1, 4))
+    lc = {k: v for k, v in times.items() if k.startswith("look=")}
+    sd = {k: v for k, v in times.items() if k.startswith("sub_delay=")}
+    assert len(lc) == 6 and all(t > 0 for t in times.values())
+    assert set(sd) == {"sub_delay=0", "sub_delay=1", "sub_delay=4"}
     look = autotune.get_entry(autotune.key("factor", b, a, "look"))
     cached = autotune.get_entry(autotune.key("factor", b, a, "cached"))
-    best = min(times, key=times.get)
+    delay = autotune.get_entry(autotune.key("factor", b, a, "sub_delay"))
+    best = min(lc, key=lc.get)
     assert best == f"look={look},cached={cached}", (best, look, cached)
+    assert min(sd, key=sd.get) == f"sub_delay={delay}", (sd, delay)
 
     # the tuned settings are the ones the next factorization runs with
     Q = synth.make_np(synth.workload(n, b, a), 3)

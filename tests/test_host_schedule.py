@@ -117,3 +117,16 @@ def test_batched_factor_interleaving_random_batches(L):
         rc = L.bta_internal_factor_batch_check(cnt, arr([m[0] for m in ms]), arr([m[1] for m in ms]),
                                                arr([m[2] for m in ms]), cus, ctypes.byref(ahead))
         assert rc == 0, (rc, cus, ms)
+
+
+@pytest.mark.parametrize("delay", [1, 2, 5, 64])
+def test_factor_schedule_sub_delays(L, delay, monkeypatch):
+    """The schedule invariants hold when the SUB tasks are dispatched `delay`
+    columns after their own (BTA_FACTOR_SUB_DELAY; capped at the column count,
+    the tail of a step then holds the SUB tasks of its last columns)."""
+    monkeypatch.setenv("BTA_FACTOR_SUB_DELAY", str(delay))
+    for n, b, a in [(3, 64 * 20 + 5, 3), (2, 64 * 40, 70), (4, 200, 0), (1, 64 * 33, 8), (5, 130, 65), (3, 64, 4)]:
+        counts = (ctypes.c_longlong * 7)()
+        assert L.bta_internal_factor_schedule_check(n, b, a, counts) == 0, (delay, n, b, a)
+        T, TA = (b + 63) // 64, (a + 63) // 64
+        assert sum(counts) == n * T * (T + 1) // 2 + (n - 1) * T * T + n * T * TA + n * TA * (TA + 1) // 2 + TA * (TA + 1) // 2
