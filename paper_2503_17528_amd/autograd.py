@@ -1,7 +1,9 @@
 """Differentiable f(Q) = log det Q + y^T Q^{-1} y for a BTA matrix Q given by its
 block arrays (D, B, R, T), the objective of Gaussian (INLA-type) models.
 
-Forward: bta_factor, then bta_solve (x = Q^{-1} y) and bta_logdet_quad.
+Forward: bta_factor, then bta_solve (x = Q^{-1} y) and bta_logdet_quad, all
+enqueued before the factorization's info is read (which raises
+NotPositiveDefinite on a failed pivot).
 Backward: bta_selinv on the saved factor gives Sigma on the BTA pattern, and
 bta_grad_logdet_quad assembles G = Sigma - x x^T on the pattern directly,
 scaled by the incoming gradient, with grad_y = 2x.  No dense matrix is formed
@@ -23,9 +25,12 @@ from . import bta
 class LogdetQuad(torch.autograd.Function):
     @staticmethod
     def forward(ctx, D, B, R, T, y):
-        LD, LB, LR, LT, _ = bta.factor(D.contiguous(), B.contiguous(), R.contiguous(), T.contiguous())
+        LD, LB, LR, LT, info = bta.factor(D.contiguous(), B.contiguous(), R.contiguous(), T.contiguous(), check=False)
         x = bta.solve(LD, LB, LR, LT, y.contiguous())
         f = bta.logdet_quad(LD, LT, y.contiguous(), x)
+        # the solve's launches are enqueued while the factorization runs; its
+        # outcome is checked once everything is queued (raises on a failed pivot)
+        bta.check_info(info)
         ctx.save_for_backward(LD, LB, LR, LT, x)
         return f
 

@@ -221,12 +221,19 @@ def factor(D, B, R, T, out=None, work=None, stream=None, check: bool = True):
                     work.data_ptr(), nbytes, info.data_ptr(), _stream(stream))
     _check(st, "bta_factor")
     if check:
-        v = int(info.item())
-        if v > 0:
-            raise NotPositiveDefinite(v)
-        if v < 0:
-            raise BTAError(BTA_EHIP, "bta_factor: progress watchdog fired")
+        check_info(info)
     return LD, LB, LR, LT, info
+
+
+def check_info(info) -> None:
+    """Raise for a failed factorization: NotPositiveDefinite for a positive
+    info (the 1-based row of the first bad pivot), BTAError for the watchdog's
+    -1.  Synchronizes with the device (reads the 0-dim info tensor)."""
+    v = int(info.item())
+    if v > 0:
+        raise NotPositiveDefinite(v)
+    if v < 0:
+        raise BTAError(BTA_EHIP, "bta_factor: progress watchdog fired")
 
 
 def factor_noalloc(D, B, R, T, out=None, stream=None):

@@ -153,3 +153,31 @@ def test_gradient_at_zero_rhs_is_selected_inverse(torch_cuda):
     e = errs(got, ref, lower=())
     say(f"   G vs Sigma: {e}")
     assert max(e.values()) < TOL
+
+
+def test_forward_raises_on_failed_pivot(torch_cuda):
+    """The forward enqueues the solve before it reads the factorization's
+    info, and still raises NotPositiveDefinite with the oracle's row (a
+    negative pivot in a middle block); a valid matrix afterwards works."""
+    torch = torch_cuda
+    from paper_2503_17528_amd import bta
+    from paper_2503_17528_amd.autograd import logdet_quad
+
+    n, b, a = 4, 64, 3
+    say(f"case autograd failed pivot n={n} b={b} a={a}")
+    wl = synth.workload(n, b, a)
+    Q = synth.make_np(wl, 8)
+    Qbad = {k: v.copy() for k, v in Q.items()}
+    Qbad["D"][2][5, 5] = -1.0
+    F = oracle.pobtaf(Qbad["D"], Qbad["B"], Qbad["R"], Qbad["T"])
+    assert F["info"] > 0
+    y = torch.from_numpy(synth.rhs_np(wl, 8, 1)[:, 0]).to("cuda")
+    dev = [torch.tensor(Qbad[k], device="cuda", requires_grad=True) for k in "DBRT"]
+    with pytest.raises(bta.NotPositiveDefinite) as ei:
+        logdet_quad(*dev, y)
+    assert ei.value.row == F["info"]
+    good = [torch.tensor(Q[k], device="cuda", requires_grad=True) for k in "DBRT"]
+    f = logdet_quad(*good, y)
+    Fg = oracle.pobtaf(Q["D"], Q["B"], Q["R"], Q["T"])
+    ref = oracle.logdet(Fg["LD"], Fg["LT"]) + float(y.cpu().numpy() @ oracle.pobtas(Fg["LD"], Fg["LB"], Fg["LR"], Fg["LT"], y.cpu().numpy()))
+    assert abs(float(f.item()) - ref) <= 1e-10 * abs(ref)
