@@ -105,9 +105,10 @@ BTA_TESTING_API int bta_internal_gemm_split(int M, int N, int K, const double* A
                                             int64_t ldb, int bt, const double* Cin, double* C, int64_t ldc,
                                             double alpha, double beta, int store, int lower_tiles, double* ws,
                                             size_t ws_doubles, int* splits, hipStream_t s);
-/* Per-kernel HIP-event timing of the main kernels (on with a pool of
- * 2*max_launches events, off with on = 0); not thread safe. */
-BTA_TESTING_API int bta_internal_timing(int on, int max_launches);
+/* Per-kernel HIP-event timing of the main kernels: `kinds` is a bit mask of
+ * the kinds recorded (bit 0 factor, 1 GEMM, 2 TRTRI leaves, 3 other; 0 turns
+ * timing off) with a pool of 2*max_launches events; not thread safe. */
+BTA_TESTING_API int bta_internal_timing(int kinds, int max_launches);
 /* Per-kind milliseconds and launch counts of the timed spans (0 = complete). */
 BTA_TESTING_API int bta_internal_timing_read(double* ms, long long* launches);
 /* Register-only FP64 MFMA rate probe: grid workgroups of 256 threads, each

@@ -821,7 +821,7 @@ thread_local StageRecorder* g_rec = nullptr;
 // ---------------------------------------------------------------- kernel timer
 namespace {
 struct KernelTimer {
-  bool on = false;
+  unsigned mask = 0;  // kinds recorded: bit k for kind k (KT_FACTOR, KT_GEMM, ...)
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<std::pair<int, std::pair<size_t, size_t>>> spans;  // (kind, (start event, stop event))
@@ -830,10 +830,10 @@ struct KernelTimer {
 KernelTimer g_timer;
 }  // namespace
 
-bool timing_on() { return g_timer.on; }
+bool timing_on() { return g_timer.mask != 0; }
 
 void timing_mark(int kind, bool start, hipStream_t stream) {
-  if (!g_timer.on || g_timer.used >= g_timer.pool.size()) return;
+  if (!((g_timer.mask >> kind) & 1u) || g_timer.used >= g_timer.pool.size()) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
   const size_t e = g_timer.used++;
@@ -1215,20 +1215,23 @@ int device_cu_count() {
 
 }  // namespace bta
 
-// Internal timing controls (not part of the public header): enable with a
-// pool of event pairs, read back per-kind total milliseconds and launch counts.
-BTA_TESTING_API int bta_internal_timing(int on, int max_launches) {
+// Internal timing controls (not part of the public header): enable the kinds
+// in `kinds` (bit k for kind k; 0 turns timing off) with a pool of event
+// pairs, read back per-kind total milliseconds and launch counts.  Every
+// recorded launch adds two event records to its stream, so a measurement of a
+// launch-heavy sequence enables only the kinds it reads.
+BTA_TESTING_API int bta_internal_timing(int kinds, int max_launches) {
   using namespace bta;
   for (hipEvent_t e : g_timer.pool) (void)hipEventDestroy(e);
   g_timer.pool.clear();
   g_timer.spans.clear();
   g_timer.used = 0;
-  g_timer.on = false;
-  if (!on) return 0;
+  g_timer.mask = 0;
+  if (!kinds) return 0;
   g_timer.pool.resize((size_t)2 * max_launches);
   for (auto& e : g_timer.pool)
     if (hipEventCreate(&e) != hipSuccess) return 1;
-  g_timer.on = true;
+  g_timer.mask = (unsigned)kinds & ((1u << KT_COUNT) - 1u);
   return 0;
 }
 
