@@ -184,3 +184,29 @@ def test_abi_rejects_bad_workspace_on_device(torch_cuda):
     with pytest.raises(bta.BTAError) as ei:
         bta.factor(D, B, R, T, work=work)
     assert ei.value.status == bta.BTA_EINVAL
+
+
+@pytest.mark.parametrize("delay", [0, 1, 3, 10])
+def test_factor_sub_delays(torch_cuda, delay):
+    """Every SUB dispatch delay gives the oracle's factor (the delay only
+    reorders the tickets of the coupling block's tiles): a 10 x 10 tile band
+    with ragged tiles and a two-tile tip, the delay set through the tuning
+    table (10 = every SUB task after its step's last column)."""
+    from paper_2503_17528_amd import autotune, bta
+
+    n, b, a = 4, 610, 70
+    say(f"case sub_delay={delay} n={n} b={b} a={a}")
+    k = autotune.key("factor", b, a, "sub_delay")
+    autotune.set_entry(k, delay)
+    try:
+        wl = synth.workload(n, b, a)
+        Q = synth.make_np(wl, 12)
+        F = oracle.pobtaf(Q["D"], Q["B"], Q["R"], Q["T"])
+        D, B, R, T = to_dev(Q)
+        L = bta.factor(D, B, R, T)
+        torch_cuda.cuda.synchronize()
+        e = errs(dict(zip("DBRT", to_np(L[:4]))), {"D": F["LD"], "B": F["LB"], "R": F["LR"], "T": F["LT"]})
+        say(f"   L err {e}")
+        assert max(e.values()) < TOL, e
+    finally:
+        autotune.clear()
