@@ -22,7 +22,8 @@
  *    frees memory.  Scratch memory is the caller's `work` buffer of at least
  *    bta_workspace_bytes(op, ...) bytes, 256-byte aligned.
  *  - Every call only validates its arguments and enqueues work on `stream`
- *    (0 = the null stream); it returns before the work runs.  The return
+ *    (0 = the null stream); it returns before the work runs (one exception:
+ *    the first bta_selinv_batched call with a descriptor set).  The return
  *    value reports argument errors (BTA_EINVAL) and launch errors (BTA_EHIP)
  *    only; numerical outcomes are reported on the device (d_info).
  *  - Outputs may alias the corresponding inputs exactly (in place: LD == D,
@@ -197,7 +198,13 @@ BTA_API bta_status bta_factor_batched(int count, const bta_desc* descs, void* wo
  * merged stage by stage (one grouped launch per stage across the batch), the
  * tile shape of every merged GEMM launch is chosen by the autotuner (measured
  * on first use of a shape class), and the whole launch sequence is captured
- * once in a HIP graph per descriptor set and replayed. */
+ * once in a HIP graph per descriptor set and replayed (the graphs of the eight
+ * most recently used descriptor sets are kept).
+ * Exception to the enqueue-only convention: the first call with a descriptor
+ * set runs the stages eagerly and, for shape classes not yet in the tuning
+ * table, times both tilings on `stream` and waits for those timings on the
+ * host; it must not be made while `stream` is being captured.  Later calls
+ * with the same descriptor set, workspace and device only enqueue the graph. */
 BTA_API bta_status bta_selinv_batched(int count, const bta_desc* descs, void* work, size_t work_bytes,
                                bta_stream_t stream);
 
