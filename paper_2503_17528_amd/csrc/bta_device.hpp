@@ -429,7 +429,8 @@ __device__ __forceinline__ void blk_store(const d4& c, double* X, int ld, int la
 // VAR 0: the pivot of column k+1 is broadcast from its updated column entry;
 // VAR 1: lane k+1 forms the next pivot from its own L(k+1,k) (one FMA), so
 // the cross-lane read of L(k+1,k) leaves the pivot chain.  TIMED: thread 0
-// writes s_memrealtime stamps of the phase ends into ts[0..10].
+// writes s_memrealtime stamps of the phase ends into ts[0..10], and of wave 0's
+// steps inside the diagonal-block inverses into ts[11..13].
 // early_flag (optional): a flag published (agent-scope release, value 1) once
 // panel 0 is done and every wave's earlier global stores are complete, so that
 // stores issued before the call are published off the critical path.
@@ -443,6 +444,12 @@ __device__ __forceinline__ int chol_inv_tile_mfma_t(double* S, double* Wl, doubl
   if (TIMED && tid == 0) ts[0] = __builtin_amdgcn_s_memrealtime();
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
+    if (p == 0 && q != 0) {
+      // waves 1..3 are idle during panel 0: clear W here (its blocks above the
+      // diagonal stay zero; the diagonal and lower blocks are written below)
+      for (int e = 2 * (tid - 64); e < 64 * 64; e += 2 * (NT - 64))
+        *reinterpret_cast<d2v*>(Wl + (e >> 6) * LDS_LD + (e & 63)) = d2v{0.0, 0.0};
+    }
     if (q == p) {
       double s[16];
 #pragma unroll
@@ -499,17 +506,9 @@ __device__ __forceinline__ int chol_inv_tile_mfma_t(double* S, double* Wl, doubl
       if (TIMED && tid == 0) ts[2 + 2 * p] = __builtin_amdgcn_s_memrealtime();
     }
   }
-  // first pivot that is not a positive finite number: its reciprocal square
-  // root is then NaN (d <= 0, NaN or +inf; zero gives 0 * inf) instead of a
-  // positive finite number
-  if (q == 0) {
-    const double ri = rinv[r];
-    const unsigned long long bad = __builtin_amdgcn_ballot_w64(!(ri > 0.0 && ri < 1.7976931348623157e308));
-    if (r == 0) *fail_sh = bad ? __builtin_ctzll(bad) + 1 : 0x7fffffff;
-  }
-
   // ---- W: diagonal 16 x 16 blocks, wave q inverts block q, lane j < 16 computes column j
   {
+    if (TIMED && tid == 0) ts[11] = __builtin_amdgcn_s_memrealtime();
     const int Q = q, j = r;
     double w[16], acc[16];
 #pragma unroll
@@ -520,19 +519,23 @@ __device__ __forceinline__ int chol_inv_tile_mfma_t(double* S, double* Wl, doubl
 #pragma unroll
       for (int i2 = i + 1; i2 < 16; ++i2) acc[i2] += S[(16 * Q + i2) * LDS_LD + 16 * Q + i] * w[i];
     }
+    if (TIMED && tid == 0) ts[12] = __builtin_amdgcn_s_memrealtime();
     if (j < 16) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) Wl[(16 * Q + i) * LDS_LD + 16 * Q + j] = (i >= j) ? w[i] : 0.0;
     }
-    // the other blocks of block row Q: zero (the lower ones are overwritten below)
-    for (int e = r; e < 16 * 48; e += 64) {
-      const int rr = e / 48, cc = e - rr * 48;
-      const int col = cc < 16 * Q ? cc : cc + 16;
-      Wl[(16 * Q + rr) * LDS_LD + col] = 0.0;
-    }
+    if (TIMED && tid == 0) ts[13] = __builtin_amdgcn_s_memrealtime();
   }
   __syncthreads();
   if (TIMED && tid == 0) ts[8] = __builtin_amdgcn_s_memrealtime();
+  // first pivot that is not a positive finite number (checked by wave 2, idle
+  // at level 16): its reciprocal square root is then NaN (d <= 0, NaN or +inf;
+  // zero gives 0 * inf) instead of a positive finite number
+  if (q == 2) {
+    const double ri = rinv[r];
+    const unsigned long long bad = __builtin_amdgcn_ballot_w64(!(ri > 0.0 && ri < 1.7976931348623157e308));
+    if (r == 0) *fail_sh = bad ? __builtin_ctzll(bad) + 1 : 0x7fffffff;
+  }
   // ---- level 16: W(1,0) = -W(1,1) L(1,0) W(0,0) (wave 0), W(3,2) = -W(3,3) L(3,2) W(2,2) (wave 1)
   if (q < 2) {
     const int I = 2 * q + 1, J = 2 * q;

@@ -43,8 +43,9 @@ BTA_TESTING_API int bta_internal_rsqrt(const double* d_in, double* d_out, int64_
 /* Latency probe of the diagonal-tile Cholesky + inverse: one workgroup
  * factors the 64 x 64 SPD tile d_A (row-major) `iters` times with panel
  * variant `var`; d_ticks[0] gets the summed 100 MHz ticks, d_ticks[1] the
- * failure column (0 = none), d_ticks[2..11] the summed phase ticks, d_L and
- * d_W (64 x 64 each) the factor and its inverse. */
+ * failure column (0 = none), d_ticks[2..11] the summed phase ticks,
+ * d_ticks[12..15] those of the steps inside the diagonal-block inverses (16
+ * entries in all), d_L and d_W (64 x 64 each) the factor and its inverse. */
 BTA_TESTING_API int bta_internal_diag_link_probe(const double* d_A, double* d_L, double* d_W, long long* d_ticks,
                                                  int iters, int var, hipStream_t s);
 /* Round-trip latency of the cross-workgroup flag hand-off between the first

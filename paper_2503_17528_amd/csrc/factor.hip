@@ -1528,7 +1528,7 @@ namespace bta {
 template <int VAR>
 __device__ void diag_link_probe_body(const double* A, double* Lout, double* Wout, long long* ticks, int iters) {
   __shared__ Shared sh;
-  __shared__ long long ts[12];
+  __shared__ long long ts[16];
   const int tid = threadIdx.x;
   double v[16];
 #pragma unroll
@@ -1536,7 +1536,7 @@ __device__ void diag_link_probe_body(const double* A, double* Lout, double* Wout
     const int idx = tid + 256 * e;
     v[e] = A[idx];
   }
-  long long total = 0, ph[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  long long total = 0, ph[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   int f = 0;
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
@@ -1550,8 +1550,13 @@ __device__ void diag_link_probe_body(const double* A, double* Lout, double* Wout
     __syncthreads();
     const long long t1 = __builtin_amdgcn_s_memrealtime();
     total += t1 - t0;
-    if (tid == 0)
+    if (tid == 0) {
       for (int k = 0; k < 10; ++k) ph[k] += ts[k + 1] - ts[k];
+      ph[10] += ts[11] - ts[7];  // inside the diagonal-block inverses (wave 0): the pivot check,
+      ph[11] += ts[12] - ts[11];  // the substitution,
+      ph[12] += ts[13] - ts[12];  // the stores of the block row,
+      ph[13] += ts[8] - ts[13];   // and the wait at the barrier
+    }
   }
   for (int e = tid; e < 4096; e += NT) {
     const int rr = e >> 6, cc = e & 63;
@@ -1561,7 +1566,7 @@ __device__ void diag_link_probe_body(const double* A, double* Lout, double* Wout
   if (tid == 0) {
     ticks[0] = total;
     ticks[1] = f;
-    for (int k = 0; k < 10; ++k) ticks[2 + k] = ph[k];
+    for (int k = 0; k < 14; ++k) ticks[2 + k] = ph[k];
   }
 }
 __global__ __launch_bounds__(NT, 1) void diag_link_probe_kernel0(const double* A, double* L, double* W, long long* t, int it) {
