@@ -87,6 +87,7 @@ __global__ __launch_bounds__(NT) void trinv_list_kernel(const TrinvOp* ops, cons
 namespace {
 
 struct StageExec {
+  StageKey key;       // (phase, major, minor) of the merged stage
   int kind;           // 0 gemm, 1 fill, 2 copy, 3 trinv
   size_t off;         // op array offset in the table region (gemm: problems with 64-tile metadata)
   size_t off_pre;     // prefix array offset (gemm: 64-tile prefix; trinv: workgroup prefix)
@@ -161,6 +162,7 @@ MergedPlan build_plan(const StageRecorder& rec) {
   for (const auto& kv : rec.stages) {
     const StageRecorder::Stage& st = kv.second;
     StageExec ex{};
+    ex.key = kv.first;
     ex.kind = st.kind;
     if (st.kind == 0) {
       std::vector<GProb> p64 = st.gemms, p128 = st.gemms;
@@ -272,11 +274,41 @@ static hipError_t record_batch(int count, const BatchMatrix* mats, char* work, c
   hipError_t e = hipSuccess;
   for (int m = 0; m < count && e == hipSuccess; ++m) {
     const BatchMatrix& x = mats[m];
+    rec.cur = m;
     e = selinv_launch(selinv_plan(x.n, x.b, x.a, false), x.n, x.b, x.a, x.LD, x.LB, x.LR, x.LT, x.XD, x.XB, x.XR, x.XT,
                       work + L.slice[m], nullptr);
   }
   g_rec = nullptr;
   return e;
+}
+
+// For each backward-sweep step of the merged plan, the index of the
+// preprocessing-branch stage (phase < 2) after which the block of that step is
+// ready in every matrix that has it (block n_m - 1 - step of matrix m); a step
+// whose blocks were not marked waits for the whole branch (absent from the map).
+static std::map<int, int> sweep_waits(const MergedPlan& mp, const StageRecorder& rec, const std::vector<int64_t>& n) {
+  std::map<StageKey, int> index;
+  for (size_t k = 0; k < mp.stages.size(); ++k) index.emplace(mp.stages[k].key, (int)k);
+  std::map<int, int> need;
+  std::map<int, bool> whole;
+  for (const StageExec& ex : mp.stages) {
+    if (ex.key.phase < 2) continue;
+    const int step = ex.key.major;
+    if (need.count(step) || whole.count(step)) continue;
+    int w = -1;
+    bool ok = true;
+    for (size_t m = 0; m < n.size() && ok; ++m) {
+      const int64_t i = n[m] - 1 - step;
+      if (i < 0) continue;
+      if (m >= rec.ready.size() || i >= (int64_t)rec.ready[m].size()) { ok = false; break; }
+      const auto it = index.find(rec.ready[m][i]);
+      if (it == index.end() || mp.stages[it->second].key.phase >= 2) { ok = false; break; }
+      w = std::max(w, it->second);
+    }
+    if (ok && w >= 0) need[step] = w;
+    else whole[step] = true;
+  }
+  return need;
 }
 
 size_t selinv_batch_bytes(int count, const int64_t* n, const int64_t* b, const int64_t* a) {
@@ -363,13 +395,48 @@ hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, h
   }
   if (e0) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); }
 
-  // capture the merged sequence for the next calls with this descriptor set
+  // capture the merged sequence for the next calls with this descriptor set,
+  // as two branches: the preprocessing and arrow-row stages (phases 0 and 1)
+  // on one, the backward sweep (phase 2) on the other, each sweep step waiting
+  // only for the stage after which every matrix's block of that step is
+  // ready (as the single-matrix path overlaps its side stream with the sweep)
+  const auto need = sweep_waits(mp, rec, n);
   SyncLease lease;
   if (!lease.get()) return hipErrorInvalidResourceHandle;
-  hipStream_t cap = lease.get()->capture;
+  SyncCtx* cx = lease.get();
+  hipStream_t cap = cx->capture, cap2 = cx->side;
+  // events: 0 forks the branches, 1 ends the preprocessing branch, 2.. follow
+  // the stages some sweep step waits for (all created before the capture)
+  std::map<int, int> ev_of;  // preprocessing-branch stage index -> event number
+  for (const auto& kv : need) ev_of.emplace(kv.second, 0);
+  int nev = 2;
+  for (auto& kv : ev_of) kv.second = nev++;
+  for (int k = 0; k < nev; ++k)
+    if (!cx->event(k)) return hipErrorInvalidResourceHandle;
   BTA_TRY_E(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-  hipError_t ce = hipSuccess;
-  for (size_t k = 0; k < mp.stages.size() && ce == hipSuccess; ++k) ce = launch_stage(mp.stages[k], dtab, choice[k], cap);
+  hipError_t ce = hipEventRecord(cx->event(0), cap);
+  if (ce == hipSuccess) ce = hipStreamWaitEvent(cap2, cx->event(0), 0);
+  for (size_t k = 0; k < mp.stages.size() && ce == hipSuccess; ++k) {
+    if (mp.stages[k].key.phase >= 2) continue;
+    ce = launch_stage(mp.stages[k], dtab, choice[k], cap2);
+    const auto it = ev_of.find((int)k);
+    if (ce == hipSuccess && it != ev_of.end()) ce = hipEventRecord(cx->event(it->second), cap2);
+  }
+  if (ce == hipSuccess) ce = hipEventRecord(cx->event(1), cap2);
+  int step = -1;
+  for (size_t k = 0; k < mp.stages.size() && ce == hipSuccess; ++k) {
+    const StageExec& ex = mp.stages[k];
+    if (ex.key.phase < 2) continue;
+    if (ex.key.major != step) {
+      step = ex.key.major;
+      const auto it = need.find(step);
+      const int ev = it != need.end() ? ev_of[it->second] : 1;
+      ce = hipStreamWaitEvent(cap, cx->event(ev), 0);
+      if (ce != hipSuccess) break;
+    }
+    ce = launch_stage(ex, dtab, choice[k], cap);
+  }
+  if (ce == hipSuccess) ce = hipStreamWaitEvent(cap, cx->event(1), 0);  // join the preprocessing branch
   hipGraph_t graph = nullptr;
   hipError_t ee = hipStreamEndCapture(cap, &graph);
   if (ce != hipSuccess) return ce;
@@ -391,16 +458,16 @@ hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, h
 // stage holds operations of one kind; (2) the operations merged into one
 // launch touch disjoint memory except for shared reads (no write of one
 // operation overlaps a read or a write of another one in the same stage);
-// (3) every matrix contributes its operations in its own stage order.
+// (3) every matrix contributes its operations in its own stage order;
+// (4) in the replayed graph, no sweep stage shares a written element with a
+// preprocessing stage it is not ordered after.  Out of place and in place.
 // Returns 0 when the plan is valid.
-BTA_TESTING_API int bta_internal_selinv_batch_check(int count, const int64_t* n,
-                                                                                      const int64_t* b, const int64_t* a) {
-  using namespace bta;
+static int selinv_batch_check_one(int count, const int64_t* n, const int64_t* b, const int64_t* a, bool inplace) {
   std::vector<BatchMatrix> mats(count);
   const uintptr_t G = uintptr_t(1) << 36;
   for (int m = 0; m < count; ++m) {
     double* L = reinterpret_cast<double*>((uintptr_t)(2 * m + 1) * G);
-    double* X = reinterpret_cast<double*>((uintptr_t)(2 * m + 2) * G);
+    double* X = inplace ? L : reinterpret_cast<double*>((uintptr_t)(2 * m + 2) * G);
     const int64_t bb = b[m] * b[m], ab = a[m] * b[m];
     mats[m] = BatchMatrix{n[m], b[m], a[m], nullptr, nullptr, nullptr, nullptr,
                           L, L + n[m] * bb, L + n[m] * bb + (n[m] - 1) * bb, L + n[m] * bb + (n[m] - 1) * bb + n[m] * ab,
@@ -410,9 +477,9 @@ BTA_TESTING_API int bta_internal_selinv_batch_check(int count, const int64_t* n,
   const BatchLayout L0 = batch_layout(count, n, b, a, 0);
   StageRecorder rec;
   if (record_batch(count, mats.data(), reinterpret_cast<char*>(uintptr_t(1) << 52), L0, rec) != hipSuccess) return 1;
-  for (const auto& kv : rec.stages) {
-    const StageRecorder::Stage& st = kv.second;
-    struct Span { const char* lo; const char* hi; bool w; int op; };
+  // byte spans of every element window a stage reads or writes, by operation
+  struct Span { const char* lo; const char* hi; bool w; int op; };
+  auto spans_of = [](const StageRecorder::Stage& st) {
     std::vector<Span> spans;
     auto add = [&](const void* base, int64_t rows, int64_t cols, int64_t ld, bool w, int op) {
       if (rows <= 0 || cols <= 0) return;
@@ -449,14 +516,46 @@ BTA_TESTING_API int bta_internal_selinv_batch_check(int count, const int64_t* n,
       }
       ++op;
     }
+    std::sort(spans.begin(), spans.end(), [](const Span& x, const Span& y) { return x.lo < y.lo; });
+    return spans;
+  };
+  // operations merged into one stage run concurrently: no element written by
+  // one may be touched by another
+  std::map<StageKey, std::vector<Span>> by_key;
+  for (const auto& kv : rec.stages) {
+    const StageRecorder::Stage& st = kv.second;
     const int kinds = (!st.gemms.empty()) + (!st.fills.empty()) + (!st.copies.empty()) + (!st.trinvs.empty());
     if (kinds != 1) return 2;
-    std::sort(spans.begin(), spans.end(), [](const Span& x, const Span& y) { return x.lo < y.lo; });
+    const std::vector<Span> spans = spans_of(st);
     for (size_t i = 0; i < spans.size(); ++i)
       for (size_t j = i + 1; j < spans.size() && spans[j].lo < spans[i].hi; ++j)
         if (spans[i].op != spans[j].op && (spans[i].w || spans[j].w)) return 3;
+    by_key.emplace(kv.first, spans);
+  }
+  // the replayed graph runs the sweep (phase 2) beside the preprocessing
+  // branch: a sweep step is ordered only after the preprocessing stage it
+  // waits for, so it must share no written element with any later one
+  const MergedPlan mp = build_plan(rec);
+  const std::vector<int64_t> nv(n, n + count);
+  const std::map<int, int> need = sweep_waits(mp, rec, nv);
+  for (const StageExec& sx : mp.stages) {
+    if (sx.key.phase < 2) continue;
+    const auto it = need.find(sx.key.major);
+    if (it == need.end()) continue;  // waits for the whole branch
+    const std::vector<Span>& ss = by_key.at(sx.key);
+    for (size_t k = (size_t)it->second + 1; k < mp.stages.size(); ++k) {
+      if (mp.stages[k].key.phase >= 2) continue;
+      for (const Span& x : by_key.at(mp.stages[k].key))
+        for (const Span& y : ss)
+          if (x.lo < y.hi && y.lo < x.hi && (x.w || y.w)) return 4;
+    }
   }
   return 0;
+}
+
+BTA_TESTING_API int bta_internal_selinv_batch_check(int count, const int64_t* n, const int64_t* b, const int64_t* a) {
+  const int r = selinv_batch_check_one(count, n, b, a, false);
+  return r != 0 ? r : selinv_batch_check_one(count, n, b, a, true);
 }
 
 }  // namespace bta

@@ -232,6 +232,17 @@ struct StageRecorder {
     std::vector<TrinvOp> trinvs;
   };
   std::map<StageKey, Stage> stages;
+  // ready[m][i]: the stage after which block i of matrix m is ready for the
+  // backward sweep (its preprocessing and arrow row done); cur: the matrix
+  // being recorded
+  int cur = -1;
+  std::vector<std::vector<StageKey>> ready;
+  void mark_ready(int64_t i) {
+    if (cur < 0) return;
+    if ((int)ready.size() <= cur) ready.resize(cur + 1);
+    if ((int64_t)ready[cur].size() <= i) ready[cur].resize(i + 1, StageKey{0, 0, 0});
+    ready[cur][i] = key;
+  }
   void gemm(const GProb& p) { Stage& s = stages[key]; s.kind = 0; s.gemms.push_back(p); }
   void fill(const FillOp& f) { Stage& s = stages[key]; s.kind = 1; s.fills.push_back(f); }
   void copy(const CopyOp& c) { Stage& s = stages[key]; s.kind = 2; s.copies.push_back(c); }

@@ -73,7 +73,11 @@ BTA_TESTING_API int bta_internal_factor_batch_check(int count, const int64_t* n,
 /* Host dry run of every launch of bta_selinv, out of place and in place: each
  * operand window inside its array, no launch writing what it reads (0 = valid). */
 BTA_TESTING_API int bta_internal_selinv_dry_check(int64_t n, int64_t b, int64_t a);
-/* Host check of the merged batched plan (0 = valid). */
+/* Host check of the merged batched plan: the operations merged into one stage
+ * touch no element that another of them writes, and in the replayed graph no
+ * backward-sweep stage shares a written element with a preprocessing stage it
+ * is not ordered after.  0 = valid; 2 = a stage mixes operation kinds, 3 = an
+ * overlap inside a stage, 4 = an overlap between the graph's two branches. */
 BTA_TESTING_API int bta_internal_selinv_batch_check(int count, const int64_t* n, const int64_t* b, const int64_t* a);
 /* The tuning table (tune.hip) as "key=value" lines (up to cap bytes); returns
  * the number of entries.  Keys: "<arch>|<op>|b=<b>|a=<a>|<knob>", e.g. the

@@ -313,6 +313,8 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
     // is ready for the sweep once its row is (event 1 + i)
     if (a == 0 && !dry)
       for (int64_t i = i1 - 1; i >= i0; --i) BTA_TRY(hipEventRecord(event_at(1 + (int)i), sa));
+    if (a == 0 && g_rec)
+      for (int64_t i = i1 - 1; i >= i0; --i) g_rec->mark_ready(i);
     for (int64_t i = i1 - 1; a > 0 && i >= i0; --i) {
       set_stage(1, (int)k, 200 + (int)(i1 - 1 - i));
       GProb p = prob_init();
@@ -329,6 +331,7 @@ hipError_t selinv_launch(const SelinvPlan& sp, int64_t n, int64_t b, int64_t a,
       p.alpha = -1.0;
       BTA_TRY(gemm_launch(&p, 1, sa));
       if (!dry) BTA_TRY(hipEventRecord(event_at(1 + (int)i), sa));
+      if (g_rec) g_rec->mark_ready(i);
     }
   }
 

@@ -74,7 +74,9 @@ def test_batched_factor_interleaving(L):
 
 def test_batched_selinv_merge_is_independent(L):
     """Operations merged into one batched launch never write memory that
-    another operation of the same launch reads or writes."""
+    another operation of the same launch reads or writes, and in the replayed
+    graph no backward-sweep stage shares a written element with a
+    preprocessing stage it is not ordered after (out of place and in place)."""
     from paper_2503_17528_amd import synth
 
     L.bta_internal_selinv_batch_check.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 3
