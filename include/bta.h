@@ -199,12 +199,17 @@ BTA_API bta_status bta_factor_batched(int count, const bta_desc* descs, void* wo
  * tile shape of every merged GEMM launch is chosen by the autotuner (measured
  * on first use of a shape class), and the whole launch sequence is captured
  * once in a HIP graph per descriptor set and replayed (the graphs of the eight
- * most recently used descriptor sets are kept).
+ * most recently used descriptor sets are kept).  In the graph the per-block
+ * preprocessing and the arrow rows form one branch and the backward sweep
+ * another; each sweep step depends only on the stage that completes its
+ * blocks (the backward recurrence of Algorithm 2).
  * Exception to the enqueue-only convention: the first call with a descriptor
  * set runs the stages eagerly and, for shape classes not yet in the tuning
  * table, times both tilings on `stream` and waits for those timings on the
- * host; it must not be made while `stream` is being captured.  Later calls
- * with the same descriptor set, workspace and device only enqueue the graph. */
+ * host.  Later calls with the same descriptor set, workspace and device only
+ * enqueue: an upload of the stage table from a pinned host buffer the library
+ * owns, then the graph.  No call may be made while `stream` is being captured
+ * (the library replays its own graph). */
 BTA_API bta_status bta_selinv_batched(int count, const bta_desc* descs, void* work, size_t work_bytes,
                                bta_stream_t stream);
 

@@ -18,7 +18,14 @@ The library keeps its tuned decisions in a table keyed by
 ``BTA_TUNE_CACHE=<file.json>`` makes the library load the table from that file
 on first use and write measured entries back; ``BTA_FACTOR_LOOKAHEAD``,
 ``BTA_FACTOR_CACHED``, ``BTA_FACTOR_SUB_DELAY`` and ``BTA_SELINV_SPLIT``
-override the table for every shape.
+override the table for every shape.  The batched entry points take fixed
+settings with measurement overrides: ``BTA_BATCH_ORDER`` (0 dispatches the
+matrices' band columns in lockstep, 1 -- the default -- in proportion to each
+chain's length), ``BTA_BATCH_LOOKAHEAD`` and ``BTA_BATCH_SUB_DELAY`` for the
+batched factorization; ``BTA_BATCH_SPREAD=0`` (align every matrix's backward
+sweep with the longest one's first steps instead of spreading it over them)
+and ``BTA_BATCH_SKINNY=0`` (arrow rows through the 64 x 64 tile kernel) for
+the batched selected inversion.
 
 ``tune_factor`` and ``tune_selinv_split`` time candidate settings on a seeded
 synthetic matrix of the given block shape (the median of ``reps`` runs each,

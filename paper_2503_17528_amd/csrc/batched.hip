@@ -12,6 +12,7 @@
 #include <cstring>
 #include <list>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -97,6 +98,7 @@ struct StageExec {
   long long work;   // trinv: workgroups; gemm: 64-tile count
   long long work2;  // gemm: 128-tile count
   bool pure;        // gemm: outputs do not feed the stage's inputs (safe to run twice)
+  bool skinny;      // gemm: every problem takes the skinny kernel (at most 16 rows: the arrow rows)
   std::string shape;
 };
 
@@ -183,6 +185,9 @@ MergedPlan build_plan(const StageRecorder& rec) {
       ex.work = t64;
       ex.work2 = t128;
       ex.pure = stage_pure(st.gemms);
+      long long v = 0;
+      ex.skinny = !(env_int("BTA_BATCH_SKINNY", 0, 1, &v) && v == 0);  // measurement override
+      for (const GProb& q : st.gemms) ex.skinny = ex.skinny && gemm_skinny_ok(q);
       ex.shape = shape_key(st.gemms);
       mp.stages.push_back(ex);
     } else if (st.kind == 1) {
@@ -213,17 +218,41 @@ MergedPlan build_plan(const StageRecorder& rec) {
 
 // ---------------------------------------------------------------- autotuner / graph cache
 
-// Captured graphs of recent descriptor sets, most recently used first; at
-// most kGraphCache of them are kept, the oldest destroyed on insertion.
+// The replay of one descriptor set: its merged stages with their tilings,
+// the sweep's waits, a pinned copy of the table image (uploaded on the
+// caller's stream before every replay, so the upload never blocks the host)
+// and the captured graph.  Recent descriptor sets are kept most recently used
+// first; at most kGraphCache of them, the oldest released on insertion (after
+// its last upload has completed).
 constexpr size_t kGraphCache = 8;
+struct Replay {
+  std::string sig;
+  std::vector<StageExec> stages;
+  std::vector<int> choice;
+  std::map<int, int> need;    // sweep step -> preprocessing stage index it waits for
+  std::map<int, int> ev_of;   // preprocessing stage index -> event number (2, 3, ...)
+  int nev = 2;                // events used: 0 fork, 1 end of the preprocessing branch
+  void* htab = nullptr;       // pinned table image
+  size_t tab_bytes = 0;
+  hipEvent_t uploaded = nullptr;  // recorded after each upload of htab
+  hipGraphExec_t exec = nullptr;
+  ~Replay() {
+    if (uploaded) { (void)hipEventSynchronize(uploaded); (void)hipEventDestroy(uploaded); }
+    if (htab) (void)hipHostFree(htab);
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
 std::mutex g_mu;
-std::list<std::pair<std::string, hipGraphExec_t>> g_graphs;
+std::list<std::shared_ptr<Replay>> g_replays;
 
 int heuristic_big(const StageExec& ex) { return ex.work2 >= 200 ? 1 : 0; }
 
 hipError_t launch_stage(const StageExec& ex, char* dtab, int big, hipStream_t s) {
   switch (ex.kind) {
     case 0: {
+      if (ex.skinny)
+        return gemm_skinny_list_launch(reinterpret_cast<const GProb*>(dtab + ex.off),
+                                       reinterpret_cast<const long long*>(dtab + ex.off_pre), ex.count, ex.work, s);
       if (big)
         return gemm_list_launch(reinterpret_cast<const GProb*>(dtab + ex.off_p128),
                                 reinterpret_cast<const long long*>(dtab + ex.off_pre128), ex.count, ex.work2, 1, s);
@@ -272,9 +301,14 @@ static BatchLayout batch_layout(int count, const int64_t* n, const int64_t* b, c
 static hipError_t record_batch(int count, const BatchMatrix* mats, char* work, const BatchLayout& L, StageRecorder& rec) {
   g_rec = &rec;
   hipError_t e = hipSuccess;
+  rec.span = 0;
+  long long v = 0;
+  if (!(env_int("BTA_BATCH_SPREAD", 0, 1, &v) && v == 0))  // measurement override: 0 aligns the sweeps' first steps
+    for (int m = 0; m < count; ++m) rec.span = std::max<int64_t>(rec.span, mats[m].n);
   for (int m = 0; m < count && e == hipSuccess; ++m) {
     const BatchMatrix& x = mats[m];
     rec.cur = m;
+    rec.cur_n = x.n;
     e = selinv_launch(selinv_plan(x.n, x.b, x.a, false), x.n, x.b, x.a, x.LD, x.LB, x.LR, x.LT, x.XD, x.XB, x.XR, x.XT,
                       work + L.slice[m], nullptr);
   }
@@ -282,32 +316,33 @@ static hipError_t record_batch(int count, const BatchMatrix* mats, char* work, c
   return e;
 }
 
-// For each backward-sweep step of the merged plan, the index of the
-// preprocessing-branch stage (phase < 2) after which the block of that step is
-// ready in every matrix that has it (block n_m - 1 - step of matrix m); a step
-// whose blocks were not marked waits for the whole branch (absent from the map).
-static std::map<int, int> sweep_waits(const MergedPlan& mp, const StageRecorder& rec, const std::vector<int64_t>& n) {
+// For each merged backward-sweep step, the index of the preprocessing-branch
+// stage (phase < 2) after which every block worked on at that step is ready
+// (the block of each matrix that has a step there); a step with a block never
+// marked ready waits for the whole branch (absent from the map).
+static std::map<int, int> sweep_waits(const MergedPlan& mp, const StageRecorder& rec) {
   std::map<StageKey, int> index;
   for (size_t k = 0; k < mp.stages.size(); ++k) index.emplace(mp.stages[k].key, (int)k);
   std::map<int, int> need;
   std::map<int, bool> whole;
-  for (const StageExec& ex : mp.stages) {
-    if (ex.key.phase < 2) continue;
-    const int step = ex.key.major;
-    if (need.count(step) || whole.count(step)) continue;
-    int w = -1;
-    bool ok = true;
-    for (size_t m = 0; m < n.size() && ok; ++m) {
-      const int64_t i = n[m] - 1 - step;
-      if (i < 0) continue;
-      if (m >= rec.ready.size() || i >= (int64_t)rec.ready[m].size()) { ok = false; break; }
-      const auto it = index.find(rec.ready[m][i]);
-      if (it == index.end() || mp.stages[it->second].key.phase >= 2) { ok = false; break; }
-      w = std::max(w, it->second);
+  for (size_t m = 0; m < rec.sweep_block.size(); ++m)
+    for (const auto& kv : rec.sweep_block[m]) {
+      const int S = kv.first;
+      const int64_t i = kv.second;
+      if (whole.count(S)) continue;
+      int idx = -1;
+      if (m < rec.ready.size() && i >= 0 && i < (int64_t)rec.ready[m].size()) {
+        const auto it = index.find(rec.ready[m][i]);
+        if (it != index.end() && mp.stages[it->second].key.phase < 2) idx = it->second;
+      }
+      if (idx < 0) {
+        whole[S] = true;
+        need.erase(S);
+        continue;
+      }
+      const auto it = need.find(S);
+      need[S] = it == need.end() ? idx : std::max(it->second, idx);
     }
-    if (ok && w >= 0) need[step] = w;
-    else whole[step] = true;
-  }
   return need;
 }
 
@@ -326,6 +361,50 @@ size_t selinv_batch_bytes(int count, const int64_t* n, const int64_t* b, const i
   return batch_layout(count, n, b, a, mp.table.size()).bytes;
 }
 
+// Issue a replay's stages: the preprocessing and arrow-row stages (phases 0
+// and 1) on `side`, forked from `main`, the backward sweep (phase 2) on
+// `main`, each sweep step waiting only for the preprocessing stage after
+// which every matrix's block of that step is ready; `side` joins `main` at
+// the end.  The preprocessing branch is issued first, so every wait follows
+// the record of its event.  (Issuing each sweep step right after the stage it
+// waits for measured slower in the captured graph: 45.9 ms against 42.5 ms
+// per step of the 64-matrix workload; launching the same sequence directly on
+// two streams instead of replaying a graph, 43.8 ms.)
+static hipError_t issue_replay(const Replay& r, char* dtab, hipStream_t main, hipStream_t side, SyncCtx* cx) {
+  BTA_TRY_E(hipEventRecord(cx->event(0), main));
+  BTA_TRY_E(hipStreamWaitEvent(side, cx->event(0), 0));
+  // sweep steps in order: (stage index waited for, event, stage indices)
+  struct Step { int wait; int ev; std::vector<int> st; };
+  std::vector<Step> steps;
+  std::vector<int> pre;
+  for (size_t k = 0; k < r.stages.size(); ++k) {
+    const StageKey& key = r.stages[k].key;
+    if (key.phase < 2) { pre.push_back((int)k); continue; }
+    if (steps.empty() || r.stages[steps.back().st.back()].key.major != key.major) {
+      const auto it = r.need.find(key.major);
+      if (it != r.need.end()) steps.push_back(Step{it->second, r.ev_of.at(it->second), {}});
+      else steps.push_back(Step{INT32_MAX, 1, {}});
+    }
+    steps.back().st.push_back((int)k);
+  }
+  size_t next = 0;
+  auto issue_steps = [&](int done) -> hipError_t {
+    for (; next < steps.size() && steps[next].wait <= done; ++next) {
+      BTA_TRY_E(hipStreamWaitEvent(main, cx->event(steps[next].ev), 0));
+      for (int k : steps[next].st) BTA_TRY_E(launch_stage(r.stages[k], dtab, r.choice[k], main));
+    }
+    return hipSuccess;
+  };
+  for (int k : pre) {
+    BTA_TRY_E(launch_stage(r.stages[k], dtab, r.choice[k], side));
+    const auto it = r.ev_of.find(k);
+    if (it != r.ev_of.end()) BTA_TRY_E(hipEventRecord(cx->event(it->second), side));
+  }
+  BTA_TRY_E(hipEventRecord(cx->event(1), side));
+  BTA_TRY_E(issue_steps(INT32_MAX));
+  return hipStreamWaitEvent(main, cx->event(1), 0);  // join the preprocessing branch
+}
+
 hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, hipStream_t stream) {
   std::vector<int64_t> n(count), b(count), a(count);
   for (int m = 0; m < count; ++m) { n[m] = mats[m].n; b[m] = mats[m].b; a[m] = mats[m].a; }
@@ -335,19 +414,28 @@ hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, h
   BTA_TRY_E(record_batch(count, mats, w, L0, rec));
   const MergedPlan mp = build_plan(rec);
   char* dtab = w + L0.table_off;
-  BTA_TRY_E(hipMemcpyAsync(dtab, mp.table.data(), mp.table.size(), hipMemcpyHostToDevice, stream));
+  int dev = 0;
+  BTA_TRY_E(hipGetDevice(&dev));
 
   // descriptor-set signature: the table image holds every pointer and size
   std::string sig(mp.table.begin(), mp.table.end());
-  sig += std::to_string(reinterpret_cast<uintptr_t>(work));
+  sig += "|" + std::to_string(reinterpret_cast<uintptr_t>(work)) + "|" + std::to_string(dev);
+  std::shared_ptr<Replay> hit;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
-      if (it->first == sig) {
-        g_graphs.splice(g_graphs.begin(), g_graphs, it);  // most recently used
-        return hipGraphLaunch(g_graphs.front().second, stream);
+    for (auto it = g_replays.begin(); it != g_replays.end(); ++it)
+      if ((*it)->sig == sig) {
+        g_replays.splice(g_replays.begin(), g_replays, it);  // most recently used
+        hit = g_replays.front();
+        break;
       }
   }
+  if (hit) {
+    BTA_TRY_E(hipMemcpyAsync(dtab, hit->htab, hit->tab_bytes, hipMemcpyHostToDevice, stream));
+    BTA_TRY_E(hipEventRecord(hit->uploaded, stream));
+    return hipGraphLaunch(hit->exec, stream);
+  }
+  BTA_TRY_E(hipMemcpyAsync(dtab, mp.table.data(), mp.table.size(), hipMemcpyHostToDevice, stream));
 
   // first use: run eagerly; a pure GEMM stage whose shape class is not in the
   // tuning table is timed with both tilings (median of three runs each; the
@@ -364,6 +452,10 @@ hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, h
     }
     long long tuned = -1;
     if (!tune_get(stage_key(ex), &tuned) || (tuned != 0 && tuned != 1)) tuned = -1;
+    if (ex.skinny) {  // one kernel: nothing to tune
+      BTA_TRY_E(launch_stage(ex, dtab, 0, stream));
+      continue;
+    }
     if (tuned < 0 && ex.pure && ex.work2 > 0) {
       if (!e0) {
         BTA_TRY_E(hipEventCreate(&e0));
@@ -395,62 +487,37 @@ hipError_t selinv_batch_launch(int count, const BatchMatrix* mats, void* work, h
   }
   if (e0) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); }
 
-  // capture the merged sequence for the next calls with this descriptor set,
-  // as two branches: the preprocessing and arrow-row stages (phases 0 and 1)
-  // on one, the backward sweep (phase 2) on the other, each sweep step waiting
-  // only for the stage after which every matrix's block of that step is
-  // ready (as the single-matrix path overlaps its side stream with the sweep)
-  const auto need = sweep_waits(mp, rec, n);
-  SyncLease lease;
-  if (!lease.get()) return hipErrorInvalidResourceHandle;
-  SyncCtx* cx = lease.get();
-  hipStream_t cap = cx->capture, cap2 = cx->side;
-  // events: 0 forks the branches, 1 ends the preprocessing branch, 2.. follow
-  // the stages some sweep step waits for (all created before the capture)
-  std::map<int, int> ev_of;  // preprocessing-branch stage index -> event number
-  for (const auto& kv : need) ev_of.emplace(kv.second, 0);
-  int nev = 2;
-  for (auto& kv : ev_of) kv.second = nev++;
-  for (int k = 0; k < nev; ++k)
-    if (!cx->event(k)) return hipErrorInvalidResourceHandle;
-  BTA_TRY_E(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-  hipError_t ce = hipEventRecord(cx->event(0), cap);
-  if (ce == hipSuccess) ce = hipStreamWaitEvent(cap2, cx->event(0), 0);
-  for (size_t k = 0; k < mp.stages.size() && ce == hipSuccess; ++k) {
-    if (mp.stages[k].key.phase >= 2) continue;
-    ce = launch_stage(mp.stages[k], dtab, choice[k], cap2);
-    const auto it = ev_of.find((int)k);
-    if (ce == hipSuccess && it != ev_of.end()) ce = hipEventRecord(cx->event(it->second), cap2);
+  // the replay of the next calls with this descriptor set
+  auto r = std::make_shared<Replay>();
+  r->sig = sig;
+  r->stages = mp.stages;
+  r->choice = choice;
+  r->need = sweep_waits(mp, rec);
+  for (const auto& kv : r->need) r->ev_of.emplace(kv.second, 0);
+  for (auto& kv : r->ev_of) kv.second = r->nev++;
+  BTA_TRY_E(hipHostMalloc(&r->htab, mp.table.size(), 0));
+  std::memcpy(r->htab, mp.table.data(), mp.table.size());
+  r->tab_bytes = mp.table.size();
+  BTA_TRY_E(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
+  {
+    SyncLease lease;
+    SyncCtx* cx = lease.get();
+    if (!cx) return hipErrorInvalidResourceHandle;
+    for (int k = 0; k < r->nev; ++k)
+      if (!cx->event(k)) return hipErrorInvalidResourceHandle;  // created before the capture
+    BTA_TRY_E(hipStreamBeginCapture(cx->capture, hipStreamCaptureModeThreadLocal));
+    const hipError_t ce = issue_replay(*r, dtab, cx->capture, cx->side, cx);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cx->capture, &graph);
+    if (ce != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return ce; }
+    if (ee != hipSuccess) return ee;
+    const hipError_t ie = hipGraphInstantiate(&r->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return ie;
   }
-  if (ce == hipSuccess) ce = hipEventRecord(cx->event(1), cap2);
-  int step = -1;
-  for (size_t k = 0; k < mp.stages.size() && ce == hipSuccess; ++k) {
-    const StageExec& ex = mp.stages[k];
-    if (ex.key.phase < 2) continue;
-    if (ex.key.major != step) {
-      step = ex.key.major;
-      const auto it = need.find(step);
-      const int ev = it != need.end() ? ev_of[it->second] : 1;
-      ce = hipStreamWaitEvent(cap, cx->event(ev), 0);
-      if (ce != hipSuccess) break;
-    }
-    ce = launch_stage(ex, dtab, choice[k], cap);
-  }
-  if (ce == hipSuccess) ce = hipStreamWaitEvent(cap, cx->event(1), 0);  // join the preprocessing branch
-  hipGraph_t graph = nullptr;
-  hipError_t ee = hipStreamEndCapture(cap, &graph);
-  if (ce != hipSuccess) return ce;
-  if (ee != hipSuccess) return ee;
-  hipGraphExec_t exec = nullptr;
-  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (ie != hipSuccess) return ie;
   std::lock_guard<std::mutex> lk(g_mu);
-  g_graphs.emplace_front(sig, exec);
-  while (g_graphs.size() > kGraphCache) {
-    (void)hipGraphExecDestroy(g_graphs.back().second);
-    g_graphs.pop_back();
-  }
+  g_replays.push_front(r);
+  while (g_replays.size() > kGraphCache) g_replays.pop_back();
   return hipSuccess;
 }
 
@@ -536,8 +603,7 @@ static int selinv_batch_check_one(int count, const int64_t* n, const int64_t* b,
   // branch: a sweep step is ordered only after the preprocessing stage it
   // waits for, so it must share no written element with any later one
   const MergedPlan mp = build_plan(rec);
-  const std::vector<int64_t> nv(n, n + count);
-  const std::map<int, int> need = sweep_waits(mp, rec, nv);
+  const std::map<int, int> need = sweep_waits(mp, rec);
   for (const StageExec& sx : mp.stages) {
     if (sx.key.phase < 2) continue;
     const auto it = need.find(sx.key.major);

@@ -46,6 +46,7 @@ struct FactorBatchPlan {
   std::vector<std::array<size_t, 2>> ws_off;
   long long nflags = 0, ntasks = 0, nseg = 0;
   size_t off_ctl = 0, off_mats = 0, off_segs = 0, off_flags = 0, bytes = 0;
+  int order = 1;  // segment order: 0 by chain position, 1 by the fraction of the chain
 };
 FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b, const int64_t* a, int num_cus);
 hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mats, void* work, hipStream_t stream,
@@ -232,16 +233,28 @@ struct StageRecorder {
     std::vector<TrinvOp> trinvs;
   };
   std::map<StageKey, Stage> stages;
-  // ready[m][i]: the stage after which block i of matrix m is ready for the
-  // backward sweep (its preprocessing and arrow row done); cur: the matrix
-  // being recorded
+  // cur: the matrix being recorded, cur_n its block count.  ready[m][i]: the
+  // stage after which block i of matrix m is ready for the backward sweep
+  // (its preprocessing and arrow row done; {-1,-1,-1} if never marked).
+  // span > 1: the sweep of every matrix is spread over `span` merged steps
+  // (its step s of cur_n becomes s (span-1) / (cur_n-1), strictly increasing),
+  // so that short sweeps do not crowd the first steps of the longest one;
+  // sweep_block[m][S] = the block matrix m works on at merged step S.
   int cur = -1;
+  int64_t cur_n = 0, span = 0;
   std::vector<std::vector<StageKey>> ready;
+  std::vector<std::map<int, int64_t>> sweep_block;
   void mark_ready(int64_t i) {
     if (cur < 0) return;
     if ((int)ready.size() <= cur) ready.resize(cur + 1);
-    if ((int64_t)ready[cur].size() <= i) ready[cur].resize(i + 1, StageKey{0, 0, 0});
+    if ((int64_t)ready[cur].size() <= i) ready[cur].resize(i + 1, StageKey{-1, -1, -1});
     ready[cur][i] = key;
+  }
+  int sweep_step(int s) const { return (span > 1 && cur_n > 1) ? (int)((int64_t)s * (span - 1) / (cur_n - 1)) : s; }
+  void note_sweep(int S, int64_t block) {
+    if (cur < 0) return;
+    if ((int)sweep_block.size() <= cur) sweep_block.resize(cur + 1);
+    sweep_block[cur][S] = block;
   }
   void gemm(const GProb& p) { Stage& s = stages[key]; s.kind = 0; s.gemms.push_back(p); }
   void fill(const FillOp& f) { Stage& s = stages[key]; s.kind = 1; s.fills.push_back(f); }
@@ -250,7 +263,13 @@ struct StageRecorder {
 };
 extern thread_local StageRecorder* g_rec;
 inline void set_stage(int phase, int major, int minor) {
-  if (g_rec) g_rec->key = StageKey{phase, major, minor};
+  if (!g_rec) return;
+  if (phase == 2) {  // backward-sweep step `major`: block cur_n - 1 - major
+    const int S = g_rec->sweep_step(major);
+    if (minor == 0) g_rec->note_sweep(S, g_rec->cur_n - 1 - major);
+    major = S;
+  }
+  g_rec->key = StageKey{phase, major, minor};
 }
 inline bool recording() { return g_dry != nullptr || g_rec != nullptr; }
 
@@ -258,6 +277,12 @@ inline bool recording() { return g_dry != nullptr || g_rec != nullptr; }
 hipError_t gemm_list_launch(const GProb* d_probs, const long long* d_tile_begin, int nprob, long long ntiles, int big,
                             hipStream_t stream);
 long long gemm_prob_tiles(GProb& p, int tile);
+// Products of at most 16 rows with plain k ranges, A by rows, B by k rows, one
+// batch entry and a full store; launched one workgroup per 64 columns
+// (tile_begin[] as for 64 x 64 tiles).
+bool gemm_skinny_ok(const GProb& p);
+hipError_t gemm_skinny_list_launch(const GProb* d_probs, const long long* d_tile_begin, int nprob, long long ntiles,
+                                   hipStream_t stream);
 
 // Optional per-kernel timing with HIP events recorded on the launch stream
 // around each launch of the main kernels (off unless enabled).

@@ -104,6 +104,13 @@ BTA_TESTING_API int bta_internal_gemm_mode(int mode);
 BTA_TESTING_API int bta_internal_gemm(int M, int N, int K, const double* A, int64_t lda, int at, const double* B,
                                       int64_t ldb, int bt, int tri, const double* Cin, double* C, int64_t ldc,
                                       double alpha, double beta, int store, int lower_tiles, hipStream_t s);
+/* A product of at most 16 rows through the skinny list kernel, as two k
+ * segments [0, K1) and [K1, K) (A by rows, B by k rows, full store); dlist is
+ * device memory of at least 512 bytes; synchronizes `s`.  -1 when the product
+ * does not qualify. */
+BTA_TESTING_API int bta_internal_gemm_skinny(int M, int N, int K, int K1, const double* A, int64_t lda, const double* B,
+                                             int64_t ldb, const double* Cin, double* C, int64_t ldc, double alpha,
+                                             double beta, void* dlist, hipStream_t s);
 /* The same product through the split-k path of the selected inversion's sweep
  * (ws: device partials of ws_doubles; *splits receives the split count used). */
 BTA_TESTING_API int bta_internal_gemm_split(int M, int N, int K, const double* A, int64_t lda, int at, const double* B,

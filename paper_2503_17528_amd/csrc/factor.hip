@@ -903,8 +903,14 @@ __global__ void factor_finish_kernel(const int* ctl, int64_t* info) {
 static int g_factor_look = 0;
 // DIAG lookahead of the batched kernel: with many matrices in flight a longer
 // lookahead only holds more workgroups on waiting tiles (measured on the 64-matrix
-// workload: 23.2, 22.5, 23.2, 23.6 and 23.9 ms for 1, 2, 3, 4 and 8 columns).
+// workload in lockstep order: 23.2, 22.5, 23.2, 23.6 and 23.9 ms for 1, 2, 3, 4
+// and 8 columns; in proportional order 19.1, 18.4-18.9, 19.1, 19.5 ms for 1-4).
 constexpr int BATCH_LOOKAHEAD = 2;
+// SUB delay of the batched kernel (columns): SUB tasks dispatched one column
+// after their own no longer hold workgroups waiting on the column's diagonal
+// tile (64-matrix workload, proportional order: 18.4-18.9 ms undelayed, 16.8 ms
+// with 1, 17.2 ms with 2).
+constexpr int BATCH_SUB_DELAY = 1;
 // Upper bound on the factor kernel's workgroups (internal, for measurements; 0: one per CU).
 static int g_factor_max_grid = 0;
 // k-loop operands through the L2 where the tiles are line-aligned: internal
@@ -1034,13 +1040,16 @@ hipError_t factor_launch(const FactorPlan& fp, int64_t n, int64_t b, int64_t a,
 
 // ---------------------------------------------------------------------------
 // Band-column interleaving of the matrices of a batch.  Segment (m, i, c)
-// holds the tasks of band column c of block step i of matrix m (the step's
-// tip updates go with its last column, the final tip tasks with the last
-// column of the last step).  Segments are ordered by the column's position on
-// its matrix's chain of diagonal tiles, i*T_m + c, so that each matrix's
-// columns are dispatched at the pace of its own chain rather than in lockstep
-// with wider matrices; equal positions go longest chain first.  Per matrix the
-// local ticket order is kept.  *total receives the number of tickets.
+// holds the tasks of column group c of block step i of matrix m, as decode()
+// lays them out (the step's tip updates go with its last group, the final tip
+// tasks with the last group of the last step).  A group's position on its
+// matrix's chain of diagonal tiles is i*T_m + c (the delayed SUB groups after
+// the last column stay at the last column); segments are ordered by that
+// position scaled by the longest chain over the matrix's own, so that each
+// matrix's columns are dispatched at the pace of its own chain and spread
+// over the longest chain's time, rather than in lockstep with wider matrices;
+// equal positions go longest chain first.  Per matrix the local ticket order
+// is kept.  *total receives the number of tickets.
 static std::vector<BatchSeg> batch_segments(const FactorBatchPlan& bp, const int64_t* n, long long* total) {
   struct Col {
     long long key, chain, local0, len;
@@ -1054,30 +1063,52 @@ static std::vector<BatchSeg> batch_segments(const FactorBatchPlan& bp, const int
     long long local = 0;
     for (int64_t i = 0; i < n[m]; ++i) {
       const bool has_sub = i < n[m] - 1;
-      for (int c = 0; c < T; ++c) {
-        // the column group of decode(): DIAG tasks, OFFD, SUB and ARW rows
-        const int ndg = (c == 0) ? L + 1 : ((c + L <= T - 1) ? 1 : 0);
-        const int no = (c <= T - 2) ? T - c - 2 : 0;
-        const int ns = has_sub ? (c == T - 1 ? T - 1 : T) : 0;
-        long long len = ndg + no + ns + TA;
-        if (c == T - 1) {
+      const int S = has_sub ? fp.sub_delay : 0;
+      for (int c = 0; c < T + S; ++c) {
+        // the column group of decode(): DIAG tasks, OFFD, the SUB tasks of
+        // column c - S and ARW rows; the last S groups hold SUB tasks only
+        const bool col = c < T;
+        const int cs = c - S;
+        const int ndg = !col ? 0 : (c == 0) ? L + 1 : ((c + L <= T - 1) ? 1 : 0);
+        const int no = (col && c <= T - 2) ? T - c - 2 : 0;
+        const int ns = (has_sub && cs >= 0) ? (cs == T - 1 ? T - 1 : T) : 0;
+        long long len = ndg + no + ns + (col ? TA : 0);
+        if (c == T + S - 1) {
           len += (long long)TA * (TA + 1) / 2;               // the step's tip updates
           if (!has_sub) len += (long long)TA * (TA + 1) / 2;  // the tip itself
         }
-        if (len > 0) cols.push_back(Col{i * T + c, n[m] * (long long)T, local, len, m});  // no segment for an empty column
+        // position on the chain; the delayed SUB groups stay at the step's
+        // last column so that the key never decreases within a matrix
+        const long long key = i * T + std::min(c, T - 1);
+        if (len > 0) cols.push_back(Col{key, n[m] * (long long)T, local, len, m});  // no segment for an empty group
         local += len;
       }
     }
   }
-  std::stable_sort(cols.begin(), cols.end(), [](const Col& x, const Col& y) {
-    if (x.key != y.key) return x.key < y.key;
+  // proportional order (the default): by the fraction of its chain scaled to
+  // the longest chain, so that every matrix's columns are spread over the
+  // longest chain's time instead of crowding its start; lockstep: by chain
+  // position
+  long long cmax = 1;
+  for (const Col& c : cols) cmax = std::max(cmax, c.chain);
+  std::vector<double> pos(cols.size());
+  for (size_t q = 0; q < cols.size(); ++q) {
+    const Col& c = cols[q];
+    pos[q] = bp.order == 1 ? (double)c.key * (double)cmax / (double)c.chain : (double)c.key;
+  }
+  std::vector<size_t> idx(cols.size());
+  for (size_t q = 0; q < idx.size(); ++q) idx[q] = q;
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t qx, size_t qy) {
+    const Col &x = cols[qx], &y = cols[qy];
+    if (pos[qx] != pos[qy]) return pos[qx] < pos[qy];
     if (x.chain != y.chain) return x.chain > y.chain;
     return x.m < y.m;
   });
   std::vector<BatchSeg> segs;
   segs.reserve(cols.size());
   long long t = 0;
-  for (const Col& c : cols) {
+  for (size_t q : idx) {
+    const Col& c = cols[q];
     segs.push_back(BatchSeg{t, c.local0, c.m, 0});
     t += c.len;
   }
@@ -1112,21 +1143,27 @@ FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b,
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
   bp.off_ctl = take(64);
   bp.off_mats = take(sizeof(FactorParams) * (size_t)count);
-  // segments: at most one per band column of every matrix
-  int64_t nseg = 0;
-  for (int m = 0; m < count; ++m) nseg += n[m] * ((b[m] + 63) / 64);
-  bp.nseg = nseg;
-  bp.off_segs = take(sizeof(BatchSeg) * (size_t)nseg);
   long long nflags = 0;
   bp.flag_off.resize(count);
   bp.ws_off.resize(count);
+  // segment order, DIAG lookahead and SUB delay of the batch: measurement
+  // overrides BTA_BATCH_ORDER (0 lockstep, 1 proportional),
+  // BTA_BATCH_LOOKAHEAD and BTA_BATCH_SUB_DELAY
+  long long v = 0;
+  bp.order = env_int("BTA_BATCH_ORDER", 0, 1, &v) ? (int)v : 1;
+  const int look = env_int("BTA_BATCH_LOOKAHEAD", 0, 64, &v) ? (int)v : BATCH_LOOKAHEAD;
+  const int sub_delay = env_int("BTA_BATCH_SUB_DELAY", 0, 64, &v) ? (int)v : BATCH_SUB_DELAY;
+  int64_t nseg = 0;  // segments: one per column group of every step
   for (int m = 0; m < count; ++m) {
     bp.plans[m] = factor_plan(n[m], b[m], a[m]);
-    bp.plans[m].look = std::min(bp.plans[m].look, BATCH_LOOKAHEAD);
-    bp.plans[m].sub_delay = 0;  // the batch segments follow decode()'s undelayed column groups
+    bp.plans[m].look = std::min(bp.plans[m].look, look);
+    bp.plans[m].sub_delay = std::min(sub_delay, bp.plans[m].T);
+    nseg += n[m] * bp.plans[m].T + (n[m] - 1) * bp.plans[m].sub_delay;
     bp.flag_off[m] = nflags;
     nflags += bp.plans[m].nflags;
   }
+  bp.nseg = nseg;
+  bp.off_segs = take(sizeof(BatchSeg) * (size_t)nseg);
   bp.nflags = nflags;
   bp.off_flags = take(sizeof(int) * (size_t)std::max<long long>(nflags, 1));
   for (int m = 0; m < count; ++m) {
@@ -1171,6 +1208,7 @@ hipError_t factor_batch_launch(const FactorBatchPlan& bp, const BatchMatrix* mat
     p.step_full = fp.step_full;
     p.step_last = fp.step_last;
     p.look = fp.look;
+    p.sub_delay = fp.sub_delay;
     p.spin_limit = 1LL << 22;
     p.cached = (factor_cached_loads(p.b, p.a) && factor_lines_aligned(p.b, p.a, p.LD, p.LB, p.LR, p.LT)) ? 1 : 0;
     p.fast = (!p.cached && factor_ops_direct(p.b, p.a, p.LD, p.LB, p.LR, p.LT)) ? 1 : 0;
@@ -1430,12 +1468,14 @@ BTA_TESTING_API int bta_internal_factor_batch_check(int count, const int64_t* n,
   std::vector<std::vector<long long>> maxdep(count), global(count);
   std::vector<bta::FactorParams> ps(count);
   for (int m = 0; m < count; ++m) {
-    if (bta::factor_schedule_replay(n[m], b[m], a[m], bp.plans[m].look, nullptr, &maxdep[m], 0) != 0) return 5;
+    if (bta::factor_schedule_replay(n[m], b[m], a[m], bp.plans[m].look, nullptr, &maxdep[m], bp.plans[m].sub_delay) != 0)
+      return 5;
     global[m].assign((size_t)bp.plans[m].ntasks, -1);
     bta::FactorParams& p = ps[m];
     p.n = (int)n[m]; p.b = (int)b[m]; p.a = (int)a[m]; p.T = bp.plans[m].T; p.TA = bp.plans[m].TA;
     p.ntasks = bp.plans[m].ntasks; p.step_full = bp.plans[m].step_full; p.step_last = bp.plans[m].step_last;
     p.look = bp.plans[m].look;
+    p.sub_delay = bp.plans[m].sub_delay;
   }
   std::vector<long long> next(count, 0);
   std::vector<int> seg_of(total > 0 ? (size_t)total : 1);
@@ -1454,22 +1494,25 @@ BTA_TESTING_API int bta_internal_factor_batch_check(int count, const int64_t* n,
   }
   for (int m = 0; m < count; ++m)
     if (next[m] != bp.plans[m].ntasks) return 3;
-  // segment contents: the column a task is dispatched with (DIAG tasks L
-  // columns early, tip work with the last column) is the segment's column
+  // segment contents: the column group a task is dispatched with (DIAG
+  // tasks L columns early, SUB tasks S columns late, tip work with the last
+  // group) is the segment's group
   {
     std::vector<long long> first_key(count, -1);
     for (size_t q = 0; q < segs.size(); ++q) {
       const long long len = (q + 1 < segs.size() ? segs[q + 1].t0 : total) - segs[q].t0;
       const int m = segs[q].mat;
       const bta::FactorParams& p = ps[m];
+      const long long G = p.T + p.sub_delay;  // groups per step (at most)
       long long key = -1;
       for (long long e = 0; e < len; ++e) {
         const bta::Task t = bta::decode(p, segs[q].local0 + e);
         long long k;
-        if (t.type == bta::T_TIPD || t.type == bta::T_TIPO) k = (long long)(p.n - 1) * p.T + p.T - 1;
-        else if (t.type == bta::T_TUPD) k = (long long)t.i * p.T + p.T - 1;
-        else if (t.type == bta::T_DIAG) k = (long long)t.i * p.T + (t.c <= p.look ? 0 : t.c - p.look);
-        else k = (long long)t.i * p.T + t.c;
+        if (t.type == bta::T_TIPD || t.type == bta::T_TIPO) k = (long long)(p.n - 1) * G + p.T - 1;
+        else if (t.type == bta::T_TUPD) k = (long long)t.i * G + (t.i < p.n - 1 ? G : p.T) - 1;
+        else if (t.type == bta::T_DIAG) k = (long long)t.i * G + (t.c <= p.look ? 0 : t.c - p.look);
+        else if (t.type == bta::T_SUB) k = (long long)t.i * G + t.c + p.sub_delay;
+        else k = (long long)t.i * G + t.c;
         if (key < 0) key = k;
         if (k != key) return 4;
       }

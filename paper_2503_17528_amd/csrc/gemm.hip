@@ -792,6 +792,101 @@ __global__ __launch_bounds__(NT, 1) void gemm128_list_kernel(const GProb* probs,
   else gemm_tile_body<4, 4, 32>(P, local, threadIdx.x, lds, lds + 128 * 34);
 }
 
+// Skinny products: at most SK_M rows of C, every segment with plain k ranges
+// (TRI_NONE), A read along its rows (at == 0) and B along its k rows
+// (bt == 1), one batch entry, a full store.  The selected inversion's arrow
+// rows are such products (a rows): with 64 x 64 tiles most of every tile's
+// MFMA work and k-loop latency would go to rows that do not exist.  One
+// workgroup per 64 columns of one problem: each thread owns a column and a
+// k residue mod 4 and keeps SK_M row sums; A is staged through LDS in chunks
+// of SK_KC k values (one broadcast read per k and row), B streams from memory
+// (coalesced rows of 64 doubles; a chunk's loads of A and B are all issued
+// before any is used: the kernel is bound by reading B).  The four k residues are added in a fixed order:
+// deterministic.
+constexpr int SK_M = 16, SK_KC = 128;
+
+bool gemm_skinny_ok(const GProb& p) {
+  if (p.M > SK_M || p.M <= 0 || p.nb0 != 1 || p.nb1 != 1 || p.store != ST_FULL || p.lower_tiles) return false;
+  for (int s = 0; s < p.nseg; ++s)
+    if (p.seg[s].tri != TRI_NONE || p.seg[s].at != 0 || p.seg[s].bt != 1) return false;
+  return true;
+}
+
+__global__ __launch_bounds__(256) void gemm_skinny_list_kernel(const GProb* probs, const long long* tile_begin, int nprob) {
+  __shared__ double As[SK_M * SK_KC];
+  __shared__ double red[4 * SK_M * 64];
+  const int j = find_prob_list(tile_begin, nprob, blockIdx.x);
+  const GProb& P = probs[j];
+  const int tid = threadIdx.x, c = tid & 63;
+  const int ks = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int M = P.M, N = P.N;
+  const int M4 = (M + 3) & ~3;  // rows in groups of four (rows M .. M4-1 of As are zero)
+  const int c0 = (int)(blockIdx.x - tile_begin[j]) * 64;
+  const int gc = c0 + c;
+  const int ar = tid >> 7, ak = tid & (SK_KC - 1);  // A staging: rows ar + 2q, column ak of the chunk
+  double acc[SK_M];
+#pragma unroll
+  for (int m = 0; m < SK_M; ++m) acc[m] = 0.0;
+  for (int s = 0; s < P.nseg; ++s) {
+    const GSeg& g = P.seg[s];
+    for (int k0 = 0; k0 < g.K; k0 += SK_KC) {
+      const int kc = min(SK_KC, g.K - k0);
+      // every load of the chunk in flight at once: the A chunk (coalesced
+      // along k) and this thread's 32 values of B (k = ks + 4u)
+      double areg[SK_M / 2];
+#pragma unroll
+      for (int q = 0; q < SK_M / 2; ++q) {
+        const int m = ar + 2 * q;
+        areg[q] = (m < M && ak < kc) ? g.A[(int64_t)m * g.lda + k0 + ak] : 0.0;
+      }
+      const double* Bk = g.B + (int64_t)k0 * g.ldb + (gc < N ? gc : 0);
+      double bv[SK_KC / 4];
+#pragma unroll
+      for (int u = 0; u < SK_KC / 4; ++u) {
+        const int k = ks + 4 * u;
+        bv[u] = (k < kc && gc < N) ? Bk[(int64_t)k * g.ldb] : 0.0;
+      }
+      __syncthreads();  // the previous chunk's reads of As are done
+#pragma unroll
+      for (int q = 0; q < SK_M / 2; ++q)
+        if (ar + 2 * q < M4) As[(ar + 2 * q) * SK_KC + ak] = areg[q];
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < SK_KC / 4; ++u) {
+        const int k = ks + 4 * u;
+#pragma unroll
+        for (int mg = 0; mg < SK_M / 4; ++mg) {
+          if (4 * mg >= M4) break;  // workgroup-uniform
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[4 * mg + r] = fma(As[(4 * mg + r) * SK_KC + k], bv[u], acc[4 * mg + r]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < SK_M; ++m) red[(ks * SK_M + m) * 64 + c] = acc[m];
+  __syncthreads();
+  for (int e = tid; e < M * 64; e += 256) {
+    const int m = e >> 6, cc = e & 63, col = c0 + cc;
+    if (col >= N) continue;
+    double v = red[(0 * SK_M + m) * 64 + cc] + red[(1 * SK_M + m) * 64 + cc];
+    v += red[(2 * SK_M + m) * 64 + cc];
+    v += red[(3 * SK_M + m) * 64 + cc];
+    v *= P.alpha;
+    if (P.beta != 0.0) v += P.beta * P.Cin[(int64_t)m * P.ldc + col];
+    P.Cout[(int64_t)m * P.ldc + col] = v;
+  }
+}
+
+// A list of skinny problems (gemm_skinny_ok): tile_begin[] as for 64 x 64
+// tiles (one tile per 64 columns: the problems have one row of tiles).
+hipError_t gemm_skinny_list_launch(const GProb* d_probs, const long long* d_tile_begin, int nprob, long long ntiles,
+                                   hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gemm_skinny_list_kernel, dim3((unsigned)ntiles), dim3(256), 0, stream, d_probs, d_tile_begin, nprob);
+  return hipGetLastError();
+}
+
 hipError_t gemm_list_launch(const GProb* d_probs, const long long* d_tile_begin, int nprob, long long ntiles, int big,
                             hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
@@ -1256,6 +1351,33 @@ BTA_TESTING_API int bta_internal_gemm(
   p.M = M; p.N = N; p.nb0 = 1; p.nb1 = 1;
   p.alpha = alpha; p.beta = beta; p.store = store; p.lower_tiles = lower_tiles;
   return (int)bta::gemm_launch(&p, 1, s);
+}
+
+// The same kind of product through the skinny list kernel, as two segments
+// (k in [0, K1) and [K1, K)) to exercise the segment loop: dlist is device
+// memory of at least 512 bytes for the one-problem list.  Returns -1 when the
+// product is not skinny (more than 16 rows), else the HIP status.
+BTA_TESTING_API int bta_internal_gemm_skinny(int M, int N, int K, int K1, const double* A, int64_t lda, const double* B,
+                                             int64_t ldb, const double* Cin, double* C, int64_t ldc, double alpha,
+                                             double beta, void* dlist, hipStream_t s) {
+  if (K1 < 0 || K1 > K) return -1;
+  bta::GProb p{};
+  p.seg[0].A = A; p.seg[0].B = B; p.seg[0].lda = lda; p.seg[0].ldb = ldb; p.seg[0].K = K1;
+  p.seg[1].A = A + K1; p.seg[1].B = B + (int64_t)K1 * ldb; p.seg[1].lda = lda; p.seg[1].ldb = ldb; p.seg[1].K = K - K1;
+  for (int q = 0; q < 2; ++q) { p.seg[q].at = 0; p.seg[q].bt = 1; p.seg[q].tri = bta::TRI_NONE; }
+  p.nseg = 2;
+  p.Cin = Cin; p.Cout = C; p.ldc = ldc;
+  p.M = M; p.N = N; p.nb0 = 1; p.nb1 = 1;
+  p.alpha = alpha; p.beta = beta; p.store = bta::ST_FULL; p.lower_tiles = 0;
+  if (!bta::gemm_skinny_ok(p)) return -1;
+  const long long tiles = bta::gemm_prob_tiles(p, 64);
+  const long long begin = 0;
+  char* d = static_cast<char*>(dlist);
+  hipError_t e = hipMemcpyAsync(d, &p, sizeof(p), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d + 256, &begin, sizeof(begin), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = bta::gemm_skinny_list_launch(reinterpret_cast<const bta::GProb*>(d), reinterpret_cast<const long long*>(d + 256), 1, tiles, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host copies are read before returning
+  return (int)e;
 }
 
 // The same product through the split-k path (ws: S*M*N doubles of partials;

@@ -157,3 +157,53 @@ def test_gemm_split_k_matches_reference(lib, case):
     say(f"   splits {splits.value}, max rel err {err:.2e}")
     assert splits.value >= 2
     assert err < 1e-12
+
+
+SKINNY_CASES = [
+    # M, N, K, K1, alpha, beta: the arrow-row product (a rows, K = b + a in two segments) and ragged edges
+    (6, 384, 390, 384, -1.0, 0.0),
+    (16, 200, 700, 300, 0.5, 1.5),
+    (1, 64, 5, 0, 1.0, 0.0),
+    (3, 1000, 33, 33, -1.0, 0.0),
+    (11, 130, 257, 256, -1.0, 2.0),
+]
+
+
+@pytest.mark.parametrize("case", SKINNY_CASES, ids=lambda c: "x".join(str(v) for v in c))
+def test_gemm_skinny_matches_reference(lib, case):
+    """The skinny list kernel (at most 16 rows; one workgroup per 64 columns,
+    k residues summed in a fixed order) against the product in float64 on the
+    CPU, over two k segments, with alpha, beta and ragged column edges; run
+    twice for identical bits."""
+    import torch
+
+    M, N, K, K1, alpha, beta = case
+    say(f"case gemm skinny {case}")
+    L = lib
+    L.bta_internal_gemm_skinny.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                                                ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                                                ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                                                ctypes.c_void_p, ctypes.c_void_p]
+    L.bta_internal_gemm_skinny.restype = ctypes.c_int
+    rng = np.random.default_rng(hash(case) % (2 ** 31))
+    A = rng.standard_normal((M, K))     # A(m, k), by rows
+    B = rng.standard_normal((K, N))     # B(c, k) stored as B[k, c]
+    Cin = rng.standard_normal((M, N))
+    dA, dB = torch.tensor(A, device="cuda"), torch.tensor(B, device="cuda")
+    dlist = torch.empty(512, dtype=torch.uint8, device="cuda")
+    outs = []
+    for _ in range(2):
+        dC = torch.tensor(Cin, device="cuda")
+        rc = L.bta_internal_gemm_skinny(M, N, K, K1, dA.data_ptr(), K, dB.data_ptr(), N,
+                                        dC.data_ptr() if beta != 0.0 else None, dC.data_ptr(), N, alpha, beta,
+                                        dlist.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        assert rc == 0
+        outs.append(dC.cpu().numpy())
+    ref = alpha * (A @ B) + (beta * Cin if beta != 0.0 else 0.0)
+    err = np.abs(outs[0] - ref).max() / np.abs(ref).max()
+    say(f"   max rel err {err:.2e}")
+    assert err < 1e-12
+    assert np.array_equal(outs[0].view(np.int64), outs[1].view(np.int64))
+    # more than 16 rows does not qualify
+    assert L.bta_internal_gemm_skinny(17, N, K, K1, dA.data_ptr(), K, dB.data_ptr(), N, None, dC.data_ptr(), N,
+                                      alpha, 0.0, dlist.data_ptr(), torch.cuda.current_stream().cuda_stream) == -1

@@ -9,6 +9,8 @@
   window each launch would read or write and checks it against array bounds.
 """
 import ctypes
+
+import numpy as np
 import itertools
 
 import pytest
@@ -85,6 +87,14 @@ def test_batched_selinv_merge_is_independent(L):
                                                                              (5, 40, 1), (4, 200, 0)]]):
         n, b, a = arr([w.n for w in wls]), arr([w.b for w in wls]), arr([w.a for w in wls])
         assert L.bta_internal_selinv_batch_check(len(wls), n, b, a) == 0
+    # random batches of mixed lengths (each sweep spread over the longest one's steps)
+    rng = np.random.default_rng(17)
+    for _ in range(20):
+        cnt = int(rng.integers(1, 13))
+        n = [int(v) for v in rng.integers(1, 41, cnt)]
+        b = [int(v) for v in rng.choice([5, 64, 130, 200], cnt)]
+        a = [int(v) for v in rng.choice([0, 1, 4, 70], cnt)]
+        assert L.bta_internal_selinv_batch_check(cnt, arr(n), arr(b), arr(a)) == 0, (n, b, a)
 
 
 @pytest.mark.parametrize("look", [1, 4, 12, 16, 32])
