@@ -498,9 +498,41 @@ struct DL2 {
   static_assert((PA + PB) % NTH == 0 && PA % 64 == 0, "stage pieces per thread");
 };
 
-template <int WR, int WC, int BI, int BJ, int L0>
+// Wait until at most N of this thread's vector memory loads are outstanding,
+// then meet the workgroup at a barrier; the statement's memory clobber keeps
+// the compiler from moving LDS accesses or direct-to-LDS loads across it.
+// (Unlike __syncthreads, whose release fence waits for every outstanding
+// direct-to-LDS load, this leaves the newer stages' loads in flight.)
+template <int N>
+__device__ __forceinline__ void wait_vm_barrier();
+template <>
+__device__ __forceinline__ void wait_vm_barrier<0>() { asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory"); }
+template <>
+__device__ __forceinline__ void wait_vm_barrier<4>() { asm volatile("s_waitcnt vmcnt(4)\n\ts_barrier" ::: "memory"); }
+template <>
+__device__ __forceinline__ void wait_vm_barrier<8>() { asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory"); }
+
+// LDS stages of the 64 x 64 list kernel (the batched products): 4, or 2 under
+// the measurement override BTA_LIST_STAGES=2.  (The single-problem 64 x 64
+// kernel keeps two stages: four measured no better there, where two stages
+// leave room for more workgroups per CU: n=128, b=2048 199.2 against 199.8 ms,
+// autograd 61.9 against 61.7 ms, the wide arrowhead 288.2 against 286.2 ms.)
+static int list_stages() {
+  static const int ns = [] {
+    long long v = 0;
+    return (env_int("BTA_LIST_STAGES", 2, 4, &v) && v == 2) ? 2 : 4;
+  }();
+  return ns;
+}
+
+// NS: LDS stages of the k loop.  2: the next stage's loads overlap this
+// stage's products.  NS > 2: NS - 1 stages in flight, each iteration waiting
+// only for its own stage's loads (vector memory loads complete in order) --
+// for tiles whose per-stage products are too short to cover a load's latency.
+template <int WR, int WC, int BI, int BJ, int L0, int NS = 2>
 __device__ __forceinline__ void gemm_tile_dl2(const GProb& P, long long local, int tid, double* lds) {
   using C = DL2<WR, WC, BI, BJ>;
+  static_assert(NS == 2 || (NS == 4 && C::PER_T == 4), "the deep pipeline's wait counts assume 4 pieces per thread");
   constexpr int TM = C::TM, TN = C::TN, BK = C::BK, PER = C::PER_T;
   const int batch = (int)(local / P.tiles_per_batch);
   const int tile = (int)(local - (long long)batch * P.tiles_per_batch);
@@ -573,7 +605,7 @@ __device__ __forceinline__ void gemm_tile_dl2(const GProb& P, long long local, i
   auto issue = [&](int kk) {
     if (kk == 0) { setup(0); stage_in_seg = 0; }
     if (kk == nk0) { setup(1); stage_in_seg = 0; }
-    double* st = lds + (kk & 1) * C::STAGE;
+    double* st = lds + (kk % NS) * C::STAGE;
     const int krel = stage_in_seg * BK;
     const bool full = krel + BK <= seg_klen;
 #pragma unroll
@@ -604,6 +636,8 @@ __device__ __forceinline__ void gemm_tile_dl2(const GProb& P, long long local, i
 #pragma unroll
     for (int jj = 0; jj < BJ; ++jj) all_live = all_live && live[i][jj];
   if (total > 0) issue(0);
+  if (NS > 2)
+    for (int q = 1; q < NS - 1 && q < total; ++q) issue(q);
   // the segments' layouts, read once into scalar registers (a reload inside
   // the k loop costs a scalar load and a full wait per stage)
   const int at0 = __builtin_amdgcn_readfirstlane(P.seg[0].at), bt0 = __builtin_amdgcn_readfirstlane(P.seg[0].bt);
@@ -614,12 +648,18 @@ __device__ __forceinline__ void gemm_tile_dl2(const GProb& P, long long local, i
     constexpr bool CK = decltype(checked)::value;
     constexpr int LC = decltype(lc)::value;
     for (int kk = k0; kk < k1; ++kk) {
-      __syncthreads();
+      if constexpr (NS == 2) {
+        __syncthreads();
+      } else {  // stages kk + 1 .. kk + NS - 2 may stay in flight
+        if (kk + 2 < total) wait_vm_barrier<2 * C::PER_T>();
+        else if (kk + 1 < total) wait_vm_barrier<C::PER_T>();
+        else wait_vm_barrier<0>();
+      }
       const bool first = kk < nk0;
-      const double* st = lds + (kk & 1) * C::STAGE;
+      const double* st = lds + (kk % NS) * C::STAGE;
       // the next stage's loads first (its buffer was last read before the
       // barrier), then this stage's operands
-      if (kk + 1 < total) issue(kk + 1);
+      if (kk + NS - 1 < total) issue(kk + NS - 1);
       double a[BI][4], b[BJ][4];
       stage_read<TM, BI>(a, st, LC < 4 ? (LC >> 1) : (first ? at0 : at1), rw, lane);
       stage_read<TN, BJ>(b, st + C::SA, LC < 4 ? (LC & 1) : (first ? bt0 : bt1), cw, lane);
@@ -770,14 +810,17 @@ __device__ __forceinline__ int find_prob_list(const long long* tile_begin, int n
 }
 
 // 64 x 64 tiles: the lean direct-to-LDS body where the problem allows it
-// (a workgroup-uniform test), the register-staged body otherwise.
-constexpr int LIST64_LDS = 2 * 64 * 66 > 2 * DL2<2, 2, 2, 2>::STAGE ? 2 * 64 * 66 : 2 * DL2<2, 2, 2, 2>::STAGE;
+// (a workgroup-uniform test), with four LDS stages (three in flight: the
+// batched products have short k loops whose loads a single stage of products
+// cannot cover), the register-staged body otherwise.
+constexpr int LIST64_LDS = 2 * 64 * 66 > 4 * DL2<2, 2, 2, 2>::STAGE ? 2 * 64 * 66 : 4 * DL2<2, 2, 2, 2>::STAGE;
+template <int NS>
 __global__ __launch_bounds__(NT, 2) void gemm_list_kernel(const GProb* probs, const long long* tile_begin, int nprob) {
   __shared__ __align__(16) double lds[LIST64_LDS];
   const int j = find_prob_list(tile_begin, nprob, blockIdx.x);
   const GProb& P = probs[j];  // read in place: a private copy would live in scratch
   const long long local = blockIdx.x - tile_begin[j];
-  if (dl_ok(P)) gemm_tile_dl2<2, 2, 2, 2, 4>(P, local, threadIdx.x, lds);
+  if (dl_ok(P)) gemm_tile_dl2<2, 2, 2, 2, 4, NS>(P, local, threadIdx.x, lds);
   else gemm_tile_body<2, 2, 64>(P, local, threadIdx.x, lds, lds + 64 * 66);
 }
 
@@ -892,8 +935,10 @@ hipError_t gemm_list_launch(const GProb* d_probs, const long long* d_tile_begin,
   if (ntiles <= 0) return hipSuccess;
   if (big)
     hipLaunchKernelGGL(gemm128_list_kernel, dim3((unsigned)ntiles), dim3(NT), 0, stream, d_probs, d_tile_begin, nprob);
+  else if (list_stages() == 2)
+    hipLaunchKernelGGL(gemm_list_kernel<2>, dim3((unsigned)ntiles), dim3(NT), 0, stream, d_probs, d_tile_begin, nprob);
   else
-    hipLaunchKernelGGL(gemm_list_kernel, dim3((unsigned)ntiles), dim3(NT), 0, stream, d_probs, d_tile_begin, nprob);
+    hipLaunchKernelGGL(gemm_list_kernel<4>, dim3((unsigned)ntiles), dim3(NT), 0, stream, d_probs, d_tile_begin, nprob);
   return hipGetLastError();
 }
 
