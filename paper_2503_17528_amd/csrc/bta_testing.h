@@ -104,6 +104,15 @@ BTA_TESTING_API int bta_internal_gemm_mode(int mode);
 BTA_TESTING_API int bta_internal_gemm(int M, int N, int K, const double* A, int64_t lda, int at, const double* B,
                                       int64_t ldb, int bt, int tri, const double* Cin, double* C, int64_t ldc,
                                       double alpha, double beta, int store, int lower_tiles, hipStream_t s);
+/* nprob copies of one product (problem q offset by q*stride in A, B and C)
+ * through the batched list kernel: 64 x 64 tiles with four LDS stages, or
+ * 128 x 128 tiles with big; dlist is device memory of at least
+ * 512 * (nprob + 1) bytes; synchronizes `s`.  -1 on a bad nprob (1..64). */
+BTA_TESTING_API int bta_internal_gemm_list(int M, int N, int K, const double* A, int64_t lda, int at, const double* B,
+                                           int64_t ldb, int bt, int tri, const double* Cin, double* C, int64_t ldc,
+                                           double alpha, double beta, int store, int lower_tiles, int nprob,
+                                           int64_t strideA, int64_t strideB, int64_t strideC, int big, void* dlist,
+                                           hipStream_t s);
 /* A product of at most 16 rows through the skinny list kernel, as two k
  * segments [0, K1) and [K1, K) (A by rows, B by k rows, full store); dlist is
  * device memory of at least 512 bytes; synchronizes `s`.  -1 when the product

@@ -9,6 +9,8 @@
 #include <cmath>
 #include <type_traits>
 
+#include <vector>
+
 #include "bta_device.hpp"
 #include "bta_internal.hpp"
 #include "bta_testing.h"
@@ -1421,6 +1423,42 @@ BTA_TESTING_API int bta_internal_gemm_skinny(int M, int N, int K, int K1, const 
   hipError_t e = hipMemcpyAsync(d, &p, sizeof(p), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d + 256, &begin, sizeof(begin), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = bta::gemm_skinny_list_launch(reinterpret_cast<const bta::GProb*>(d), reinterpret_cast<const long long*>(d + 256), 1, tiles, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host copies are read before returning
+  return (int)e;
+}
+
+// A list of `nprob` copies of one product (problem q reads A + q*strideA,
+// B + q*strideB and writes C + q*strideC) through the 64 x 64 list kernel
+// (four LDS stages) or, with big, the 128 x 128 one; dlist is device memory of
+// at least 512 * (nprob + 1) bytes.  Returns the HIP status (synchronizes `s`).
+BTA_TESTING_API int bta_internal_gemm_list(int M, int N, int K, const double* A, int64_t lda, int at, const double* B,
+                                           int64_t ldb, int bt, int tri, const double* Cin, double* C, int64_t ldc,
+                                           double alpha, double beta, int store, int lower_tiles, int nprob,
+                                           int64_t strideA, int64_t strideB, int64_t strideC, int big, void* dlist,
+                                           hipStream_t s) {
+  if (nprob < 1 || nprob > 64) return -1;
+  std::vector<bta::GProb> ps(nprob);
+  std::vector<long long> begin(nprob);
+  long long tiles = 0;
+  for (int q = 0; q < nprob; ++q) {
+    bta::GProb& p = ps[q];
+    p = bta::GProb{};
+    p.seg[0].A = A + q * strideA; p.seg[0].B = B + q * strideB; p.seg[0].lda = lda; p.seg[0].ldb = ldb; p.seg[0].K = K;
+    p.seg[0].at = at; p.seg[0].bt = bt; p.seg[0].tri = tri;
+    p.nseg = 1;
+    p.Cin = Cin ? Cin + q * strideC : nullptr; p.Cout = C + q * strideC; p.ldc = ldc;
+    p.M = M; p.N = N; p.nb0 = 1; p.nb1 = 1;
+    p.alpha = alpha; p.beta = beta; p.store = store; p.lower_tiles = lower_tiles;
+    begin[q] = tiles;
+    tiles += bta::gemm_prob_tiles(p, big ? 128 : 64);
+  }
+  char* d = static_cast<char*>(dlist);
+  const size_t off = ((sizeof(bta::GProb) * nprob + 255) / 256) * 256;
+  hipError_t e = hipMemcpyAsync(d, ps.data(), sizeof(bta::GProb) * nprob, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d + off, begin.data(), sizeof(long long) * nprob, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = bta::gemm_list_launch(reinterpret_cast<const bta::GProb*>(d), reinterpret_cast<const long long*>(d + off), nprob,
+                              tiles, big, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host copies are read before returning
   return (int)e;
 }

@@ -207,3 +207,67 @@ def test_gemm_skinny_matches_reference(lib, case):
     # more than 16 rows does not qualify
     assert L.bta_internal_gemm_skinny(17, N, K, K1, dA.data_ptr(), K, dB.data_ptr(), N, None, dC.data_ptr(), N,
                                       alpha, 0.0, dlist.data_ptr(), torch.cuda.current_stream().cuda_stream) == -1
+
+
+LIST_CASES = [
+    # M, N, K, at, bt, tri, store, lower_tiles, nprob: k loops of 1, 2, 3 and many stages (the deep
+    # pipeline's tail waits), an odd K (the register-staged body), transposes, triangular k ranges,
+    # lower stores and several problems per launch
+    (64, 64, 16, 0, 1, TRI_NONE, ST_FULL, 0, 3),
+    (70, 130, 32, 0, 1, TRI_NONE, ST_FULL, 0, 2),
+    (128, 96, 48, 1, 0, TRI_NONE, ST_FULL, 0, 2),
+    (384, 384, 390, 0, 1, TRI_NONE, ST_FULL, 0, 4),
+    (256, 256, 256, 1, 1, TRI_K_GE_ROW, ST_LOWER_MIRROR, 1, 2),
+    (192, 192, 192, 0, 1, TRI_K_GE_COL, ST_FULL, 0, 3),
+    (200, 200, 5, 0, 1, TRI_NONE, ST_FULL, 0, 2),
+]
+
+
+@pytest.mark.parametrize("big", [0, 1])
+@pytest.mark.parametrize("case", LIST_CASES, ids=lambda c: "x".join(str(v) for v in c))
+def test_gemm_list_kernels_match_reference(lib, case, big):
+    """The batched list kernels (64 x 64 tiles with four LDS stages, 128 x 128
+    tiles) over several problems in one launch, against float64 products on
+    the CPU."""
+    import torch
+
+    M, N, K, at, bt, tri, store, lower_tiles, nprob = case
+    say(f"case gemm list big={big} {case}")
+    L = lib
+    L.bta_internal_gemm_list.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                                              ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                              ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                                              ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                              ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    L.bta_internal_gemm_list.restype = ctypes.c_int
+    rng = np.random.default_rng(hash(case) % (2 ** 31))
+    ops = [_operands(rng, M, N, K, at, bt, tri) for _ in range(nprob)]
+    A = np.stack([o[0] for o in ops])
+    B = np.stack([o[1] for o in ops])
+    S = max(M, N)
+    Cin = rng.standard_normal((nprob, M, N)) if store == ST_FULL else rng.standard_normal((nprob, S, S))[:, :M, :N].copy()
+    alpha, beta = -1.0, (1.0 if store != ST_LOWER_MIRROR else 0.0)
+    dA, dB = torch.tensor(A, device="cuda"), torch.tensor(B, device="cuda")
+    dC = torch.tensor(Cin, device="cuda")
+    dlist = torch.empty(512 * (nprob + 1), dtype=torch.uint8, device="cuda")
+    rc = L.bta_internal_gemm_list(M, N, K, dA.data_ptr(), A.shape[2], at, dB.data_ptr(), B.shape[2], bt, tri,
+                                  dC.data_ptr() if beta != 0.0 else None, dC.data_ptr(), N, alpha, beta, store,
+                                  lower_tiles, nprob, A[0].size, B[0].size, M * N, big, dlist.data_ptr(),
+                                  torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    got = dC.cpu().numpy()
+    worst = 0.0
+    for q in range(nprob):
+        ref = alpha * ops[q][2] + (beta * Cin[q] if beta != 0.0 else 0.0)
+        if store == ST_FULL:
+            err = np.abs(got[q] - ref).max() / np.abs(ref).max()
+        else:
+            il = np.tril_indices(min(M, N))
+            err = np.abs(got[q][il] - ref[il]).max() / np.abs(ref[il]).max()
+            if store == ST_LOWER_MIRROR:
+                assert np.array_equal(got[q][:N, :N], got[q][:N, :N].T)
+        worst = max(worst, err)
+    say(f"   max rel err {worst:.2e}")
+    assert worst < 1e-12
