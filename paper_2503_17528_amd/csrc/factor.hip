@@ -44,6 +44,11 @@ namespace bta {
 
 enum : int { T_DIAG = 0, T_OFFD = 1, T_SUB = 2, T_ARW = 3, T_TUPD = 4, T_TIPD = 5, T_TIPO = 6 };
 
+// Control words of a launch (ints at p.ctl): the ticket counter at 0, the
+// abort flag raised by a wait that timed out on a line of its own (128 bytes
+// further), which every polling workgroup reads.
+constexpr int CTL_ABORT = 32;
+
 struct FactorParams {
   int n, b, a;
   int T;   // tiles per block edge: ceil(b/64)
@@ -301,8 +306,8 @@ __device__ __forceinline__ void load_k(const FactorParams& p, double* dst, const
 // Block until flags are set (thread 0 polls); returns false on abort.
 __device__ __forceinline__ bool wait_ready(const FactorParams& p, const int* f1, const int* f2, Shared& sh, int tid) {
   if (tid == 0) {
-    bool ok = spin_wait(f1, p.ctl + 2, p.spin_limit);
-    if (ok && f2 != f1) ok = spin_wait(f2, p.ctl + 2, p.spin_limit);
+    bool ok = spin_wait(f1, p.ctl + CTL_ABORT, p.spin_limit);
+    if (ok && f2 != f1) ok = spin_wait(f2, p.ctl + CTL_ABORT, p.spin_limit);
     acquire_fence();
     sh.ok = ok ? 1 : 0;
   }
@@ -870,13 +875,14 @@ __global__ void factor_batched_reset_kernel(int* flags, long long nflags, int* c
   const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   for (long long i = i0; i < nflags; i += (long long)gridDim.x * blockDim.x) flags[i] = 0;
   if (i0 < 4) ctl[i0] = 0;
+  if (i0 == 0) ctl[CTL_ABORT] = 0;
   for (long long m = i0; m < count; m += (long long)gridDim.x * blockDim.x) *mats[m].info = 0x7fffffffffffffffLL;
 }
 
 __global__ void factor_batched_finish_kernel(const int* ctl, const FactorParams* mats, int count) {
   for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < count; m += gridDim.x * blockDim.x) {
     int64_t* info = mats[m].info;
-    if (ctl[2] != 0) *info = -1;
+    if (ctl[CTL_ABORT] != 0) *info = -1;
     else if (*info == 0x7fffffffffffffffLL) *info = 0;
   }
 }
@@ -886,6 +892,7 @@ __global__ void factor_reset_kernel(int* flags, long long nflags, int* ctl, int6
   const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   for (long long i = i0; i < nflags; i += (long long)gridDim.x * blockDim.x) flags[i] = 0;
   if (i0 < 4) ctl[i0] = 0;
+  if (i0 == 0) ctl[CTL_ABORT] = 0;
   if (i0 == 0) *info = 0x7fffffffffffffffLL;
 }
 
@@ -893,7 +900,7 @@ __global__ void factor_reset_kernel(int* flags, long long nflags, int* ctl, int6
 // aborted run (watchdog) to -1.
 __global__ void factor_finish_kernel(const int* ctl, int64_t* info) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (ctl[2] != 0) *info = -1;
+    if (ctl[CTL_ABORT] != 0) *info = -1;
     else if (*info == 0x7fffffffffffffffLL) *info = 0;
   }
 }
@@ -985,7 +992,7 @@ FactorPlan factor_plan(int64_t n, int64_t b, int64_t a) {
   fp.sub_delay = (int)std::min<int64_t>(factor_sub_delay(b, a), T);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
-  fp.off_ctl = take(64);
+  fp.off_ctl = take(256);  // ticket counter, abort flag at CTL_ABORT
   fp.off_flags = take(sizeof(int) * (size_t)fp.nflags);
   fp.off_Wd = take(sizeof(double) * 4096 * (size_t)(n * T));
   fp.off_Wt = take(sizeof(double) * 4096 * (size_t)(TA > 0 ? TA : 1));
@@ -1141,7 +1148,7 @@ FactorBatchPlan factor_batch_plan(int count, const int64_t* n, const int64_t* b,
   bp.plans.resize(count);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
-  bp.off_ctl = take(64);
+  bp.off_ctl = take(256);  // ticket counter, abort flag at CTL_ABORT
   bp.off_mats = take(sizeof(FactorParams) * (size_t)count);
   long long nflags = 0;
   bp.flag_off.resize(count);
