@@ -776,12 +776,30 @@ __global__ __launch_bounds__(512, 3) void gemm_l128x64_kernel(GemmArgs args) {
   gemm_tile_dl2<4, 2, 2, 2, L0>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
 }
 
+// 128 x 128 tiles: four LDS stages, three in flight (one workgroup per CU:
+// the deeper pipeline covers the loads that a second workgroup covered with
+// two stages; n=128, b=2048 selected inversion 118.7 -> 118.2 ms, n=256,
+// b=4096 1600.6 -> 1590.5 ms); two stages under BTA_L128_STAGES=2.
 template <int L0>
-__global__ __launch_bounds__(512, 2) void gemm_l128_kernel(GemmArgs args) {
+__global__ __launch_bounds__(512, 1) void gemm_l128_kernel(GemmArgs args) {
+  __shared__ __align__(16) double lds[4 * DL2<4, 2, 2, 4>::STAGE];
+  const long long t = xcd_tile(blockIdx.x, gridDim.x);
+  const int j = find_prob(args, t);
+  gemm_tile_dl2<4, 2, 2, 4, L0, 4>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
+}
+template <int L0>
+__global__ __launch_bounds__(512, 2) void gemm_l128s2_kernel(GemmArgs args) {
   __shared__ __align__(16) double lds[2 * DL2<4, 2, 2, 4>::STAGE];
   const long long t = xcd_tile(blockIdx.x, gridDim.x);
   const int j = find_prob(args, t);
   gemm_tile_dl2<4, 2, 2, 4, L0>(args.p[j], t - args.p[j].tile_begin, threadIdx.x, lds);
+}
+static int l128_stages() {
+  static const int ns = [] {
+    long long v = 0;
+    return (env_int("BTA_L128_STAGES", 2, 4, &v) && v == 2) ? 2 : 4;
+  }();
+  return ns;
 }
 
 // Whether the direct-to-LDS bodies can take a problem: 16-byte aligned
@@ -1108,7 +1126,10 @@ hipError_t gemm_launch(GProb* probs, int nprob, hipStream_t stream) {
       case 3: BTA_LAUNCH_L0(gemm_dl64_kernel, t64, NT, small); break;
       case 4: BTA_LAUNCH_L0(gemm_dl128_kernel, t128, NT, big); break;
       case 5: BTA_LAUNCH_L0(gemm_l64_kernel, t64, 256, small); break;
-      case 7: BTA_LAUNCH_L0(gemm_l128_kernel, t128, 512, big); break;
+      case 7:
+        if (l128_stages() == 2) BTA_LAUNCH_L0(gemm_l128s2_kernel, t128, 512, big)
+        else BTA_LAUNCH_L0(gemm_l128_kernel, t128, 512, big)
+        break;
       default: BTA_LAUNCH_L0(gemm_l128x64_kernel, t12864, 512, mid); break;
     }
 #undef BTA_LAUNCH_L0
